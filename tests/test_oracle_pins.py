@@ -1,0 +1,297 @@
+"""Pins of the oracle against closed forms and invariants the model fixes (CPU, no GPU).
+
+V1  flat interface relaxes to the tanh profile of width W (text after Eq. 8)
+V2  Laplace law dp = gamma/R in 2D (Eqs. 10-11 with F_s = mu grad Phi)
+V4  Young angle on a flat wall (Eq. 20 wetting condition)
+V5  Poiseuille flow between walls (flow scheme + halfway bounce-back)
+V6  capacitor: linear potential, and the series-resistance layered solution (Eq. 13)
+V7  electrode strip: far-field decay rate alpha0 = pi/(2L) of Eq. 4
+V8  charge relaxation at rate sigma/eps in a uniform medium (Eq. 14)
+V9  Maxwell-stress jump across a flat dielectric interface, and the Coulomb force (Eq. 12)
+V10 per-component mass conservation and the charge balance
+V11 the potential solve's adjoint against finite differences
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from inputs import make_case
+from inputs.presets import ELECTRODE0, FLUID, GROUND, NEUMANN
+from oracle import Oracle
+
+import pin_cases as pc
+
+F64 = torch.float64
+
+
+def _run(case, steps, rho0=None, every=None, cb=None):
+    n, per, p, fl, phi = case
+    dim = 3 if n[2] > 1 else 2
+    o = Oracle(dim, n, per, p, fl)
+    s = o.init_state(phi, rho0)
+    aux = None
+    for k in range(1, steps + 1):
+        s, aux = o.step(s)
+        if cb is not None and every and k % every == 0:
+            cb(k, o, s, aux)
+    return o, s, aux
+
+
+# ---------------------------------------------------------------- V1
+def test_v1_flat_interface_tanh_profile():
+    """A sharp slab relaxes towards the tanh profile, and a tanh start settles on the scheme's
+    discrete equilibrium: sum Phi(1 - Phi) = W/4 per interface, profile within 1e-2 of tanh."""
+    W = 4.0
+    n, per, p, fl, phi = pc.flat_interface(nx=64, ny=4, lo=16, hi=48, width=W, mobility=0.1)
+    x = np.arange(64)
+    prof = 0.5 * (np.tanh(2 * (x - 15.5) / W) - np.tanh(2 * (x - 47.5) / W))
+    o, s, _ = _run((n, per, p, fl, phi), 1500)
+    p1 = o.fields(s)["phi"][0].reshape(4, 64)[0].numpy()
+    assert abs(np.sum(p1 * (1 - p1)) - 2 * W / 4) < 1e-5 * W
+    assert np.abs(p1 - prof).max() < 1e-2
+    assert float(o.fields(s)["phi"][1].abs().max()) == 0.0        # absent lubricant stays absent
+    xx, yy, zz = pc.grid(n)
+    pt = 0.5 * (np.tanh(2 * (xx - 15.5) / W) - np.tanh(2 * (xx - 47.5) / W))
+    o, s, aux = _run((n, per, p, fl, np.stack([pt, 0 * pt, 1 - pt])), 1500)
+    p1 = o.fields(s)["phi"][0].reshape(4, 64)[0].numpy()
+    assert abs(np.sum(p1 * (1 - p1)) - 2 * W / 4) < 1e-6 * W
+    assert np.abs(p1 - prof).max() < 1e-2
+    assert float(aux["u"].abs().max()) < 1e-6
+
+
+# ---------------------------------------------------------------- V2
+def _laplace_dp(radius, steps=1600, avg_from=600):
+    n = (64, 64, 1)
+    case = pc.periodic_droplet(n=n, radius=radius, mobility=0.02)
+    x = np.arange(64) - 32 + 0.5
+    X, Y = np.meshgrid(x, x)
+    r = np.sqrt(X ** 2 + Y ** 2).ravel()
+    inner = torch.from_numpy(r < radius - 6)
+    outer = torch.from_numpy(r > radius + 6)
+    acc = []
+
+    def cb(k, o, s, aux):
+        if k >= avg_from:
+            pr = o.fields(s)["p"]
+            acc.append(float(pr[inner].mean() - pr[outer].mean()))
+    _run(case, steps, every=10, cb=cb)
+    return float(np.mean(acc))
+
+
+def test_v2_laplace_law():
+    gamma = 1e-3
+    dp12 = _laplace_dp(12.0)
+    dp16 = _laplace_dp(16.0)
+    # 1/R scaling (the diffuse-interface correction is common to both radii)
+    assert abs((dp12 / dp16) / (16.0 / 12.0) - 1) < 0.03
+    # magnitude gamma/R; a 4-lu interface carries a few-percent discretisation deficit
+    for R, dp in ((12.0, dp12), (16.0, dp16)):
+        assert abs(dp * R / gamma - 1) < 0.10
+
+
+# ---------------------------------------------------------------- V4
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_v4_young_angle(theta):
+    # a cap at the Young angle stays there ...
+    case = pc.wall_droplet(nx=64, ny=32, radius=12.0, theta0_deg=theta, theta13_deg=theta, mobility=0.1)
+    o, s, _ = _run(case, 1000)
+    ang, _ = pc.contact_angle(o.fields(s)["phi"][0].reshape(32, 64).numpy())
+    assert abs(ang - theta) < 1.5
+    # ... and a half disc (90 deg) moves towards it
+    case = pc.wall_droplet(nx=64, ny=32, radius=12.0, theta0_deg=90.0, theta13_deg=theta, mobility=0.1)
+    o, s, _ = _run(case, 1000)
+    ang90, _ = pc.contact_angle(o.fields(s)["phi"][0].reshape(32, 64).numpy())
+    assert (ang90 - 90.0) * (theta - 90.0) > 0 and abs(ang90 - 90.0) > 0.5
+
+
+# ---------------------------------------------------------------- V5
+def test_v5_poiseuille():
+    F = 1e-6
+    ny = 18
+    case = pc.channel(nx=4, ny=ny, body_force=(F, 0.0, 0.0))
+    o, s, aux = _run(case, 4000)
+    u = aux["u"][0].reshape(ny, 4)[1:-1, 0].numpy()
+    y = np.arange(1, ny - 1, dtype=np.float64)
+    c = np.polyfit(y, u, 2)
+    nu = (1.0 - 0.5) / 3.0
+    assert abs(2 * c[0] / (-F / nu) - 1) < 1e-9
+    roots = np.sort(np.roots(c).real)
+    assert abs(roots[0] - 0.5) < 0.01 and abs(roots[1] - (ny - 1.5)) < 0.01
+    assert np.abs(np.polyval(c, y) - u).max() < 1e-10 * u.max()
+    assert float(aux["u"][1].abs().max()) < 1e-18
+
+
+# ---------------------------------------------------------------- V6
+def test_v6_capacitor_uniform_and_layered():
+    V = 0.05
+    ny = 34
+    case = pc.capacitor(ny=ny, ehd=1, electrode_volts=(V, 0, 0, 0), cond=(0.0, 0.0, 0.0))
+    o, s, aux = _run(case, 1)
+    pot = aux["pot"].reshape(ny, 4)[:, 0].numpy()
+    y = np.arange(1, ny - 1)
+    assert np.abs(pot[1:-1] - V * (y - 0.5) / (ny - 2)).max() < 1e-15
+    # layered: eps = 80 below row 17, 1 above; potential = V * (resistance below node)/(total)
+    case = pc.capacitor(ny=ny, layer=17, ehd=1, electrode_volts=(V, 0, 0, 0), cond=(0.0, 0.0, 0.0))
+    o, s, aux = _run(case, 1)
+    pot = aux["pot"].reshape(ny, 4)[:, 0].numpy()
+    eps = np.where(np.arange(ny) < 17, 80.0, 1.0)
+    res = [1.0 / (2 * eps[1])]
+    for j in range(1, ny - 2):
+        res.append(1.0 / (0.5 * (eps[j] + eps[j + 1])))
+    res.append(1.0 / (2 * eps[ny - 2]))
+    cum = np.cumsum(res)
+    expect = V * cum[:-1] / cum[-1]
+    assert np.abs(pot[1:-1] - expect).max() < 1e-15
+
+
+# ---------------------------------------------------------------- V7
+def test_v7_strip_decay_rate():
+    ny = 42
+    L = ny - 2
+    case = pc.strip(nx=262, ny=ny, e_lo=21, ehd=1, electrode_volts=(0.05, 0, 0, 0), cond=(0, 0, 0))
+    o, s, aux = _run(case, 1)
+    pot = aux["pot"].reshape(ny, 262).numpy()
+    row = pot[ny // 2]
+    xs = np.arange(20, 60)
+    cosh_a = (row[xs + 1] + row[xs - 1]) / (2 * row[xs])
+    alpha = np.arccosh(cosh_a.mean())
+    alpha0 = math.pi / (2 * L)                       # Eq. 4, continuous strip
+    alpha_d = math.acosh(2 - math.cos(math.pi / (2 * L)))  # same mode on the 5-point lattice
+    assert abs(alpha / alpha0 - 1) < 0.01
+    assert abs(alpha / alpha_d - 1) < 1e-6
+    assert np.ptp(cosh_a) < 1e-6
+
+
+# ---------------------------------------------------------------- V8
+def test_v8_charge_relaxation():
+    """Uniform eps and sigma: the Ohmic source is exactly -(sigma/eps) rho_e, so a uniform
+    charge follows q(t+1) = q(t) - k q(t) - k (q(t) - q(t-1))/2 at every node (the first
+    step has no time derivative), whose decay factor is exp(-k) + O(k^3) per step."""
+    nx, ny = 8, 10
+    kappa = 0.01
+    case = pc.capacitor(nx=nx, ny=ny, top=GROUND, ehd=1, cond=(0.0, 0.0, kappa), eps=(80.0, 2.5, 1.0),
+                        charge_diffusion=1e-3, electrode_volts=(0, 0, 0, 0))
+    n, per, p, fl, phi = case
+    rho0 = np.where(fl == FLUID, 1e-6, 0.0)
+    steps = 200
+    o, s, aux = _run(case, steps, rho0=rho0)
+    q = [1.0, 1.0 - kappa]
+    for t in range(1, steps):
+        q.append(q[t] - kappa * q[t] - 0.5 * kappa * (q[t] - q[t - 1]))
+    rho = o.fields(s)["rho_e"].numpy()
+    m = fl == FLUID
+    assert np.abs(rho[m] / rho0[m] / q[steps] - 1).max() < 1e-9
+    assert abs(q[steps] / math.exp(-kappa * steps) - 1) < 3 * steps * kappa ** 3
+
+
+# ---------------------------------------------------------------- V9
+def test_v9_maxwell_stress_jump():
+    """sigma = 0, flat dielectric interface normal to E: D = eps E is uniform and the
+    integrated force -|E|^2 grad(eps)/2 equals D^2 (1/eps_top - 1/eps_bottom)/2.  The
+    discrete force converges to it at second order in the interface width."""
+    ny, V = 130, 0.05
+    n = (4, ny, 1)
+    x, y, z = pc.grid(n)
+    errs = []
+    for W in (8.0, 16.0):
+        case = pc.capacitor(nx=4, ny=ny, ehd=1, electrode_volts=(V, 0, 0, 0), cond=(0, 0, 0), width=W)
+        _, per, p, fl, _ = case
+        p1 = 0.5 * (1 - np.tanh(2 * (y - 64.5) / W))
+        phi = np.stack([p1, np.zeros_like(p1), 1 - p1])
+        phi[:, fl != FLUID] = 0
+        o, s, aux = _run((n, per, p, fl, phi), 1)
+        Fe = aux["Fe"][1].reshape(ny, 4)[:, 0].numpy()
+        E = aux["E"][1].reshape(ny, 4)[:, 0].numpy()
+        eps = aux["eps"].reshape(ny, 4)[:, 0].numpy()
+        D = eps[2] * E[2]
+        assert abs(eps[ny - 3] * E[ny - 3] / D - 1) < 1e-5           # D uniform in the bulk (Gauss law)
+        jump = 0.5 * D * D * (1 / 1.0 - 1 / 80.0)
+        errs.append(Fe.sum() / jump - 1)
+    assert abs(errs[0]) < 0.02 and abs(errs[1]) < 0.005
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_v9_coulomb_force_total():
+    """Uniform charge rho0 between a grounded plate and an electrode at V: with the face
+    mirrors of the potential, the central-difference field sums to -V over a column, so
+    the Coulomb force rho0 E sums to -rho0 V per column exactly."""
+    ny, V, rho0 = 20, 0.03, 2e-4
+    case = pc.capacitor(nx=4, ny=ny, ehd=1, electrode_volts=(V, 0, 0, 0), cond=(0, 0, 0))
+    n, per, p, fl, phi = case
+    r0 = np.where(fl == FLUID, rho0, 0.0)
+    o, s, aux = _run(case, 1, rho0=r0)
+    Fy = aux["Fe"][1].reshape(ny, 4)[:, 0].numpy()
+    assert abs(Fy.sum() - (-rho0 * V)) < 1e-18
+
+
+# ---------------------------------------------------------------- V10
+def test_v10_mass_and_charge_balance():
+    c = make_case("c2s")
+    o = Oracle(c.dim, c.n, c.periodic, c.params, c.flags)
+    s = o.init_state(c.phi)
+    m0 = o.observables(s)["mass"]
+    q_prev_sum = None
+    for k in range(60):
+        rho_before = float(o.fields(s)["rho_e"].sum())
+        s_new, aux = o.step(s)
+        rho_after = float(o.fields(s_new)["rho_e"].sum())
+        Q = aux["Q"]
+        dt_on = 0.0 if k == 0 else 1.0
+        expect = float(Q.sum() + 0.5 * dt_on * (Q.sum() - s.q_prev.sum()))
+        assert abs((rho_after - rho_before) - expect) < 1e-15 + 1e-12 * abs(expect)
+        # the fluid-fluid faces cancel: the net source is the current through Dirichlet faces
+        geom = o.geom
+        cur = 0.0
+        sig = aux["sigma"]
+        pot = aux["pot"]
+        for a in range(2):
+            for q in o.lat.axis_dirs[a]:
+                y = geom.nbr[q]
+                fy = geom.flags[y]
+                phid = torch.where(fy >= ELECTRODE0, torch.tensor(c.params["electrode_volts"][0], dtype=F64),
+                                   torch.zeros((), dtype=F64))
+                dirich = geom.fluid & ((fy == GROUND) | (fy >= ELECTRODE0))
+                cur += float((2 * sig * (phid - pot))[dirich].sum())
+        assert abs(float(Q.sum()) - cur) < 1e-14 * max(1.0, abs(cur))
+        s = s_new
+    m1 = o.observables(s)["mass"]
+    assert torch.all(((m1 - m0) / m0).abs() < 1e-13)
+
+
+def test_initial_charge_is_zero():
+    c = make_case("c2s")
+    o = Oracle(c.dim, c.n, c.periodic, c.params, c.flags)
+    s = o.init_state(c.phi)
+    assert float(o.fields(s)["rho_e"].abs().max()) == 0.0
+
+
+# ---------------------------------------------------------------- V11
+def test_v11_potential_adjoint_gradcheck():
+    case = pc.capacitor(nx=5, ny=7, layer=3, ehd=1, electrode_volts=(0.05, 0, 0, 0))
+    n, per, p, fl, phi = case
+    o = Oracle(2, n, per, p, fl)
+    g = torch.Generator().manual_seed(0)
+    eps = (1.0 + torch.rand(o.N, generator=g, dtype=F64)) * o.fl
+    rho = 1e-3 * torch.randn(o.N, generator=g, dtype=F64) * o.fl
+    volts = torch.tensor([0.05, 0.0, 0.0, 0.0], dtype=F64)
+    w = torch.randn(o.N, generator=g, dtype=F64)
+
+    def f(e, r, v):
+        return (o.pot.solve(e, r, v) * w).sum()
+    e = eps.clone().requires_grad_(True)
+    r = rho.clone().requires_grad_(True)
+    v = volts.clone().requires_grad_(True)
+    f(e, r, v).backward()
+    h = 1e-6
+    for tens, grad in ((eps, e.grad), (rho, r.grad), (volts, v.grad)):
+        for idx in [i for i in range(tens.numel()) if (tens is volts and i == 0) or (tens is not volts and o.fl[i] > 0)][:6]:
+            tp = tens.clone()
+            tm = tens.clone()
+            tp[idx] += h
+            tm[idx] -= h
+            args_p = [tp if tens is a else a for a in (eps, rho, volts)]
+            args_m = [tm if tens is a else a for a in (eps, rho, volts)]
+            fd = (float(f(*args_p)) - float(f(*args_m))) / (2 * h)
+            assert abs(fd - float(grad[idx])) < 1e-7 * max(1.0, abs(fd))
