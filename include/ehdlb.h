@@ -1,0 +1,192 @@
+/*
+ * ehdlb.h — C ABI of the ternary electrohydrodynamic lattice-Boltzmann library (gfx950).
+ *
+ * One library call advances the coupled system the paper defines in its Methods
+ * section: three conservative Allen-Cahn phase fields (droplet, lubricant,
+ * ambient; Eqs. 8, 15-19), incompressible flow with capillary and electric
+ * forcing (Eqs. 9-12), the Gauss law for the potential (Eq. 13, solved to a
+ * tolerance every step as the inner iteration of Eq. 21 does) and leaky-
+ * dielectric charge transport (Eq. 14), on a lattice with micropillar walls,
+ * energy-based wetting (Eq. 20) and electrodes.  The problem statement follows
+ * the Results section (Fig. 1): pillars and substrate grounded, electrodes
+ * held at their potential, insulating (Neumann) walls elsewhere.
+ *
+ * Conventions
+ *   - Lattice units.  Phase index 0 = droplet, 1 = lubricant, 2 = ambient.
+ *   - Node index n = x + Nx*(y + Ny*z), x fastest; 2D lattices have Nz = 1.
+ *   - Every axis wraps in index space; an axis declared non-periodic must have
+ *     solid end layers (EHDLB_EINVAL otherwise).
+ *   - Host arrays passed in are copied during the call; the caller keeps
+ *     ownership.  Device memory is never allocated by the library: the caller
+ *     provides one device workspace (ehdlb_workspace_bytes) and a HIP stream
+ *     at ehdlb_bind, and keeps both alive until ehdlb_destroy.
+ *   - Every call returns an ehdlb_status; nothing throws across the ABI.  The
+ *     message of the last error is available from ehdlb_last_error.
+ *   - A context is single-threaded: concurrent calls on one context are not
+ *     allowed; distinct contexts are independent.
+ */
+#ifndef EHDLB_H
+#define EHDLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EHDLB_MAX_ELECTRODES 4
+
+typedef enum {
+  EHDLB_OK = 0,
+  EHDLB_EINVAL = -1,      /* invalid parameter, geometry or argument          */
+  EHDLB_ESTATE = -2,      /* call out of order (e.g. step before set_phase)   */
+  EHDLB_EHIP = -3,        /* HIP runtime error (message in ehdlb_last_error)  */
+  EHDLB_ENOMEM = -4,      /* workspace smaller than ehdlb_workspace_bytes     */
+  EHDLB_ENONFINITE = -5,  /* non-finite field detected (sticky)               */
+  EHDLB_ENOCONV = -6      /* potential solve hit its iteration cap (sticky)   */
+} ehdlb_status;
+
+typedef enum { EHDLB_FP64 = 0, EHDLB_FP32_DEV = 1 } ehdlb_precision;
+
+/* Node flags (uint8): fluid, grounded solid (potential 0: pillars and
+ * substrate), insulating solid (zero normal flux), electrode k (potential
+ * V_k(t)).  Every non-fluid node is a wall for the populations. */
+typedef enum {
+  EHDLB_FLUID = 0,
+  EHDLB_GROUND = 1,
+  EHDLB_INSULATOR = 2,
+  EHDLB_ELECTRODE0 = 3
+} ehdlb_flag;
+
+/* Fields readable with ehdlb_read_field, always returned as float64 on the host.
+ * PHI*: phase fields of the current populations (Eq. 19).  UX..UZ: velocity of
+ * the last completed step (u = j + F/2).  P: pressure cs^2 (rho - 1) of the
+ * current populations.  RHO_E: charge density of the current populations.
+ * POT: potential solved in the last completed step.  Q: Ohmic source of the
+ * last completed step.  POPS: the current populations in canonical order
+ * [family][q][node] with families g (deviation from w), f1, f2, f3, h (the
+ * last only when the field is on); size ehdlb_num_populations doubles. */
+typedef enum {
+  EHDLB_FIELD_PHI1 = 0, EHDLB_FIELD_PHI2 = 1, EHDLB_FIELD_PHI3 = 2,
+  EHDLB_FIELD_UX = 3, EHDLB_FIELD_UY = 4, EHDLB_FIELD_UZ = 5,
+  EHDLB_FIELD_P = 6, EHDLB_FIELD_RHO_E = 7, EHDLB_FIELD_POT = 8,
+  EHDLB_FIELD_Q = 9, EHDLB_FIELD_POPS = 10
+} ehdlb_field;
+
+typedef struct ehdlb_ctx ehdlb_ctx;
+
+typedef struct {
+  int32_t dim;          /* 2 (D2Q9) or 3 (D3Q19)                                */
+  int32_t n[3];         /* Nx, Ny, Nz (Nz = 1 in 2D); each >= 1                 */
+  int32_t periodic[3];  /* 1: the axis wraps; 0: its two end layers are solid  */
+  int32_t precision;    /* ehdlb_precision                                      */
+} ehdlb_lattice;
+
+typedef struct {
+  double tau_flow[3];       /* flow relaxation time per phase (> 1/2); nu = (tau - 1/2)/3,
+                               mixed linearly in the phase fields                         */
+  double mobility;          /* M of Eq. 8 (> 0)                                           */
+  double width;             /* W_int of Eqs. 8, 10, 18, 20 (> 0)                          */
+  double gamma12, gamma13, gamma23;   /* pair tensions, Eq. 11; each Upsilon_i must be > 0 */
+  double cos12, cos13, cos23;         /* cos(theta_ij) of Eq. 20, theta_ij measured through
+                                         phase i                                          */
+  int32_t ehd;              /* 0: no electric field (no potential, no charge family)      */
+  int32_t reserved0;
+  double eps[3];            /* permittivity per phase (> 0), mixed linearly               */
+  double cond[3];           /* conductivity per phase (>= 0), mixed linearly              */
+  double charge_diffusion;  /* alpha of Eq. 14 (>= 0)                                     */
+  double body_force[3];     /* uniform body force density                                 */
+  double electrode_volts[EHDLB_MAX_ELECTRODES];  /* constant V_k unless a schedule is set */
+  double poisson_tol;       /* stop when max|b - A phi| <= tol * max|b|, residual in FP64 */
+  int32_t poisson_max_iter; /* iteration cap of the potential solve (>= 1)                */
+  int32_t poisson_check_every;  /* residual check period in iterations (>= 1)             */
+} ehdlb_params;
+
+typedef struct {
+  int64_t step;             /* completed steps                                          */
+  double mass[3];           /* sum of Phi_i over fluid nodes                            */
+  double centroid[3];       /* Phi_1-weighted mean node coordinate                      */
+  double velocity[3];       /* Phi_1-weighted mean velocity of the last completed step  */
+  double total_charge;      /* sum of rho_e over fluid nodes                            */
+  double sum_phi_drift;     /* max |Phi_1 + Phi_2 + Phi_3 - 1| over fluid nodes         */
+  double poisson_residual;  /* last relative FP64 residual of the potential solve       */
+  int32_t poisson_iters;    /* iterations of the last potential solve                   */
+  int32_t flags;            /* bit 0: non-finite seen; bit 1: solve hit its cap         */
+} ehdlb_obs;
+
+/* Validate lattice and parameters and create a context (no device work).
+ * EINVAL: dim not 2/3, sizes < 1, Nz != 1 in 2D, tau <= 1/2, M <= 0, W <= 0,
+ * any Upsilon_i <= 0, eps <= 0, cond < 0, alpha < 0, tol <= 0, max_iter < 1. */
+ehdlb_status ehdlb_create(const ehdlb_lattice* lattice, const ehdlb_params* params,
+                          ehdlb_ctx** out);
+
+/* Bytes of device workspace the context needs (populations A/B, fields,
+ * solver hierarchy, reduction scratch).  Valid right after create. */
+size_t ehdlb_workspace_bytes(const ehdlb_ctx* ctx);
+
+/* Bind a caller-owned device buffer of at least ehdlb_workspace_bytes bytes
+ * (256-byte aligned) on the current HIP device, and the HIP stream (a
+ * hipStream_t, or NULL for the null stream) all work is enqueued on.
+ * ENOMEM if bytes is too small; EINVAL on a misaligned pointer. */
+ehdlb_status ehdlb_bind(ehdlb_ctx* ctx, void* device_workspace, size_t bytes, void* hip_stream);
+
+/* Node flags, host array of N uint8 (ehdlb_flag values; 3 + k for electrode k).
+ * Builds the wetting links of solid nodes next to fluid and the potential
+ * solver's hierarchy on the host, then copies them to the device.
+ * EINVAL: unknown flag, electrode index >= EHDLB_MAX_ELECTRODES, fluid on the
+ * end layer of a non-periodic axis, a fluid node without a fluid neighbour, or
+ * (field on) a fluid region with no grounded or electrode face.
+ * Can be called before bind (then only validation and host tables). */
+ehdlb_status ehdlb_set_geometry(ehdlb_ctx* ctx, const uint8_t* flags);
+
+/* Initial phase fields, host float64 array [3][N].  Populations are set to
+ * equilibrium at rest (u = 0, rho = 1), rho_e = 0 (no bulk free charge), and
+ * the step counter to 0.  Needs bind and set_geometry (ESTATE otherwise). */
+ehdlb_status ehdlb_set_phase(ehdlb_ctx* ctx, const double* phi);
+
+/* Optional initial charge density, host float64 [N] (after set_phase). */
+ehdlb_status ehdlb_set_charge(ehdlb_ctx* ctx, const double* rho_e);
+
+/* Piecewise-constant voltage schedule of electrode k: during step t (0-based)
+ * the electrode holds volts[s] with s = floor(t * n_seg / t_total), clamped to
+ * n_seg - 1 for t >= t_total.  The array is copied.  EINVAL on k out of range,
+ * n_seg < 1 or t_total < 1.  n_seg = 0 clears the schedule. */
+ehdlb_status ehdlb_set_schedule(ehdlb_ctx* ctx, int32_t electrode, int32_t n_seg,
+                                const double* volts, int64_t t_total);
+
+/* Advance n >= 0 steps.  Work is enqueued on the bound stream; the call
+ * synchronises only for the potential solve's residual checks. */
+ehdlb_status ehdlb_step(ehdlb_ctx* ctx, int64_t n);
+
+/* Copy one field to a host float64 array of N values (POPS: see above).
+ * Synchronises the bound stream. */
+ehdlb_status ehdlb_read_field(ehdlb_ctx* ctx, int32_t field, double* dst_host);
+
+/* Number of doubles ehdlb_read_field(EHDLB_FIELD_POPS) writes. */
+size_t ehdlb_num_populations(const ehdlb_ctx* ctx);
+
+/* Droplet observables of the current state (FP64 fixed-order reductions).
+ * Synchronises.  Returns ENONFINITE / ENOCONV (sticky) after filling *out. */
+ehdlb_status ehdlb_observables(ehdlb_ctx* ctx, ehdlb_obs* out);
+
+/* Full state (populations, previous-step fields, potential, step counter) as
+ * an opaque device blob of ehdlb_state_bytes bytes; save/load copy on the
+ * bound stream (device to device). */
+size_t ehdlb_state_bytes(const ehdlb_ctx* ctx);
+ehdlb_status ehdlb_save_state(ehdlb_ctx* ctx, void* device_dst);
+ehdlb_status ehdlb_load_state(ehdlb_ctx* ctx, const void* device_src);
+
+/* Wetting links built by set_geometry (host, no device needed): for each
+ * solid node next to fluid, the node index and the direction index n* of
+ * the link along which its phase values are extrapolated.  Writes at most
+ * cap entries and returns the total count (or a negative status). */
+int64_t ehdlb_wetting_links(const ehdlb_ctx* ctx, int64_t* nodes, int32_t* dirs, int64_t cap);
+
+const char* ehdlb_last_error(const ehdlb_ctx* ctx);
+void ehdlb_destroy(ehdlb_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EHDLB_H */

@@ -1,0 +1,97 @@
+"""ctypes binding of libehdlb.so (argument marshalling only; see include/ehdlb.h).
+
+The library is loaded from this package directory.  There is no fallback: if
+the shared object is missing the import of `lib()` raises.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libehdlb.so")
+
+MAX_ELECTRODES = 4
+OK, EINVAL, ESTATE, EHIP, ENOMEM, ENONFINITE, ENOCONV = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "EHIP", -4: "ENOMEM", -5: "ENONFINITE", -6: "ENOCONV"}
+FP64, FP32_DEV = 0, 1
+FIELDS = dict(phi1=0, phi2=1, phi3=2, ux=3, uy=4, uz=5, p=6, rho_e=7, pot=8, q=9, pops=10)
+
+
+class Lattice(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("periodic", C.c_int32 * 3), ("precision", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("tau_flow", C.c_double * 3),
+        ("mobility", C.c_double),
+        ("width", C.c_double),
+        ("gamma12", C.c_double), ("gamma13", C.c_double), ("gamma23", C.c_double),
+        ("cos12", C.c_double), ("cos13", C.c_double), ("cos23", C.c_double),
+        ("ehd", C.c_int32), ("reserved0", C.c_int32),
+        ("eps", C.c_double * 3), ("cond", C.c_double * 3),
+        ("charge_diffusion", C.c_double),
+        ("body_force", C.c_double * 3),
+        ("electrode_volts", C.c_double * MAX_ELECTRODES),
+        ("poisson_tol", C.c_double),
+        ("poisson_max_iter", C.c_int32), ("poisson_check_every", C.c_int32),
+    ]
+
+
+class Obs(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64),
+        ("mass", C.c_double * 3), ("centroid", C.c_double * 3), ("velocity", C.c_double * 3),
+        ("total_charge", C.c_double), ("sum_phi_drift", C.c_double), ("poisson_residual", C.c_double),
+        ("poisson_iters", C.c_int32), ("flags", C.c_int32),
+    ]
+
+
+class EhdlbError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+SIGNATURES = {
+    "ehdlb_create": (C.c_int, [C.POINTER(Lattice), C.POINTER(Params), C.POINTER(C.c_void_p)]),
+    "ehdlb_workspace_bytes": (C.c_size_t, [C.c_void_p]),
+    "ehdlb_bind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ehdlb_set_geometry": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ehdlb_set_phase": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ehdlb_set_charge": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ehdlb_set_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64]),
+    "ehdlb_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "ehdlb_read_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "ehdlb_num_populations": (C.c_size_t, [C.c_void_p]),
+    "ehdlb_observables": (C.c_int, [C.c_void_p, C.POINTER(Obs)]),
+    "ehdlb_state_bytes": (C.c_size_t, [C.c_void_p]),
+    "ehdlb_save_state": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ehdlb_load_state": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ehdlb_wetting_links": (C.c_int64, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "ehdlb_last_error": (C.c_char_p, [C.c_void_p]),
+    "ehdlb_destroy": (None, [C.c_void_p]),
+}
+
+
+def lib():
+    """Load libehdlb.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2608_12868_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def check(ctx, status):
+    if status != OK:
+        msg = lib().ehdlb_last_error(ctx)
+        raise EhdlbError(status, msg.decode() if msg else "")
+    return status

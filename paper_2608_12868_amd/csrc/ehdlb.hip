@@ -1,0 +1,918 @@
+// Host side of the ternary EHD lattice-Boltzmann library: validation, geometry tables,
+// workspace layout, the time-step driver and the C ABI declared in include/ehdlb.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ehdlb.h"
+#include "kernels.h"
+
+using namespace ehd;
+
+namespace {
+
+struct Status {
+  ehdlb_status code;
+};
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+struct MGLevel {
+  Level L;
+  size_t cp, diag, r, z, t;  // byte offsets
+};
+
+}  // namespace
+
+struct ehdlb_ctx {
+  ehdlb_lattice lat{};
+  ehdlb_params prm{};
+  int D = 2, Q = 9, F = 4;
+  int64_t N = 0;
+  size_t tsize = 8;
+  bool ehd = false;
+  std::string err;
+  // host tables
+  std::vector<uint8_t> flags;
+  std::vector<int32_t> ghost_node, ghost_src;
+  std::vector<int32_t> ghost_dir;
+  bool have_geometry = false;
+  bool have_state = false;
+  // schedules
+  struct Sched {
+    std::vector<double> v;
+    int64_t t_total = 0;
+  } sched[EHDLB_MAX_ELECTRODES];
+  // device
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  int64_t t = 0;
+  int cur = 0;
+  int sticky = 0;
+  double last_resid = 0.0;
+  int last_iters = 0;
+  // layout (byte offsets into ws)
+  size_t off_pop[2]{}, off_phi[2]{}, off_rho[2]{}, off_u[2]{}, off_q[2]{}, off_pot = 0;
+  size_t off_flags = 0, off_gnode = 0, off_gsrc = 0, off_glen = 0, off_scratch = 0;
+  size_t off_b = 0, off_r = 0, off_z = 0, off_p = 0, off_qv = 0;
+  size_t off_part = 0, off_red = 0, off_cg = 0, off_inv = 0, off_dbl = 0;
+  size_t state_bytes = 0, total = 0;
+  std::vector<MGLevel> mg;
+  int64_t max_ghost = 0;
+  int64_t nparts = 0;
+  int64_t hdr[4]{};  // host staging of the state header (kept alive for async copies)
+
+  template <class T>
+  T* ptr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+// ============================================================================ helpers
+static ehdlb_status fail(ehdlb_ctx* c, ehdlb_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(c, EHDLB_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCHCHK()                                                                        \
+  do {                                                                                     \
+    hipError_t e_ = hipGetLastError();                                                     \
+    if (e_ != hipSuccess) return fail(c, EHDLB_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+static void upsilons(const ehdlb_params& p, double u[3], double& ut) {
+  u[0] = p.gamma12 + p.gamma13 - p.gamma23;
+  u[1] = p.gamma12 + p.gamma23 - p.gamma13;
+  u[2] = p.gamma13 + p.gamma23 - p.gamma12;
+  ut = 3.0 / (1.0 / u[0] + 1.0 / u[1] + 1.0 / u[2]);
+}
+
+template <class T>
+static Phys<T> make_phys(const ehdlb_params& p) {
+  Phys<T> r{};
+  double u[3], ut;
+  upsilons(p, u, ut);
+  r.W = (T)p.width;
+  for (int i = 0; i < 3; ++i) r.ups[i] = (T)u[i];
+  r.upsT = (T)ut;
+  r.cos12 = (T)p.cos12;
+  r.cos13 = (T)p.cos13;
+  r.cos23 = (T)p.cos23;
+  r.s_phi = (T)(1.0 / (0.5 + 3.0 * p.mobility));
+  r.s_e = (T)(1.0 / (0.5 + 3.0 * p.charge_diffusion));
+  for (int i = 0; i < 3; ++i) {
+    r.nu[i] = (T)((p.tau_flow[i] - 0.5) / 3.0);
+    r.eps[i] = (T)p.eps[i];
+    r.cond[i] = (T)p.cond[i];
+    r.body[i] = (T)p.body_force[i];
+  }
+  return r;
+}
+
+static double volts_at(const ehdlb_ctx* c, int k, int64_t t) {
+  const auto& s = c->sched[k];
+  if (s.v.empty()) return c->prm.electrode_volts[k];
+  // floor(t * n_seg / t_total) in exact integer arithmetic
+  int64_t seg = (t * (int64_t)s.v.size()) / s.t_total;
+  if (seg >= (int64_t)s.v.size()) seg = (int64_t)s.v.size() - 1;
+  if (seg < 0) seg = 0;
+  return s.v[(size_t)seg];
+}
+
+// lattice tables on the host (same canonical order as the device)
+static void host_lattice(int dim, std::vector<int>& ex, std::vector<int>& ey, std::vector<int>& ez,
+                         std::vector<int>& w36) {
+  if (dim == 2) {
+    ex.assign(D2Q9::ex, D2Q9::ex + 9);
+    ey.assign(D2Q9::ey, D2Q9::ey + 9);
+    ez.assign(D2Q9::ez, D2Q9::ez + 9);
+    w36.assign(D2Q9::w36, D2Q9::w36 + 9);
+  } else {
+    ex.assign(D3Q19::ex, D3Q19::ex + 19);
+    ey.assign(D3Q19::ey, D3Q19::ey + 19);
+    ez.assign(D3Q19::ez, D3Q19::ez + 19);
+    w36.assign(D3Q19::w36, D3Q19::w36 + 19);
+  }
+}
+
+// ============================================================================ layout
+static void plan_layout(ehdlb_ctx* c) {
+  const int64_t N = c->N;
+  const size_t ts = c->tsize;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  // --- state region (save/load copies [state_begin, state_end))
+  for (int k = 0; k < 2; ++k) c->off_pop[k] = take((size_t)c->F * c->Q * N * ts);
+  for (int k = 0; k < 2; ++k) c->off_phi[k] = take(3 * N * ts);
+  for (int k = 0; k < 2; ++k) c->off_rho[k] = take(N * ts);
+  for (int k = 0; k < 2; ++k) c->off_u[k] = take((size_t)c->D * N * ts);
+  for (int k = 0; k < 2; ++k) c->off_q[k] = take(N * ts);
+  c->off_pot = take(N * ts);
+  // --- geometry
+  c->off_flags = take(N);
+  c->max_ghost = N;  // upper bound; actual count known at set_geometry
+  c->off_gnode = take(N * 4);
+  c->off_gsrc = take(N * 4);
+  c->off_glen = take(N * ts);
+  c->off_scratch = take(N * ts);
+  c->off_dbl = take(N * 8);
+  // --- potential solver
+  c->mg.clear();
+  if (c->ehd) {
+    c->off_b = take(N * ts);
+    c->off_r = take(N * ts);
+    c->off_z = take(N * ts);
+    c->off_p = take(N * ts);
+    c->off_qv = take(N * ts);
+    Level L0{{c->lat.n[0], c->lat.n[1], c->lat.n[2]}, N};
+    MGLevel m0{};
+    m0.L = L0;
+    m0.cp = take((size_t)c->D * N * ts);
+    m0.diag = take(N * ts);
+    m0.r = c->off_r;
+    m0.z = take(N * ts);
+    m0.t = take(N * ts);
+    c->mg.push_back(m0);
+    while (c->mg.back().L.N > kCoarseMax) {
+      Level f = c->mg.back().L;
+      Level l{};
+      for (int a = 0; a < 3; ++a) l.n[a] = (a < c->D) ? (f.n[a] + 1) / 2 : 1;
+      l.N = (int64_t)l.n[0] * l.n[1] * l.n[2];
+      if (l.N == f.N) break;
+      MGLevel m{};
+      m.L = l;
+      m.cp = take((size_t)c->D * l.N * ts);
+      m.diag = take(l.N * ts);
+      m.r = take(l.N * ts);
+      m.z = take(l.N * ts);
+      m.t = take(l.N * ts);
+      c->mg.push_back(m);
+    }
+    const int64_t nc = c->mg.back().L.N;
+    c->off_inv = take((size_t)nc * nc * 8);
+  }
+  c->nparts = nblocks(N);
+  c->off_part = take((size_t)c->nparts * kObs * 8 + 64);
+  c->off_red = take(64 * 8);
+  c->off_cg = take(8 * 8);
+  c->state_bytes = 256 + align_up((size_t)c->F * c->Q * N * ts) + (c->off_pot + N * ts - c->off_phi[0]);
+  c->total = o;
+}
+
+// ============================================================================ validation
+static ehdlb_status validate(ehdlb_ctx* c, const ehdlb_lattice* L, const ehdlb_params* p) {
+  if (!L || !p) return fail(c, EHDLB_EINVAL, "null lattice or params");
+  if (L->dim != 2 && L->dim != 3) return fail(c, EHDLB_EINVAL, "dim must be 2 or 3");
+  for (int a = 0; a < 3; ++a)
+    if (L->n[a] < 1) return fail(c, EHDLB_EINVAL, "lattice sizes must be >= 1");
+  if (L->dim == 2 && L->n[2] != 1) return fail(c, EHDLB_EINVAL, "2D lattices need Nz = 1");
+  if ((int64_t)L->n[0] * L->n[1] * L->n[2] >= (int64_t)1 << 31) return fail(c, EHDLB_EINVAL, "too many nodes");
+  if (L->precision != EHDLB_FP64 && L->precision != EHDLB_FP32_DEV)
+    return fail(c, EHDLB_EINVAL, "unknown precision");
+  for (int i = 0; i < 3; ++i) {
+    if (!(p->tau_flow[i] > 0.5)) return fail(c, EHDLB_EINVAL, "tau_flow must exceed 1/2");
+    if (p->ehd && !(p->eps[i] > 0.0)) return fail(c, EHDLB_EINVAL, "permittivity must be > 0");
+    if (p->ehd && !(p->cond[i] >= 0.0)) return fail(c, EHDLB_EINVAL, "conductivity must be >= 0");
+  }
+  if (!(p->mobility > 0.0)) return fail(c, EHDLB_EINVAL, "mobility must be > 0");
+  if (!(p->width > 0.0)) return fail(c, EHDLB_EINVAL, "interface width must be > 0");
+  double u[3], ut;
+  upsilons(*p, u, ut);
+  for (int i = 0; i < 3; ++i)
+    if (!(u[i] > 0.0)) return fail(c, EHDLB_EINVAL, "every Upsilon_i (Eq. 11) must be > 0");
+  if (p->ehd) {
+    if (!(p->charge_diffusion >= 0.0)) return fail(c, EHDLB_EINVAL, "charge diffusion must be >= 0");
+    if (!(p->poisson_tol > 0.0)) return fail(c, EHDLB_EINVAL, "poisson_tol must be > 0");
+    if (p->poisson_max_iter < 1) return fail(c, EHDLB_EINVAL, "poisson_max_iter must be >= 1");
+    if (p->poisson_check_every < 1) return fail(c, EHDLB_EINVAL, "poisson_check_every must be >= 1");
+  }
+  return EHDLB_OK;
+}
+
+// ============================================================================ potential solve
+template <int D, class T>
+static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout) {
+  hipStream_t s = c->stream;
+  MGLevel& m = c->mg[lvl];
+  const Level L = m.L;
+  T* cp = c->ptr<T>(m.cp);
+  T* dg = c->ptr<T>(m.diag);
+  if (lvl + 1 == c->mg.size()) {
+    T* z = c->ptr<T>(m.z);
+    hipLaunchKernelGGL(k_coarse_apply<T>, dim3(1), dim3(kBlock), 0, s, (int)L.N,
+                       c->ptr<double>(c->off_inv), dg, r, z);
+    LAUNCHCHK();
+    *zout = z;
+    return EHDLB_OK;
+  }
+  const T omega = T(0.8);
+  const int nu = 2;
+  T* z = c->ptr<T>(m.z);
+  T* t = c->ptr<T>(m.t);
+  hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nblocks(L.N)), dim3(kBlock), 0, s, L, cp, dg, r, (const T*)nullptr, z, omega);
+  for (int k = 1; k < nu; ++k) {
+    hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nblocks(L.N)), dim3(kBlock), 0, s, L, cp, dg, r, z, t, omega);
+    std::swap(z, t);
+  }
+  MGLevel& mc = c->mg[lvl + 1];
+  T* rc = c->ptr<T>(mc.r);
+  hipLaunchKernelGGL((k_restrict_resid<D, T>), dim3(nblocks(mc.L.N)), dim3(kBlock), 0, s, L, cp, dg, r, z, mc.L, rc);
+  LAUNCHCHK();
+  T* zc = nullptr;
+  ehdlb_status st = vcycle<D, T>(c, lvl + 1, rc, &zc);
+  if (st) return st;
+  hipLaunchKernelGGL((k_prolong<D, T>), dim3(nblocks(L.N)), dim3(kBlock), 0, s, L, dg, z, mc.L, (const T*)zc, T(1));
+  for (int k = 0; k < nu; ++k) {
+    hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nblocks(L.N)), dim3(kBlock), 0, s, L, cp, dg, r, z, t, omega);
+    std::swap(z, t);
+  }
+  LAUNCHCHK();
+  *zout = z;
+  return EHDLB_OK;
+}
+
+template <class LT, class T>
+static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, const Volts<T>& volts) {
+  constexpr int D = LT::D;
+  hipStream_t s = c->stream;
+  const int64_t N = c->N;
+  const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
+  MGLevel& m0 = c->mg[0];
+  T* cp0 = c->ptr<T>(m0.cp);
+  T* dg0 = c->ptr<T>(m0.diag);
+  T* b = c->ptr<T>(c->off_b);
+  T* x = c->ptr<T>(c->off_pot);
+  T* r = c->ptr<T>(c->off_r);
+  T* p = c->ptr<T>(c->off_p);
+  T* qv = c->ptr<T>(c->off_qv);
+  double* part = c->ptr<double>(c->off_part);
+  double* red = c->ptr<double>(c->off_red);
+  double* cg = c->ptr<double>(c->off_cg);
+  const Phys<T> ph = make_phys<T>(c->prm);
+  const int nb0 = nblocks(N);
+
+  hipLaunchKernelGGL((k_pois_setup<LT, T>), dim3(nb0), dim3(kBlock), 0, s, dm, c->ptr<uint8_t>(c->off_flags), phi, rho,
+                     ph, volts, cp0, dg0, b);
+  for (size_t l = 0; l + 1 < c->mg.size(); ++l) {
+    MGLevel& f = c->mg[l];
+    MGLevel& g = c->mg[l + 1];
+    hipLaunchKernelGGL((k_coarsen<D, T>), dim3(nblocks(g.L.N)), dim3(kBlock), 0, s, f.L, c->ptr<T>(f.cp),
+                       c->ptr<T>(f.diag), g.L, c->ptr<T>(g.cp), c->ptr<T>(g.diag));
+  }
+  {
+    MGLevel& g = c->mg.back();
+    hipLaunchKernelGGL((k_coarse_invert<D, T>), dim3(1), dim3(kBlock), 0, s, g.L, c->ptr<T>(g.cp), c->ptr<T>(g.diag),
+                       c->ptr<double>(c->off_inv));
+  }
+  LAUNCHCHK();
+
+  auto check = [&](double& rel, double& bmax) -> ehdlb_status {
+    hipLaunchKernelGGL((k_true_resid<D, T>), dim3(nb0), dim3(kBlock), 0, s, m0.L, cp0, dg0, b, x, r, part);
+    hipLaunchKernelGGL((k_final<2, true>), dim3(1), dim3(kBlock), 0, s, part, nb0, red);
+    LAUNCHCHK();
+    double h[2];
+    HIPCHK(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bmax = h[1];
+    rel = bmax > 0.0 ? h[0] / bmax : 0.0;
+    return EHDLB_OK;
+  };
+
+  double rel = 0.0, bmax = 0.0;
+  ehdlb_status st = check(rel, bmax);
+  if (st) return st;
+  c->last_iters = 0;
+  if (bmax == 0.0) {
+    hipLaunchKernelGGL(k_zero<T>, dim3(nb0), dim3(kBlock), 0, s, N, x);
+    c->last_resid = 0.0;
+    return EHDLB_OK;
+  }
+  const double tol = c->prm.poisson_tol;
+  if (!(rel <= tol) && std::isfinite(rel)) {
+    T* z = nullptr;
+    if ((st = vcycle<D, T>(c, 0, r, &z))) return st;
+    hipLaunchKernelGGL(k_dot<T>, dim3(nb0), dim3(kBlock), 0, s, N, r, z, part);
+    hipLaunchKernelGGL((k_final<1, false>), dim3(1), dim3(kBlock), 0, s, part, nb0, red);
+    hipLaunchKernelGGL(k_cg_init_rz, dim3(1), dim3(1), 0, s, red, cg);
+    hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb0), dim3(kBlock), 0, s, N, cg, z, p, 1);
+    LAUNCHCHK();
+    int it = 0;
+    const int maxit = c->prm.poisson_max_iter, every = c->prm.poisson_check_every;
+    bool conv = false;
+    while (it < maxit) {
+      ++it;
+      hipLaunchKernelGGL((k_spmv<D, T, true>), dim3(nb0), dim3(kBlock), 0, s, m0.L, cp0, dg0, p, qv, part);
+      hipLaunchKernelGGL((k_final<1, false>), dim3(1), dim3(kBlock), 0, s, part, nb0, red);
+      hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1), 0, s, red, cg);
+      hipLaunchKernelGGL(k_cg_update<T>, dim3(nb0), dim3(kBlock), 0, s, N, cg, p, qv, x, r);
+      LAUNCHCHK();
+      if (it % every == 0 || it == maxit) {
+        if ((st = check(rel, bmax))) return st;
+        if (rel <= tol || !std::isfinite(rel)) {
+          conv = rel <= tol;
+          break;
+        }
+      }
+      if ((st = vcycle<D, T>(c, 0, r, &z))) return st;
+      hipLaunchKernelGGL(k_dot<T>, dim3(nb0), dim3(kBlock), 0, s, N, r, z, part);
+      hipLaunchKernelGGL((k_final<1, false>), dim3(1), dim3(kBlock), 0, s, part, nb0, red);
+      hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1), 0, s, red, cg);
+      hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb0), dim3(kBlock), 0, s, N, cg, z, p, 0);
+      LAUNCHCHK();
+    }
+    c->last_iters = it;
+    if (!conv) c->sticky |= 2;
+  }
+  if (!std::isfinite(rel)) c->sticky |= 1;
+  c->last_resid = rel;
+  return EHDLB_OK;
+}
+
+// ============================================================================ step
+template <class LT, class T, bool EHD>
+static ehdlb_status step_impl(ehdlb_ctx* c, int64_t n) {
+  hipStream_t s = c->stream;
+  const int64_t N = c->N;
+  const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
+  const Phys<T> ph = make_phys<T>(c->prm);
+  const uint8_t* flags = c->ptr<uint8_t>(c->off_flags);
+  const int G = (int)c->ghost_node.size();
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t t = c->t;
+    const int pi = (int)(t & 1), pp = 1 - pi;
+    Volts<T> v{};
+    for (int e = 0; e < kMaxE; ++e) v.v[e] = (T)volts_at(c, e, t);
+    T* phi = c->ptr<T>(c->off_phi[pi]);
+    T* rho = c->ptr<T>(c->off_rho[pi]);
+    const T* pin = c->ptr<T>(c->off_pop[c->cur]);
+    T* pout = c->ptr<T>(c->off_pop[1 - c->cur]);
+    hipLaunchKernelGGL((k_moments<LT, T, EHD>), dim3(nblocks(N)), dim3(kBlock), 0, s, dm, flags, pin, phi, rho,
+                       (T*)nullptr);
+    if (G > 0)
+      hipLaunchKernelGGL(k_ghosts<T>, dim3(nblocks(G)), dim3(kBlock), 0, s, N, G, c->ptr<int32_t>(c->off_gnode),
+                         c->ptr<int32_t>(c->off_gsrc), c->ptr<T>(c->off_glen), phi, ph);
+    LAUNCHCHK();
+    if (EHD) {
+      ehdlb_status st = potential_solve<LT, T>(c, phi, rho, v);
+      if (st) return st;
+    }
+    StepArgs<T> a{};
+    a.d = dm;
+    a.flags = flags;
+    a.pop_in = pin;
+    a.pop_out = pout;
+    a.phi = phi;
+    a.phi_prev = c->ptr<T>(c->off_phi[pp]);
+    a.rho = rho;
+    a.rho_prev = c->ptr<T>(c->off_rho[pp]);
+    a.u_prev = c->ptr<T>(c->off_u[pp]);
+    a.u_out = c->ptr<T>(c->off_u[pi]);
+    a.q_prev = c->ptr<T>(c->off_q[pp]);
+    a.q_out = c->ptr<T>(c->off_q[pi]);
+    a.pot = c->ptr<T>(c->off_pot);
+    a.p = ph;
+    a.volts = v;
+    a.dt_on = t == 0 ? T(0) : T(1);
+    hipLaunchKernelGGL((k_step<LT, T, EHD>), dim3(nblocks(N)), dim3(kBlock), 0, s, a);
+    LAUNCHCHK();
+    c->cur = 1 - c->cur;
+    c->t = t + 1;
+  }
+  return EHDLB_OK;
+}
+
+template <class LT, class T, bool EHD>
+static ehdlb_status moments_now(ehdlb_ctx* c, T* drho) {
+  const int64_t N = c->N;
+  const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
+  const int pi = (int)(c->t & 1);
+  hipLaunchKernelGGL((k_moments<LT, T, EHD>), dim3(nblocks(N)), dim3(kBlock), 0, c->stream, dm,
+                     c->ptr<uint8_t>(c->off_flags), c->ptr<T>(c->off_pop[c->cur]), c->ptr<T>(c->off_phi[pi]),
+                     c->ptr<T>(c->off_rho[pi]), drho);
+  LAUNCHCHK();
+  return EHDLB_OK;
+}
+
+template <class LT, class T, bool EHD>
+static ehdlb_status observables_impl(ehdlb_ctx* c, ehdlb_obs* o) {
+  ehdlb_status st = moments_now<LT, T, EHD>(c, nullptr);
+  if (st) return st;
+  const int64_t N = c->N;
+  const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
+  const int pi = (int)(c->t & 1), pp = 1 - pi;
+  // per-block partials: sums [nblocks][kObs] in the FP64 scratch, maxima [nblocks] in the
+  // reduction buffer
+  double* psum = c->ptr<double>(c->off_dbl);
+  double* pmax = c->ptr<double>(c->off_part);
+  const int nb = nblocks(N);
+  hipLaunchKernelGGL((k_obs<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, c->stream, dm, c->ptr<uint8_t>(c->off_flags),
+                     c->ptr<T>(c->off_phi[pi]), c->ptr<T>(c->off_phi[pp]), c->ptr<T>(c->off_u[pp]),
+                     c->ptr<T>(c->off_rho[pi]), psum, pmax);
+  double* red = c->ptr<double>(c->off_red);
+  hipLaunchKernelGGL((k_final<kObs, false>), dim3(1), dim3(kBlock), 0, c->stream, psum, nb, red);
+  hipLaunchKernelGGL((k_final<1, true>), dim3(1), dim3(kBlock), 0, c->stream, pmax, nb, red + kObs);
+  LAUNCHCHK();
+  double h[kObs + 1];
+  HIPCHK(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::memset(o, 0, sizeof(*o));
+  o->step = c->t;
+  for (int i = 0; i < 3; ++i) o->mass[i] = h[i];
+  for (int a = 0; a < 3; ++a) o->centroid[a] = h[3 + a] / h[0];
+  for (int a = 0; a < 3; ++a) o->velocity[a] = h[9] != 0.0 ? h[6 + a] / h[9] : 0.0;
+  o->total_charge = h[10];
+  o->sum_phi_drift = h[kObs];
+  o->poisson_residual = c->last_resid;
+  o->poisson_iters = c->last_iters;
+  if (h[11] != 0.0 || !std::isfinite(h[0] + h[1] + h[2])) c->sticky |= 1;
+  o->flags = c->sticky;
+  return EHDLB_OK;
+}
+
+// dispatch on (lattice, precision, field on/off)
+template <template <class, class, bool> class Fn, class... A>
+static ehdlb_status dispatch(ehdlb_ctx* c, A... args) {
+  const bool f32 = c->lat.precision == EHDLB_FP32_DEV;
+  if (c->D == 2) {
+    if (f32) return c->ehd ? Fn<D2Q9, float, true>::run(c, args...) : Fn<D2Q9, float, false>::run(c, args...);
+    return c->ehd ? Fn<D2Q9, double, true>::run(c, args...) : Fn<D2Q9, double, false>::run(c, args...);
+  }
+  if (f32) return c->ehd ? Fn<D3Q19, float, true>::run(c, args...) : Fn<D3Q19, float, false>::run(c, args...);
+  return c->ehd ? Fn<D3Q19, double, true>::run(c, args...) : Fn<D3Q19, double, false>::run(c, args...);
+}
+
+template <class LT, class T, bool EHD>
+struct StepFn {
+  static ehdlb_status run(ehdlb_ctx* c, int64_t n) { return step_impl<LT, T, EHD>(c, n); }
+};
+template <class LT, class T, bool EHD>
+struct ObsFn {
+  static ehdlb_status run(ehdlb_ctx* c, ehdlb_obs* o) { return observables_impl<LT, T, EHD>(c, o); }
+};
+template <class LT, class T, bool EHD>
+struct InitFn {
+  static ehdlb_status run(ehdlb_ctx* c, int dummy) {
+    (void)dummy;
+    const int64_t N = c->N;
+    const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
+    // initial fields were copied into the t = -1 slots (index 1): they serve as the
+    // previous-step fields of the first step
+    hipLaunchKernelGGL((k_init<LT, T, EHD>), dim3(nblocks(N)), dim3(kBlock), 0, c->stream, dm,
+                       c->ptr<uint8_t>(c->off_flags), c->ptr<T>(c->off_pop[0]), c->ptr<T>(c->off_phi[1]),
+                       c->ptr<T>(c->off_rho[1]), c->ptr<T>(c->off_u[1]), c->ptr<T>(c->off_q[1]));
+    const int64_t npop = (int64_t)c->F * c->Q * N;
+    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(npop)), dim3(kBlock), 0, c->stream, npop, c->ptr<T>(c->off_pop[1]));
+    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, c->stream, N, c->ptr<T>(c->off_pot));
+    LAUNCHCHK();
+    return EHDLB_OK;
+  }
+};
+template <class LT, class T, bool EHD>
+struct MomFn {
+  static ehdlb_status run(ehdlb_ctx* c, int dummy) {
+    (void)dummy;
+    return moments_now<LT, T, EHD>(c, c->ptr<T>(c->off_scratch));
+  }
+};
+
+template <class T>
+static ehdlb_status copy_out(ehdlb_ctx* c, const T* src, int64_t n, double* dst) {
+  // convert on the device into the FP64 scratch in chunks of N, then copy
+  double* tmp = c->ptr<double>(c->off_dbl);
+  for (int64_t o = 0; o < n; o += c->N) {
+    const int64_t m = std::min<int64_t>(c->N, n - o);
+    hipLaunchKernelGGL(k_to_double<T>, dim3(nblocks(m)), dim3(kBlock), 0, c->stream, m, src + o, tmp);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(dst + o, tmp, m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  return EHDLB_OK;
+}
+
+template <class T>
+static ehdlb_status upload(ehdlb_ctx* c, const double* src, int64_t n, T* dst) {
+  std::vector<T> h((size_t)n);
+  for (int64_t i = 0; i < n; ++i) h[(size_t)i] = (T)src[i];
+  HIPCHK(hipMemcpyAsync(dst, h.data(), n * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return EHDLB_OK;
+}
+
+// copy flags and wetting links to the device
+static ehdlb_status upload_geometry(ehdlb_ctx* c) {
+  std::vector<int> ex, ey, ez, w36;
+  host_lattice(c->D, ex, ey, ez, w36);
+  HIPCHK(hipMemcpyAsync(c->ptr<uint8_t>(c->off_flags), c->flags.data(), c->N, hipMemcpyHostToDevice, c->stream));
+  const size_t G = c->ghost_node.size();
+  if (G) {
+    HIPCHK(hipMemcpyAsync(c->ptr<int32_t>(c->off_gnode), c->ghost_node.data(), G * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->ptr<int32_t>(c->off_gsrc), c->ghost_src.data(), G * 4, hipMemcpyHostToDevice, c->stream));
+    std::vector<double> len(G);
+    for (size_t k = 0; k < G; ++k) {
+      const int q = c->ghost_dir[k];
+      len[k] = std::sqrt((double)(ex[q] * ex[q] + ey[q] * ey[q] + ez[q] * ez[q]));
+    }
+    ehdlb_status st = c->tsize == 8 ? upload<double>(c, len.data(), (int64_t)G, c->ptr<double>(c->off_glen))
+                                    : upload<float>(c, len.data(), (int64_t)G, c->ptr<float>(c->off_glen));
+    if (st) return st;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return EHDLB_OK;
+}
+
+// ============================================================================ C ABI
+extern "C" {
+
+ehdlb_status ehdlb_create(const ehdlb_lattice* lattice, const ehdlb_params* params, ehdlb_ctx** out) {
+  if (!out) return EHDLB_EINVAL;
+  *out = nullptr;
+  ehdlb_ctx tmp;
+  ehdlb_status st = validate(&tmp, lattice, params);
+  if (st) return st;
+  ehdlb_ctx* c = new ehdlb_ctx();
+  c->lat = *lattice;
+  c->prm = *params;
+  c->D = lattice->dim;
+  c->Q = lattice->dim == 2 ? 9 : 19;
+  c->ehd = params->ehd != 0;
+  c->F = c->ehd ? 5 : 4;
+  c->N = (int64_t)lattice->n[0] * lattice->n[1] * lattice->n[2];
+  c->tsize = lattice->precision == EHDLB_FP64 ? 8 : 4;
+  plan_layout(c);
+  *out = c;
+  return EHDLB_OK;
+}
+
+size_t ehdlb_workspace_bytes(const ehdlb_ctx* c) { return c ? c->total : 0; }
+
+size_t ehdlb_state_bytes(const ehdlb_ctx* c) { return c ? c->state_bytes : 0; }
+
+size_t ehdlb_num_populations(const ehdlb_ctx* c) { return c ? (size_t)c->F * c->Q * c->N : 0; }
+
+ehdlb_status ehdlb_bind(ehdlb_ctx* c, void* ws, size_t bytes, void* stream) {
+  if (!c) return EHDLB_EINVAL;
+  if (!ws) return fail(c, EHDLB_EINVAL, "null workspace");
+  if (((uintptr_t)ws) % 256 != 0) return fail(c, EHDLB_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < c->total) return fail(c, EHDLB_ENOMEM, "workspace too small");
+  c->ws = (char*)ws;
+  c->ws_bytes = bytes;
+  c->stream = (hipStream_t)stream;
+  c->bound = true;
+  c->have_state = false;
+  if (c->have_geometry) return upload_geometry(c);
+  return EHDLB_OK;
+}
+
+ehdlb_status ehdlb_set_geometry(ehdlb_ctx* c, const uint8_t* flags) {
+  if (!c) return EHDLB_EINVAL;
+  if (!flags) return fail(c, EHDLB_EINVAL, "null flags");
+  const int nx = c->lat.n[0], ny = c->lat.n[1], nz = c->lat.n[2];
+  const int64_t N = c->N;
+  std::vector<int> ex, ey, ez, w36;
+  host_lattice(c->D, ex, ey, ez, w36);
+  const int Q = c->Q;
+  for (int64_t i = 0; i < N; ++i) {
+    if (flags[i] > EHDLB_ELECTRODE0 + EHDLB_MAX_ELECTRODES - 1)
+      return fail(c, EHDLB_EINVAL, "unknown node flag at node " + std::to_string(i));
+  }
+  auto nbr = [&](int64_t i, int q) -> int64_t {
+    int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+    x = (x + ex[q] + nx) % nx;
+    y = (y + ey[q] + ny) % ny;
+    z = (z + ez[q] + nz) % nz;
+    return x + (int64_t)nx * (y + (int64_t)ny * z);
+  };
+  // end layers of non-periodic axes must be solid
+  for (int64_t i = 0; i < N; ++i) {
+    if (flags[i] != EHDLB_FLUID) continue;
+    const int xyz[3] = {(int)(i % nx), (int)((i / nx) % ny), (int)(i / ((int64_t)nx * ny))};
+    for (int a = 0; a < 3; ++a) {
+      if (!c->lat.periodic[a] && c->lat.n[a] > 1 && (xyz[a] == 0 || xyz[a] == c->lat.n[a] - 1))
+        return fail(c, EHDLB_EINVAL, "fluid on the end layer of a non-periodic axis");
+    }
+    bool any = false;
+    for (int q = 1; q < Q && !any; ++q) any = flags[nbr(i, q)] == EHDLB_FLUID;
+    if (!any) return fail(c, EHDLB_EINVAL, "fluid node without a fluid neighbour: " + std::to_string(i));
+  }
+  // potential: every fluid region (connected through axis faces) needs a Dirichlet face
+  if (c->ehd) {
+    std::vector<int32_t> comp((size_t)N, -1);
+    std::vector<int64_t> stack;
+    for (int64_t s0 = 0; s0 < N; ++s0) {
+      if (flags[s0] != EHDLB_FLUID || comp[(size_t)s0] >= 0) continue;
+      bool dir = false;
+      stack.clear();
+      stack.push_back(s0);
+      comp[(size_t)s0] = 1;
+      while (!stack.empty()) {
+        const int64_t i = stack.back();
+        stack.pop_back();
+        for (int q = 1; q < Q; ++q) {
+          if (ex[q] * ex[q] + ey[q] * ey[q] + ez[q] * ez[q] != 1) continue;
+          const int64_t j = nbr(i, q);
+          const uint8_t f = flags[j];
+          if (f == EHDLB_FLUID) {
+            if (comp[(size_t)j] < 0) {
+              comp[(size_t)j] = 1;
+              stack.push_back(j);
+            }
+          } else if (f == EHDLB_GROUND || f >= EHDLB_ELECTRODE0) {
+            dir = true;
+          }
+        }
+      }
+      if (!dir) return fail(c, EHDLB_EINVAL, "a fluid region has no grounded or electrode face");
+    }
+  }
+  // wetting links: n* maximises (e.N_s)/|e| over fluid neighbours with e.N_s > 0,
+  // N_s = sum over fluid neighbours of 36 w e (exact integers); ties to the lowest index;
+  // N_s = 0 -> the first fluid neighbour.
+  c->ghost_node.clear();
+  c->ghost_src.clear();
+  c->ghost_dir.clear();
+  for (int64_t s = 0; s < N; ++s) {
+    if (flags[s] == EHDLB_FLUID) continue;
+    int nsx = 0, nsy = 0, nsz = 0, first = -1;
+    for (int q = 1; q < Q; ++q) {
+      if (flags[nbr(s, q)] != EHDLB_FLUID) continue;
+      if (first < 0) first = q;
+      nsx += w36[q] * ex[q];
+      nsy += w36[q] * ey[q];
+      nsz += w36[q] * ez[q];
+    }
+    if (first < 0) continue;
+    int best = -1;
+    long long bd = 0, bl = 1;
+    if (nsx == 0 && nsy == 0 && nsz == 0) {
+      best = first;
+    } else {
+      for (int q = 1; q < Q; ++q) {
+        if (flags[nbr(s, q)] != EHDLB_FLUID) continue;
+        const long long d = (long long)ex[q] * nsx + (long long)ey[q] * nsy + (long long)ez[q] * nsz;
+        if (d <= 0) continue;
+        const long long l2 = ex[q] * ex[q] + ey[q] * ey[q] + ez[q] * ez[q];
+        if (best < 0 || d * d * bl > bd * bd * l2) {
+          best = q;
+          bd = d;
+          bl = l2;
+        }
+      }
+    }
+    c->ghost_node.push_back((int32_t)s);
+    c->ghost_dir.push_back(best);
+    c->ghost_src.push_back((int32_t)nbr(s, best));
+  }
+  c->flags.assign(flags, flags + N);
+  c->have_geometry = true;
+  c->have_state = false;
+  if (c->bound) return upload_geometry(c);
+  return EHDLB_OK;
+}
+
+ehdlb_status ehdlb_set_phase(ehdlb_ctx* c, const double* phi) {
+  if (!c) return EHDLB_EINVAL;
+  if (!phi) return fail(c, EHDLB_EINVAL, "null phase array");
+  if (!c->bound) return fail(c, EHDLB_ESTATE, "set_phase before bind");
+  if (!c->have_geometry) return fail(c, EHDLB_ESTATE, "set_phase before set_geometry");
+  ehdlb_status st;
+  const int64_t N = c->N;
+  std::vector<double> zero((size_t)N, 0.0);
+  if (c->tsize == 8) {
+    if ((st = upload<double>(c, phi, 3 * N, c->ptr<double>(c->off_phi[1])))) return st;
+    if ((st = upload<double>(c, zero.data(), N, c->ptr<double>(c->off_rho[1])))) return st;
+  } else {
+    if ((st = upload<float>(c, phi, 3 * N, c->ptr<float>(c->off_phi[1])))) return st;
+    if ((st = upload<float>(c, zero.data(), N, c->ptr<float>(c->off_rho[1])))) return st;
+  }
+  c->t = 0;
+  c->cur = 0;
+  c->sticky = 0;
+  c->last_iters = 0;
+  c->last_resid = 0.0;
+  if ((st = dispatch<InitFn>(c, 0))) return st;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->have_state = true;
+  return EHDLB_OK;
+}
+
+ehdlb_status ehdlb_set_charge(ehdlb_ctx* c, const double* rho) {
+  if (!c) return EHDLB_EINVAL;
+  if (!rho) return fail(c, EHDLB_EINVAL, "null charge array");
+  if (!c->have_state || c->t != 0) return fail(c, EHDLB_ESTATE, "set_charge needs a fresh set_phase");
+  if (!c->ehd) return fail(c, EHDLB_EINVAL, "set_charge with the field off");
+  // the initial fields sit in the t = -1 slots; replace the charge there and rebuild
+  ehdlb_status st;
+  if (c->tsize == 8) {
+    if ((st = upload<double>(c, rho, c->N, c->ptr<double>(c->off_rho[1])))) return st;
+  } else {
+    if ((st = upload<float>(c, rho, c->N, c->ptr<float>(c->off_rho[1])))) return st;
+  }
+  if ((st = dispatch<InitFn>(c, 0))) return st;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return EHDLB_OK;
+}
+
+ehdlb_status ehdlb_set_schedule(ehdlb_ctx* c, int32_t k, int32_t n_seg, const double* volts, int64_t t_total) {
+  if (!c) return EHDLB_EINVAL;
+  if (k < 0 || k >= EHDLB_MAX_ELECTRODES) return fail(c, EHDLB_EINVAL, "electrode index out of range");
+  if (n_seg == 0) {
+    c->sched[k].v.clear();
+    return EHDLB_OK;
+  }
+  if (n_seg < 0 || !volts || t_total < 1) return fail(c, EHDLB_EINVAL, "bad schedule");
+  c->sched[k].v.assign(volts, volts + n_seg);
+  c->sched[k].t_total = t_total;
+  return EHDLB_OK;
+}
+
+ehdlb_status ehdlb_step(ehdlb_ctx* c, int64_t n) {
+  if (!c) return EHDLB_EINVAL;
+  if (n < 0) return fail(c, EHDLB_EINVAL, "negative step count");
+  if (!c->have_state) return fail(c, EHDLB_ESTATE, "step before set_phase");
+  return dispatch<StepFn>(c, n);
+}
+
+ehdlb_status ehdlb_read_field(ehdlb_ctx* c, int32_t field, double* dst) {
+  if (!c) return EHDLB_EINVAL;
+  if (!dst) return fail(c, EHDLB_EINVAL, "null destination");
+  if (!c->have_state) return fail(c, EHDLB_ESTATE, "read_field before set_phase");
+  const int64_t N = c->N;
+  const int pi = (int)(c->t & 1), pp = 1 - pi;
+  ehdlb_status st;
+  auto out = [&](size_t off, int64_t n) -> ehdlb_status {
+    return c->tsize == 8 ? copy_out<double>(c, c->ptr<double>(off), n, dst)
+                         : copy_out<float>(c, c->ptr<float>(off), n, dst);
+  };
+  switch (field) {
+    case EHDLB_FIELD_PHI1:
+    case EHDLB_FIELD_PHI2:
+    case EHDLB_FIELD_PHI3:
+    case EHDLB_FIELD_RHO_E:
+    case EHDLB_FIELD_P:
+      if ((st = dispatch<MomFn>(c, 0))) return st;
+      if (field == EHDLB_FIELD_RHO_E) {
+        if (!c->ehd) {
+          std::fill(dst, dst + N, 0.0);
+          return EHDLB_OK;
+        }
+        return out(c->off_rho[pi], N);
+      }
+      if (field == EHDLB_FIELD_P) {
+        if ((st = out(c->off_scratch, N))) return st;
+        for (int64_t i = 0; i < N; ++i) dst[i] *= 1.0 / 3.0;
+        return EHDLB_OK;
+      }
+      return out(c->off_phi[pi] + (size_t)(field - EHDLB_FIELD_PHI1) * N * c->tsize, N);
+    case EHDLB_FIELD_UX:
+    case EHDLB_FIELD_UY:
+    case EHDLB_FIELD_UZ: {
+      const int a = field - EHDLB_FIELD_UX;
+      if (a >= c->D) {
+        std::fill(dst, dst + N, 0.0);
+        return EHDLB_OK;
+      }
+      return out(c->off_u[pp] + (size_t)a * N * c->tsize, N);
+    }
+    case EHDLB_FIELD_POT:
+      if (!c->ehd) {
+        std::fill(dst, dst + N, 0.0);
+        return EHDLB_OK;
+      }
+      return out(c->off_pot, N);
+    case EHDLB_FIELD_Q:
+      if (!c->ehd) {
+        std::fill(dst, dst + N, 0.0);
+        return EHDLB_OK;
+      }
+      return out(c->off_q[pp], N);
+    case EHDLB_FIELD_POPS:
+      return out(c->off_pop[c->cur], (int64_t)c->F * c->Q * N);
+    default:
+      return fail(c, EHDLB_EINVAL, "unknown field id");
+  }
+}
+
+ehdlb_status ehdlb_observables(ehdlb_ctx* c, ehdlb_obs* o) {
+  if (!c) return EHDLB_EINVAL;
+  if (!o) return fail(c, EHDLB_EINVAL, "null output");
+  if (!c->have_state) return fail(c, EHDLB_ESTATE, "observables before set_phase");
+  ehdlb_status st = dispatch<ObsFn>(c, o);
+  if (st) return st;
+  if (c->sticky & 1) return fail(c, EHDLB_ENONFINITE, "non-finite field");
+  if (c->sticky & 2) return fail(c, EHDLB_ENOCONV, "potential solve hit its iteration cap");
+  return EHDLB_OK;
+}
+
+// state blob: [256-byte header: t, magic, N, sizeof(T)][current populations][field slots
+// phi x2, rho x2, u x2, q x2, pot, in t-parity order]
+ehdlb_status ehdlb_save_state(ehdlb_ctx* c, void* dst) {
+  if (!c) return EHDLB_EINVAL;
+  if (!dst) return fail(c, EHDLB_EINVAL, "null destination");
+  if (!c->have_state) return fail(c, EHDLB_ESTATE, "save_state before set_phase");
+  char* d = (char*)dst;
+  c->hdr[0] = c->t;
+  c->hdr[1] = 0x45484442;
+  c->hdr[2] = (int64_t)c->N;
+  c->hdr[3] = (int64_t)c->tsize;
+  HIPCHK(hipMemcpyAsync(d, c->hdr, sizeof(c->hdr), hipMemcpyHostToDevice, c->stream));
+  const size_t pop_bytes = (size_t)c->F * c->Q * c->N * c->tsize;
+  HIPCHK(hipMemcpyAsync(d + 256, c->ws + c->off_pop[c->cur], pop_bytes, hipMemcpyDeviceToDevice, c->stream));
+  const size_t rest = c->off_pot + c->N * c->tsize - c->off_phi[0];
+  HIPCHK(hipMemcpyAsync(d + 256 + align_up(pop_bytes), c->ws + c->off_phi[0], rest, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return EHDLB_OK;
+}
+
+ehdlb_status ehdlb_load_state(ehdlb_ctx* c, const void* src) {
+  if (!c) return EHDLB_EINVAL;
+  if (!src) return fail(c, EHDLB_EINVAL, "null source");
+  if (!c->bound || !c->have_geometry) return fail(c, EHDLB_ESTATE, "load_state before bind/set_geometry");
+  const char* s = (const char*)src;
+  int64_t hdr[4];
+  HIPCHK(hipMemcpyAsync(hdr, s, sizeof(hdr), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (hdr[1] != 0x45484442 || hdr[2] != c->N || hdr[3] != (int64_t)c->tsize)
+    return fail(c, EHDLB_EINVAL, "state blob does not match this context");
+  const size_t pop_bytes = (size_t)c->F * c->Q * c->N * c->tsize;
+  HIPCHK(hipMemcpyAsync(c->ws + c->off_pop[0], s + 256, pop_bytes, hipMemcpyDeviceToDevice, c->stream));
+  const size_t rest = c->off_pot + c->N * c->tsize - c->off_phi[0];
+  HIPCHK(hipMemcpyAsync(c->ws + c->off_phi[0], s + 256 + align_up(pop_bytes), rest, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->t = hdr[0];
+  c->cur = 0;
+  c->have_state = true;
+  return EHDLB_OK;
+}
+
+int64_t ehdlb_wetting_links(const ehdlb_ctx* c, int64_t* nodes, int32_t* dirs, int64_t cap) {
+  if (!c) return EHDLB_EINVAL;
+  if (!c->have_geometry) return EHDLB_ESTATE;
+  const int64_t G = (int64_t)c->ghost_node.size();
+  for (int64_t k = 0; k < std::min(G, cap); ++k) {
+    if (nodes) nodes[k] = c->ghost_node[(size_t)k];
+    if (dirs) dirs[k] = c->ghost_dir[(size_t)k];
+  }
+  return G;
+}
+
+const char* ehdlb_last_error(const ehdlb_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void ehdlb_destroy(ehdlb_ctx* c) { delete c; }
+
+}  // extern "C"

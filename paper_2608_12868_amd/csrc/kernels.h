@@ -1,0 +1,894 @@
+// Device kernels of the ternary EHD lattice-Boltzmann step (gfx950).
+//
+// Layout: structure of arrays.  Populations pop[family][q][node] with node =
+// x + Nx*(y + Ny*z), families g (flow, stored as the deviation g - w), f1, f2,
+// f3 (phase fields), h (charge).  Scalar fields [N], vector fields [D][N].
+// One thread per node, x fastest, so every family/direction plane is streamed
+// with unit stride.  Streaming is "push": a fluid node collides its own
+// populations (aligned loads) and writes each post-collision value to the
+// neighbour it moves to, or back into its own opposite slot when that
+// neighbour is solid (halfway bounce-back); A/B buffers, so there are no
+// in-place races and every fluid slot is written exactly once.
+//
+// Arithmetic type T is double (FP64 path) or float (FP32 path, flow stored as
+// deviations).  Reductions and the potential solve's residual are FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include "lattice.h"
+
+namespace ehd {
+
+constexpr int kBlock = 256;
+constexpr int kMaxE = 4;
+constexpr int kObs = 16;   // observable accumulators per block
+
+// ----------------------------------------------------------------------------- geometry helpers
+struct Dims {
+  int nx, ny, nz;
+  int64_t N;
+};
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+template <class L>
+__device__ __forceinline__ void neighbours(const Dims& d, int64_t node, int (&nb)[L::Q]) {
+  const int x = (int)(node % d.nx);
+  const int y = (int)((node / d.nx) % d.ny);
+  const int z = (int)(node / ((int64_t)d.nx * d.ny));
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const int xx = wrap(x + L::ex[q], d.nx);
+    const int yy = wrap(y + L::ey[q], d.ny);
+    const int zz = wrap(z + L::ez[q], d.nz);
+    nb[q] = xx + d.nx * (yy + d.ny * zz);
+  }
+}
+
+// ----------------------------------------------------------------------------- parameters
+template <class T>
+struct Phys {
+  T W;            // interface width
+  T ups[3], upsT; // Eq. 11
+  T cos12, cos13, cos23;
+  T s_phi;        // first-order rate of the phase fields, 1/(1/2 + M/cs2)
+  T s_e;          // first-order rate of the charge, 1/(1/2 + alpha/cs2)
+  T nu[3];        // kinematic viscosity per phase
+  T eps[3], cond[3];
+  T body[3];
+};
+
+template <class T>
+struct Volts {
+  T v[kMaxE];
+};
+
+template <class T>
+struct StepArgs {
+  Dims d;
+  const uint8_t* flags;
+  const T* pop_in;
+  T* pop_out;
+  const T* phi;       // [3][N] at t, ghosts filled
+  const T* phi_prev;  // [3][N] at t-1
+  const T* rho;       // [N] at t
+  const T* rho_prev;  // [N] at t-1
+  const T* u_prev;    // [D][N] at t-1
+  T* u_out;           // [D][N] at t
+  const T* q_prev;    // [N]
+  T* q_out;           // [N]
+  const T* pot;       // [N]
+  Phys<T> p;
+  Volts<T> volts;
+  T dt_on;            // 0 on the first step (no time derivatives), 1 afterwards
+};
+
+// ----------------------------------------------------------------------------- moments (Eq. 19)
+// Phi_i = sum_q f_i,q and rho_e = sum_q h_q at fluid nodes; zero at solid nodes
+// (the wetting kernel then overwrites the solid nodes next to fluid).  With
+// drho != nullptr also the flow density deviation (read-out only).
+template <class L, class T, bool EHD>
+__global__ __launch_bounds__(kBlock) void k_moments(Dims d, const uint8_t* __restrict__ flags,
+                                                     const T* __restrict__ pop, T* __restrict__ phi,
+                                                     T* __restrict__ rho, T* __restrict__ drho) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= d.N) return;
+  const int64_t N = d.N;
+  const bool fluid = flags[node] == 0;
+  T s[3] = {0, 0, 0};
+  T r = 0, g = 0;
+  if (fluid) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) s[i] += pop[((int64_t)(1 + i) * L::Q + q) * N + node];
+    }
+    if (EHD) {
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) r += pop[((int64_t)4 * L::Q + q) * N + node];
+    }
+    if (drho) {
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) g += pop[(int64_t)q * N + node];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) phi[(int64_t)i * N + node] = s[i];
+  if (EHD) rho[node] = r;
+  if (drho) drho[node] = g;
+}
+
+// ----------------------------------------------------------------------------- wetting ghosts (Eq. 20)
+// For solid node s with link e*: Phi_i(s) = Phi_i(s + e*) - |e*| * (4/W) * R_i,
+// R_i the bracket of Eq. 20 evaluated with the fluid neighbour's values.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_ghosts(int64_t N, int G, const int32_t* __restrict__ gnode,
+                                                    const int32_t* __restrict__ gsrc,
+                                                    const T* __restrict__ glen, T* __restrict__ phi,
+                                                    Phys<T> p) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= G) return;
+  const int64_t s = gnode[k], f = gsrc[k];
+  const T p1 = phi[f], p2 = phi[N + f], p3 = phi[2 * N + f];
+  const T a = T(4) / p.W;
+  const T r1 = a * (-p.cos13 * p1 * p3 - p.cos12 * p1 * p2);
+  const T r2 = a * (p.cos12 * p1 * p2 - p.cos23 * p2 * p3);
+  const T r3 = a * (p.cos23 * p2 * p3 + p.cos13 * p1 * p3);
+  const T l = glen[k];
+  phi[s] = p1 - l * r1;
+  phi[N + s] = p2 - l * r2;
+  phi[2 * N + s] = p3 - l * r3;
+}
+
+// ----------------------------------------------------------------------------- fused collide-stream
+template <class L, class T, bool EHD>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
+  constexpr int Q = L::Q;
+  constexpr int D = L::D;
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= a.d.N) return;
+  if (a.flags[node] != 0) return;
+  const int64_t N = a.d.N;
+  const Phys<T>& p = a.p;
+  const T cs2 = T(1) / T(3);
+
+  int nb[Q];
+  neighbours<L>(a.d, node, nb);
+
+  // ---- a3: isotropic gradient and Laplacian of the three phase fields
+  T pc[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) pc[i] = a.phi[(int64_t)i * N + node];
+  T gr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  T lap[3] = {0, 0, 0};
+  uint32_t solid = 0;
+  T sig_ax[2 * D];  // conductivity at the axis neighbours (+a, -a)
+  uint8_t fl_ax[2 * D];
+#pragma unroll
+  for (int q = 1; q < Q; ++q) {
+    const int m = nb[q];
+    const uint8_t fm = a.flags[m];
+    if (fm) solid |= 1u << q;
+    const T w = T(L::w36[q]) / T(36);
+    T v[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      v[i] = a.phi[(int64_t)i * N + m];
+      gr[i][0] += w * T(L::ex[q]) * v[i];
+      gr[i][1] += w * T(L::ey[q]) * v[i];
+      if (D == 3) gr[i][2] += w * T(L::ez[q]) * v[i];
+      lap[i] += w * (v[i] - pc[i]);
+    }
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      if (q == L::axp[ax] || q == L::axm[ax]) {
+        const int k = 2 * ax + (q == L::axp[ax] ? 0 : 1);
+        sig_ax[k] = p.cond[0] * v[0] + p.cond[1] * v[1] + p.cond[2] * v[2];
+        fl_ax[k] = fm;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gr[i][c] *= T(3);
+    lap[i] *= T(6);
+  }
+
+  // ---- a4: chemical potentials (Eq. 10) and capillary force F_s = sum mu_i grad Phi_i
+  const T triple = pc[0] * pc[1] * pc[2];
+  T F[3] = {p.body[0], p.body[1], p.body[2]};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T mu = T(24) * p.ups[i] / p.W * pc[i] * (pc[i] - T(1)) * (pc[i] - T(0.5)) -
+                 T(24) * p.upsT / p.W * triple - T(0.75) * p.ups[i] * p.W * lap[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) F[c] += mu * gr[i][c];
+  }
+
+  // ---- a6: electric force (Eq. 12) and Ohmic source of the charge equation
+  T Qs = 0;
+  if (EHD) {
+    const T phx = a.pot[node];
+    const T sigx = p.cond[0] * pc[0] + p.cond[1] * pc[1] + p.cond[2] * pc[2];
+    T E[3] = {0, 0, 0};
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      T side[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int q = k == 0 ? L::axp[ax] : L::axm[ax];
+        const uint8_t fm = fl_ax[2 * ax + k];
+        if (fm == 0) {
+          const T v = a.pot[nb[q]];
+          side[k] = v;
+          Qs += T(0.5) * (sigx + sig_ax[2 * ax + k]) * (v - phx);
+        } else if (fm == 1 || fm >= 3) {
+          const T pd = fm == 1 ? T(0) : a.volts.v[fm - 3];
+          side[k] = T(2) * pd - phx;
+          Qs += T(2) * sigx * (pd - phx);
+        } else {
+          side[k] = phx;
+        }
+      }
+      E[ax] = -T(0.5) * (side[0] - side[1]);
+    }
+    const T e2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
+    const T rq = a.rho[node];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T ge = p.eps[0] * gr[0][c] + p.eps[1] * gr[1][c] + p.eps[2] * gr[2][c];
+      F[c] += rq * E[c] - T(0.5) * e2 * ge;
+    }
+  }
+
+  auto emit = [&](int fam, int q, T val) {
+    if ((solid >> q) & 1u)
+      a.pop_out[((int64_t)fam * Q + L::opp[q]) * N + node] = val;
+    else
+      a.pop_out[((int64_t)fam * Q + q) * N + nb[q]] = val;
+  };
+
+  // ---- a7: flow.  u = j + F/2, incompressible equilibrium, Guo source, raw-moment MRT
+  // with second-order moments at 1/tau(x) and all higher moments at 1.
+  T u[3];
+  {
+    T gq[Q];
+    T drho = 0, j[3] = {0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      gq[q] = a.pop_in[(int64_t)q * N + node];
+      drho += gq[q];
+      j[0] += T(L::ex[q]) * gq[q];
+      j[1] += T(L::ey[q]) * gq[q];
+      j[2] += T(L::ez[q]) * gq[q];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = j[c] + T(0.5) * F[c];
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    const T nu = p.nu[0] * pc[0] + p.nu[1] * pc[1] + p.nu[2] * pc[2];
+    const T s_nu = T(1) / (T(0.5) + T(3) * nu);
+    // second-order raw moments of g - g_eq + F_q/2
+    T Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const T exq = T(L::ex[q]), eyq = T(L::ey[q]), ezq = T(L::ez[q]);
+      const T w = T(L::w36[q]) / T(36);
+      const T eu = exq * u[0] + eyq * u[1] + ezq * u[2];
+      const T eF = exq * F[0] + eyq * F[1] + ezq * F[2];
+      const T geq = w * (drho + T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu);
+      const T fq = w * (T(3) * (eF - uF) + T(9) * eu * eF);
+      const T dq = gq[q] - geq + T(0.5) * fq;
+      Pxx += exq * exq * dq;
+      Pyy += eyq * eyq * dq;
+      Pxy += exq * eyq * dq;
+      if (D == 3) {
+        Pzz += ezq * ezq * dq;
+        Pxz += exq * ezq * dq;
+        Pyz += eyq * ezq * dq;
+      }
+    }
+    const T om = T(1) - s_nu;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
+      const T exq = T(ix), eyq = T(iy), ezq = T(iz);
+      const T w = T(L::w36[q]) / T(36);
+      const T eu = exq * u[0] + eyq * u[1] + ezq * u[2];
+      const T eF = exq * F[0] + eyq * F[1] + ezq * F[2];
+      const T geq = w * (drho + T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu);
+      const T fq = w * (T(3) * (eF - uF) + T(9) * eu * eF);
+      // columns of M^-1 of the monomial basis for the second-order moments:
+      // xx: +1/2 on the +-x links, -1 at rest; xy: e_x e_y / 4 on the xy-plane diagonals
+      T corr;
+      const int l2 = ix * ix + iy * iy + iz * iz;
+      if (l2 == 0) {
+        corr = -(Pxx + Pyy + Pzz);
+      } else if (l2 == 1) {
+        corr = T(0.5) * (ix ? Pxx : (iy ? Pyy : Pzz));
+      } else {
+        corr = T(0.25) * (iz == 0 ? exq * eyq * Pxy : (iy == 0 ? exq * ezq * Pxz : eyq * ezq * Pyz));
+      }
+      emit(0, q, geq + T(0.5) * fq + om * corr);
+    }
+  }
+
+  // ---- a8: phase fields (Eqs. 15-18).  G_i = cs2 F_Phi_i + d(Phi_i u)/dt; first-order raw
+  // moments at s_phi, others at 1: f* = f_eq + C/2 + (1 - s_phi)/2 e.J on the axis links.
+  {
+    T nrm[3][3], amag[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T m2 = gr[i][0] * gr[i][0] + gr[i][1] * gr[i][1] + gr[i][2] * gr[i][2];
+      const T inv = T(1) / sqrt(m2 + T(1e-24));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) nrm[i][c] = gr[i][c] * inv;
+      amag[i] = T(4) / p.W * fabs(pc[i] * (T(1) - pc[i]));
+    }
+    T tot[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) tot[c] = amag[0] * nrm[0][c] + amag[1] * nrm[1][c] + amag[2] * nrm[2][c];
+    T den = pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2];
+    if (!(den > T(0))) den = T(1);
+    const T om = T(1) - p.s_phi;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T share = pc[i] * pc[i] / den;
+      const T php = a.phi_prev[(int64_t)i * N + node];
+      T G[3], J[3];
+      T jf[3] = {0, 0, 0};
+      T fq[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        fq[q] = a.pop_in[((int64_t)(1 + i) * Q + q) * N + node];
+        jf[0] += T(L::ex[q]) * fq[q];
+        jf[1] += T(L::ey[q]) * fq[q];
+        jf[2] += T(L::ez[q]) * fq[q];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T up = c < D ? a.u_prev[(int64_t)c * N + node] : T(0);
+        const T Fphi = amag[i] * nrm[i][c] - share * tot[c];
+        G[c] = cs2 * Fphi + a.dt_on * (pc[i] * u[c] - php * up);
+        J[c] = jf[c] - pc[i] * u[c] + T(0.5) * G[c];
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
+        const T w = T(L::w36[q]) / T(36);
+        const T eu = T(ix) * u[0] + T(iy) * u[1] + T(iz) * u[2];
+        const T eG = T(ix) * G[0] + T(iy) * G[1] + T(iz) * G[2];
+        T val = w * pc[i] * (T(1) + T(3) * eu) + T(1.5) * w * eG;
+        if (ix * ix + iy * iy + iz * iz == 1) val += T(0.5) * om * (T(ix) * J[0] + T(iy) * J[1] + T(iz) * J[2]);
+        emit(1 + i, q, val);
+      }
+    }
+  }
+
+  // ---- a9: charge (Eq. 14): equilibrium rho_e w (1 + e.u/cs2), R = (w/cs2) e.d(rho_e u)/dt
+  // inside the MRT, Ohmic source w (Q + dQ/dt / 2) after the collision.
+  if (EHD) {
+    const T rq = a.rho[node];
+    const T rp = a.rho_prev[node];
+    T dru[3], J[3], jh[3] = {0, 0, 0};
+    T hq[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      hq[q] = a.pop_in[((int64_t)4 * Q + q) * N + node];
+      jh[0] += T(L::ex[q]) * hq[q];
+      jh[1] += T(L::ey[q]) * hq[q];
+      jh[2] += T(L::ez[q]) * hq[q];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T up = c < D ? a.u_prev[(int64_t)c * N + node] : T(0);
+      dru[c] = a.dt_on * (rq * u[c] - rp * up);
+      J[c] = jh[c] - rq * u[c] + T(0.5) * dru[c];
+    }
+    const T src = Qs + T(0.5) * a.dt_on * (Qs - a.q_prev[node]);
+    const T om = T(1) - p.s_e;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
+      const T w = T(L::w36[q]) / T(36);
+      const T eu = T(ix) * u[0] + T(iy) * u[1] + T(iz) * u[2];
+      const T eR = T(ix) * dru[0] + T(iy) * dru[1] + T(iz) * dru[2];
+      T val = w * rq * (T(1) + T(3) * eu) + T(1.5) * w * eR + w * src;
+      if (ix * ix + iy * iy + iz * iz == 1) val += T(0.5) * om * (T(ix) * J[0] + T(iy) * J[1] + T(iz) * J[2]);
+      emit(4, q, val);
+    }
+    a.q_out[node] = Qs;
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) a.u_out[(int64_t)c * N + node] = u[c];
+}
+
+// ----------------------------------------------------------------------------- initial state
+// Populations at rest equilibrium: f_i = w Phi_i, g - w = 0, h = w rho_e.  phi0/rho0 hold the
+// initial fields (they double as the previous-step fields of the first step).
+template <class L, class T, bool EHD>
+__global__ __launch_bounds__(kBlock) void k_init(Dims d, const uint8_t* __restrict__ flags,
+                                                  T* __restrict__ pop, T* __restrict__ phi0,
+                                                  T* __restrict__ rho0, T* __restrict__ u_prev,
+                                                  T* __restrict__ q_prev) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= d.N) return;
+  const int64_t N = d.N;
+  const bool fluid = flags[node] == 0;
+  T ph[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    ph[i] = fluid ? phi0[(int64_t)i * N + node] : T(0);
+    phi0[(int64_t)i * N + node] = ph[i];
+  }
+  const T r = (EHD && fluid) ? rho0[node] : T(0);
+  if (EHD) {
+    rho0[node] = r;
+    q_prev[node] = T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const T w = T(L::w36[q]) / T(36);
+    pop[(int64_t)q * N + node] = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pop[((int64_t)(1 + i) * L::Q + q) * N + node] = w * ph[i];
+    if (EHD) pop[((int64_t)4 * L::Q + q) * N + node] = w * r;
+  }
+#pragma unroll
+  for (int c = 0; c < L::D; ++c) u_prev[(int64_t)c * N + node] = T(0);
+}
+
+// ----------------------------------------------------------------------------- block reductions
+template <int K, bool MAX>
+__device__ __forceinline__ void block_reduce(double (&v)[K], double* __restrict__ out) {
+  __shared__ double sm[kBlock / 64][K];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double y = __shfl_down(x, off, 64);
+      x = MAX ? fmax(x, y) : x + y;
+    }
+    if (lane == 0) sm[wv][k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double x = sm[0][threadIdx.x];
+    for (int w = 1; w < kBlock / 64; ++w) x = MAX ? fmax(x, sm[w][threadIdx.x]) : x + sm[w][threadIdx.x];
+    out[threadIdx.x] = x;
+  }
+}
+
+// Sum (or max) of nblk partial rows of width K into out[K]; one block, fixed order.
+template <int K, bool MAX>
+__global__ __launch_bounds__(kBlock) void k_final(const double* __restrict__ part, int nblk,
+                                                   double* __restrict__ out) {
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = MAX ? -INFINITY : 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kBlock) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = MAX ? fmax(v[k], part[(int64_t)b * K + k]) : v[k] + part[(int64_t)b * K + k];
+  }
+  block_reduce<K, MAX>(v, out);
+}
+
+// ----------------------------------------------------------------------------- observables (a10)
+// Per-block FP64 partials: 0-2 masses, 3-5 sum x Phi1, 6-8 sum Phi1_prev u_prev,
+// 9 sum Phi1_prev, 10 total charge, 11 count of non-finite values; block 2 of the
+// output (max |sum Phi - 1|) is a separate max-partial.
+template <class L, class T, bool EHD>
+__global__ __launch_bounds__(kBlock) void k_obs(Dims d, const uint8_t* __restrict__ flags,
+                                                 const T* __restrict__ phi, const T* __restrict__ phi_prev,
+                                                 const T* __restrict__ u_prev, const T* __restrict__ rho,
+                                                 double* __restrict__ part_sum, double* __restrict__ part_max) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[kObs];
+#pragma unroll
+  for (int k = 0; k < kObs; ++k) v[k] = 0.0;
+  double mx[1] = {0.0};
+  if (node < d.N && flags[node] == 0) {
+    const int64_t N = d.N;
+    const double p1 = phi[node], p2 = phi[N + node], p3 = phi[2 * N + node];
+    const double x = (double)(node % d.nx), y = (double)((node / d.nx) % d.ny),
+                 z = (double)(node / ((int64_t)d.nx * d.ny));
+    v[0] = p1;
+    v[1] = p2;
+    v[2] = p3;
+    v[3] = x * p1;
+    v[4] = y * p1;
+    v[5] = z * p1;
+    const double pp = phi_prev[node];
+    v[6] = pp * (double)u_prev[node];
+    v[7] = pp * (double)u_prev[N + node];
+    if (L::D == 3) v[8] = pp * (double)u_prev[2 * N + node];
+    v[9] = pp;
+    if (EHD) v[10] = rho[node];
+    const double s = p1 + p2 + p3;
+    v[11] = (isfinite(s) && isfinite(v[6] + v[7] + v[8]) && isfinite(v[10])) ? 0.0 : 1.0;
+    mx[0] = fabs(s - 1.0);
+  }
+  block_reduce<kObs, false>(v, part_sum + (int64_t)blockIdx.x * kObs);
+  __syncthreads();
+  block_reduce<1, true>(mx, part_max + blockIdx.x);
+}
+
+// ----------------------------------------------------------------------------- potential solver
+// Finite-volume Gauss law on the axis faces: coefficients per level are explicit:
+// cp[a][i] couples cell i with i + e_a (0 across solids), diag[i] includes the Dirichlet
+// faces.  Level 0 is the lattice; coarser levels aggregate 2 (2D: 2x2, 3D: 2x2x2) cells
+// with the Galerkin operator of piecewise-constant interpolation.
+struct Level {
+  int n[3];
+  int64_t N;
+};
+
+template <int D>
+__device__ __forceinline__ void cell_xyz(const Level& L, int64_t i, int& x, int& y, int& z) {
+  x = (int)(i % L.n[0]);
+  y = (int)((i / L.n[0]) % L.n[1]);
+  z = D == 3 ? (int)(i / ((int64_t)L.n[0] * L.n[1])) : 0;
+}
+
+template <int D>
+__device__ __forceinline__ int64_t cell_id(const Level& L, int x, int y, int z) {
+  return x + (int64_t)L.n[0] * (y + (int64_t)L.n[1] * z);
+}
+
+// Fine-level coefficients, right-hand side and permittivity from the phase fields.
+template <class L, class T>
+__global__ __launch_bounds__(kBlock) void k_pois_setup(Dims d, const uint8_t* __restrict__ flags,
+                                                        const T* __restrict__ phi, const T* __restrict__ rho,
+                                                        Phys<T> p, Volts<T> volts,
+                                                        T* __restrict__ cp, T* __restrict__ diag,
+                                                        T* __restrict__ b) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= d.N) return;
+  const int64_t N = d.N;
+  if (flags[node] != 0) {
+    for (int ax = 0; ax < L::D; ++ax) cp[(int64_t)ax * N + node] = T(0);
+    diag[node] = T(0);
+    b[node] = T(0);
+    return;
+  }
+  int nb[L::Q];
+  neighbours<L>(d, node, nb);
+  const T ex = p.eps[0] * phi[node] + p.eps[1] * phi[N + node] + p.eps[2] * phi[2 * N + node];
+  T dg = 0, rhs = rho ? rho[node] : T(0);
+#pragma unroll
+  for (int ax = 0; ax < L::D; ++ax) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int q = k == 0 ? L::axp[ax] : L::axm[ax];
+      const int m = nb[q];
+      const uint8_t fm = flags[m];
+      T c = 0;
+      if (fm == 0) {
+        const T em = p.eps[0] * phi[m] + p.eps[1] * phi[N + m] + p.eps[2] * phi[2 * N + m];
+        c = T(0.5) * (ex + em);
+        dg += c;
+      } else if (fm == 1 || fm >= 3) {
+        const T cd = T(2) * ex;
+        dg += cd;
+        rhs += cd * (fm == 1 ? T(0) : volts.v[fm - 3]);
+      }
+      if (k == 0) cp[(int64_t)ax * N + node] = c;
+    }
+  }
+  diag[node] = dg;
+  b[node] = rhs;
+}
+
+// y = A x at one level (explicit coefficients), optionally with per-block FP64 partials of x.y
+template <int D, class T, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_spmv(Level L, const T* __restrict__ cp, const T* __restrict__ diag,
+                                                  const T* __restrict__ x, T* __restrict__ y,
+                                                  double* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[1] = {0.0};
+  if (i < L.N) {
+    const T dg = diag[i];
+    T r = 0;
+    if (dg != T(0)) {
+      int cx, cy, cz;
+      cell_xyz<D>(L, i, cx, cy, cz);
+      r = dg * x[i];
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        int xp = cx, yp = cy, zp = cz, xm = cx, ym = cy, zm = cz;
+        if (ax == 0) { xp = wrap(cx + 1, L.n[0]); xm = wrap(cx - 1, L.n[0]); }
+        if (ax == 1) { yp = wrap(cy + 1, L.n[1]); ym = wrap(cy - 1, L.n[1]); }
+        if (ax == 2) { zp = wrap(cz + 1, L.n[2]); zm = wrap(cz - 1, L.n[2]); }
+        const int64_t jp = cell_id<D>(L, xp, yp, zp), jm = cell_id<D>(L, xm, ym, zm);
+        r -= cp[(int64_t)ax * L.N + i] * x[jp] + cp[(int64_t)ax * L.N + jm] * x[jm];
+      }
+    }
+    y[i] = r;
+    if (DOT) acc[0] = (double)x[i] * (double)r;
+  }
+  if (DOT) block_reduce<1, false>(acc, part + blockIdx.x);
+}
+
+// Damped Jacobi sweep: z_out = z_in + w (r - A z_in)/diag  (z_in == nullptr: z_out = w r/diag)
+template <int D, class T>
+__global__ __launch_bounds__(kBlock) void k_jacobi(Level L, const T* __restrict__ cp, const T* __restrict__ diag,
+                                                    const T* __restrict__ r, const T* __restrict__ z_in,
+                                                    T* __restrict__ z_out, T omega) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.N) return;
+  const T dg = diag[i];
+  if (dg == T(0)) {
+    z_out[i] = T(0);
+    return;
+  }
+  if (!z_in) {
+    z_out[i] = omega * r[i] / dg;
+    return;
+  }
+  int cx, cy, cz;
+  cell_xyz<D>(L, i, cx, cy, cz);
+  T az = dg * z_in[i];
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    int xp = cx, yp = cy, zp = cz, xm = cx, ym = cy, zm = cz;
+    if (ax == 0) { xp = wrap(cx + 1, L.n[0]); xm = wrap(cx - 1, L.n[0]); }
+    if (ax == 1) { yp = wrap(cy + 1, L.n[1]); ym = wrap(cy - 1, L.n[1]); }
+    if (ax == 2) { zp = wrap(cz + 1, L.n[2]); zm = wrap(cz - 1, L.n[2]); }
+    const int64_t jp = cell_id<D>(L, xp, yp, zp), jm = cell_id<D>(L, xm, ym, zm);
+    az -= cp[(int64_t)ax * L.N + i] * z_in[jp] + cp[(int64_t)ax * L.N + jm] * z_in[jm];
+  }
+  z_out[i] = z_in[i] + omega * (r[i] - az) / dg;
+}
+
+// Restriction of the residual r - A z to the coarse level (sum over the children), fused:
+// each coarse cell recomputes the residual of its children.
+template <int D, class T>
+__global__ __launch_bounds__(kBlock) void k_restrict_resid(Level Lf, const T* __restrict__ cp,
+                                                            const T* __restrict__ diag, const T* __restrict__ r,
+                                                            const T* __restrict__ z, Level Lc,
+                                                            T* __restrict__ rc) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= Lc.N) return;
+  int X, Y, Z;
+  cell_xyz<D>(Lc, I, X, Y, Z);
+  T acc = 0;
+  for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int cx = 2 * X + dx, cy = 2 * Y + dy, cz = 2 * Z + dz;
+        if (cx >= Lf.n[0] || cy >= Lf.n[1] || (D == 3 && cz >= Lf.n[2])) continue;
+        const int64_t i = cell_id<D>(Lf, cx, cy, cz);
+        const T dg = diag[i];
+        if (dg == T(0)) continue;
+        T az = dg * z[i];
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+          int xp = cx, yp = cy, zp = cz, xm = cx, ym = cy, zm = cz;
+          if (ax == 0) { xp = wrap(cx + 1, Lf.n[0]); xm = wrap(cx - 1, Lf.n[0]); }
+          if (ax == 1) { yp = wrap(cy + 1, Lf.n[1]); ym = wrap(cy - 1, Lf.n[1]); }
+          if (ax == 2) { zp = wrap(cz + 1, Lf.n[2]); zm = wrap(cz - 1, Lf.n[2]); }
+          const int64_t jp = cell_id<D>(Lf, xp, yp, zp), jm = cell_id<D>(Lf, xm, ym, zm);
+          az -= cp[(int64_t)ax * Lf.N + i] * z[jp] + cp[(int64_t)ax * Lf.N + jm] * z[jm];
+        }
+        acc += r[i] - az;
+      }
+  rc[I] = acc;
+}
+
+// z_fine += scale * z_coarse[parent] on active fine cells
+template <int D, class T>
+__global__ __launch_bounds__(kBlock) void k_prolong(Level Lf, const T* __restrict__ diag, T* __restrict__ z,
+                                                     Level Lc, const T* __restrict__ zc, T scale) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Lf.N) return;
+  if (diag[i] == T(0)) return;
+  int cx, cy, cz;
+  cell_xyz<D>(Lf, i, cx, cy, cz);
+  z[i] += scale * zc[cell_id<D>(Lc, cx >> 1, cy >> 1, cz >> 1)];
+}
+
+// Galerkin coarse operator of piecewise-constant aggregation: diag_I = sum of the
+// children's diagonals minus twice the faces inside I; cp_I(a) = sum of the fine faces
+// from I to I + e_a.
+template <int D, class T>
+__global__ __launch_bounds__(kBlock) void k_coarsen(Level Lf, const T* __restrict__ cpf,
+                                                     const T* __restrict__ diagf, Level Lc,
+                                                     T* __restrict__ cpc, T* __restrict__ diagc) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= Lc.N) return;
+  int X, Y, Z;
+  cell_xyz<D>(Lc, I, X, Y, Z);
+  T dg = 0;
+  T c[3] = {0, 0, 0};
+  for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int cx = 2 * X + dx, cy = 2 * Y + dy, cz = 2 * Z + dz;
+        if (cx >= Lf.n[0] || cy >= Lf.n[1] || (D == 3 && cz >= Lf.n[2])) continue;
+        const int64_t i = cell_id<D>(Lf, cx, cy, cz);
+        dg += diagf[i];
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+          const T f = cpf[(int64_t)ax * Lf.N + i];
+          int jx = cx, jy = cy, jz = cz;
+          if (ax == 0) jx = wrap(cx + 1, Lf.n[0]);
+          if (ax == 1) jy = wrap(cy + 1, Lf.n[1]);
+          if (ax == 2) jz = wrap(cz + 1, Lf.n[2]);
+          const bool inside = (jx >> 1) == X && (jy >> 1) == Y && (jz >> 1) == Z;
+          if (inside)
+            dg -= T(2) * f;
+          else
+            c[ax] += f;
+        }
+      }
+  diagc[I] = dg;
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) cpc[(int64_t)ax * Lc.N + I] = c[ax];
+}
+
+// Coarsest level: dense inverse by Gauss-Jordan (SPD, no pivoting) in one block, FP64.
+// Inactive cells (diag 0) become identity rows.  n <= kCoarseMax.
+constexpr int kCoarseMax = 48;
+template <int D, class T>
+__global__ __launch_bounds__(kBlock) void k_coarse_invert(Level L, const T* __restrict__ cp,
+                                                           const T* __restrict__ diag, double* __restrict__ inv) {
+  __shared__ double A[kCoarseMax][kCoarseMax + 1];
+  __shared__ double B[kCoarseMax][kCoarseMax + 1];
+  const int n = (int)L.N;
+  for (int k = threadIdx.x; k < n * n; k += blockDim.x) {
+    const int r = k / n, c = k % n;
+    A[r][c] = 0.0;
+    B[r][c] = r == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < n; ++i) {
+      const double dg = diag[i];
+      if (dg == 0.0) {
+        A[i][i] = 1.0;
+        continue;
+      }
+      A[i][i] += dg;
+      int cx, cy, cz;
+      cell_xyz<D>(L, i, cx, cy, cz);
+      for (int ax = 0; ax < D; ++ax) {
+        int xp = cx, yp = cy, zp = cz;
+        if (ax == 0) xp = wrap(cx + 1, L.n[0]);
+        if (ax == 1) yp = wrap(cy + 1, L.n[1]);
+        if (ax == 2) zp = wrap(cz + 1, L.n[2]);
+        const int j = (int)cell_id<D>(L, xp, yp, zp);
+        const double c = cp[(int64_t)ax * L.N + i];
+        if (c != 0.0 && j != i) {
+          A[i][j] -= c;
+          A[j][i] -= c;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double piv = A[k][k];
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      A[k][c] /= piv;
+      B[k][c] /= piv;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int r = e / n, c = e % n;
+      if (r == k) continue;
+      const double f = A[r][k];
+      if (c != k) A[r][c] -= f * A[k][c];
+      B[r][c] -= f * B[k][c];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += blockDim.x)
+      if (r != k) A[r][k] = 0.0;
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < n * n; k += blockDim.x) inv[k] = B[k / n][k % n];
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_coarse_apply(int n, const double* __restrict__ inv,
+                                                          const T* __restrict__ diag, const T* __restrict__ r,
+                                                          T* __restrict__ z) {
+  const int i = threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < n; ++j) acc += inv[i * n + j] * (double)r[j];
+  z[i] = diag[i] == T(0) ? T(0) : (T)acc;
+}
+
+// CG scalars, FP64, on the device.  s[0] = rz, s[1] = alpha, s[2] = beta.
+__global__ void k_cg_alpha(const double* __restrict__ pq, double* __restrict__ s) {
+  const double d = pq[0];
+  s[1] = d != 0.0 ? s[0] / d : 0.0;
+}
+__global__ void k_cg_beta(const double* __restrict__ rz_new, double* __restrict__ s) {
+  const double n = rz_new[0];
+  s[2] = s[0] != 0.0 ? n / s[0] : 0.0;
+  s[0] = n;
+}
+__global__ void k_cg_init_rz(const double* __restrict__ rz, double* __restrict__ s) { s[0] = rz[0]; }
+
+// x += alpha p, r -= alpha q
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t N, const double* __restrict__ s,
+                                                       const T* __restrict__ p, const T* __restrict__ q,
+                                                       T* __restrict__ x, T* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const T al = (T)s[1];
+  x[i] += al * p[i];
+  r[i] -= al * q[i];
+}
+
+// p = z + beta p  (beta from s[2]; first == true: p = z)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_cg_dir(int64_t N, const double* __restrict__ s,
+                                                    const T* __restrict__ z, T* __restrict__ p, int first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  p[i] = first ? z[i] : z[i] + (T)s[2] * p[i];
+}
+
+// per-block FP64 partial of a.b
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dot(int64_t N, const T* __restrict__ a, const T* __restrict__ b,
+                                                 double* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[1] = {i < N ? (double)a[i] * (double)b[i] : 0.0};
+  block_reduce<1, false>(v, part + blockIdx.x);
+}
+
+// FP64 true residual: r = b - A x (stored in T), per-block partials of max|r| and max|b|
+template <int D, class T>
+__global__ __launch_bounds__(kBlock) void k_true_resid(Level L, const T* __restrict__ cp, const T* __restrict__ diag,
+                                                        const T* __restrict__ b, const T* __restrict__ x,
+                                                        T* __restrict__ r, double* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double m[2] = {0.0, 0.0};
+  if (i < L.N) {
+    const double dg = diag[i];
+    double res = 0.0;
+    if (dg != 0.0) {
+      int cx, cy, cz;
+      cell_xyz<D>(L, i, cx, cy, cz);
+      double ax_ = dg * (double)x[i];
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        int xp = cx, yp = cy, zp = cz, xm = cx, ym = cy, zm = cz;
+        if (ax == 0) { xp = wrap(cx + 1, L.n[0]); xm = wrap(cx - 1, L.n[0]); }
+        if (ax == 1) { yp = wrap(cy + 1, L.n[1]); ym = wrap(cy - 1, L.n[1]); }
+        if (ax == 2) { zp = wrap(cz + 1, L.n[2]); zm = wrap(cz - 1, L.n[2]); }
+        const int64_t jp = cell_id<D>(L, xp, yp, zp), jm = cell_id<D>(L, xm, ym, zm);
+        ax_ -= (double)cp[(int64_t)ax * L.N + i] * (double)x[jp] + (double)cp[(int64_t)ax * L.N + jm] * (double)x[jm];
+      }
+      res = (double)b[i] - ax_;
+      m[1] = fabs((double)b[i]);
+    }
+    r[i] = (T)res;
+    m[0] = fabs(res);
+  }
+  block_reduce<2, true>(m, part + (int64_t)blockIdx.x * 2);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_zero(int64_t N, T* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) x[i] = T(0);
+}
+
+// T -> double copy (read-out)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_to_double(int64_t N, const T* __restrict__ a, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) out[i] = (double)a[i];
+}
+
+}  // namespace ehd

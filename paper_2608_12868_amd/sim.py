@@ -1,0 +1,150 @@
+"""Python face of libehdlb: a Simulation owns one library context.
+
+PyTorch provides the device workspace (one uint8 tensor) and the stream; every
+step of the method runs in the library's HIP kernels.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+def make_structs(dim, n, periodic, precision, params):
+    lat = L.Lattice()
+    lat.dim = int(dim)
+    for a in range(3):
+        lat.n[a] = int(n[a])
+        lat.periodic[a] = int(periodic[a])
+    lat.precision = L.FP64 if precision in ("fp64", L.FP64) else L.FP32_DEV
+    p = L.Params()
+    for i in range(3):
+        p.tau_flow[i] = float(params["tau_flow"][i])
+        p.eps[i] = float(params["eps"][i])
+        p.cond[i] = float(params["cond"][i])
+        p.body_force[i] = float(params["body_force"][i])
+    for k in ("mobility", "width", "gamma12", "gamma13", "gamma23", "cos12", "cos13", "cos23",
+              "charge_diffusion", "poisson_tol"):
+        setattr(p, k, float(params[k]))
+    p.ehd = int(params["ehd"])
+    for k in range(L.MAX_ELECTRODES):
+        p.electrode_volts[k] = float(params["electrode_volts"][k])
+    p.poisson_max_iter = int(params["poisson_max_iter"])
+    p.poisson_check_every = int(params["poisson_check_every"])
+    return lat, p
+
+
+class Context:
+    """A library context without device memory: validation and host-side tables only."""
+
+    def __init__(self, dim, n, periodic, precision, params):
+        self.dim, self.n = int(dim), tuple(int(v) for v in n)
+        self.N = self.n[0] * self.n[1] * self.n[2]
+        self.precision = precision
+        self.params = dict(params)
+        lat, p = make_structs(dim, n, periodic, precision, params)
+        h = C.c_void_p()
+        st = L.lib().ehdlb_create(C.byref(lat), C.byref(p), C.byref(h))
+        if st != L.OK:
+            raise L.EhdlbError(st, "ehdlb_create rejected the lattice or parameters")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            L.lib().ehdlb_destroy(h)
+            self.h = None
+
+    def _chk(self, st):
+        return L.check(self.h, st)
+
+    def set_geometry(self, flags):
+        self._flags = np.ascontiguousarray(flags, dtype=np.uint8).reshape(-1)
+        if self._flags.size != self.N:
+            raise ValueError("flags must have N entries")
+        self._chk(L.lib().ehdlb_set_geometry(self.h, self._flags.ctypes.data))
+
+    def wetting_links(self):
+        n = L.lib().ehdlb_wetting_links(self.h, None, None, 0)
+        if n < 0:
+            self._chk(int(n))
+        nodes = np.zeros(n, np.int64)
+        dirs = np.zeros(n, np.int32)
+        L.lib().ehdlb_wetting_links(self.h, nodes.ctypes.data, dirs.ctypes.data, n)
+        return nodes, dirs
+
+    @property
+    def workspace_bytes(self):
+        return int(L.lib().ehdlb_workspace_bytes(self.h))
+
+
+class Simulation(Context):
+    """A bound context: device workspace from torch, work on torch's current stream."""
+
+    def __init__(self, dim, n, periodic, precision, params, flags, phi, device="cuda"):
+        import torch
+        super().__init__(dim, n, periodic, precision, params)
+        self.torch = torch
+        self.device = torch.device(device)
+        nbytes = self.workspace_bytes
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self.stream = torch.cuda.current_stream(self.device)
+        self._chk(L.lib().ehdlb_bind(self.h, C.c_void_p(base + off), nbytes, C.c_void_p(self.stream.cuda_stream)))
+        self.set_geometry(flags)
+        self.set_phase(phi)
+
+    @classmethod
+    def from_case(cls, case, precision=None, **over):
+        params = dict(case.params)
+        params.update(over)
+        return cls(case.dim, case.n, case.periodic, precision or case.precision, params, case.flags, case.phi)
+
+    def set_phase(self, phi):
+        a = np.ascontiguousarray(phi, dtype=np.float64).reshape(3, self.N)
+        self._chk(L.lib().ehdlb_set_phase(self.h, a.ctypes.data))
+
+    def set_charge(self, rho):
+        a = np.ascontiguousarray(rho, dtype=np.float64).reshape(self.N)
+        self._chk(L.lib().ehdlb_set_charge(self.h, a.ctypes.data))
+
+    def set_schedule(self, electrode, volts, t_total):
+        v = np.ascontiguousarray(volts, dtype=np.float64)
+        self._chk(L.lib().ehdlb_set_schedule(self.h, int(electrode), int(v.size), v.ctypes.data, int(t_total)))
+
+    def step(self, n=1):
+        self._chk(L.lib().ehdlb_step(self.h, int(n)))
+
+    def field(self, name):
+        fid = L.FIELDS[name]
+        size = int(L.lib().ehdlb_num_populations(self.h)) if name == "pops" else self.N
+        out = np.empty(size, np.float64)
+        self._chk(L.lib().ehdlb_read_field(self.h, fid, out.ctypes.data))
+        return out
+
+    def observables(self, strict=True):
+        o = L.Obs()
+        st = L.lib().ehdlb_observables(self.h, C.byref(o))
+        if strict:
+            self._chk(st)
+        return dict(step=o.step, mass=np.array(o.mass[:]), centroid=np.array(o.centroid[:]),
+                    velocity=np.array(o.velocity[:]), total_charge=o.total_charge,
+                    sum_phi_drift=o.sum_phi_drift, poisson_residual=o.poisson_residual,
+                    poisson_iters=o.poisson_iters, flags=o.flags, status=st)
+
+    @property
+    def state_bytes(self):
+        return int(L.lib().ehdlb_state_bytes(self.h))
+
+    def save_state(self, dst=None):
+        torch = self.torch
+        if dst is None:
+            dst = torch.empty(self.state_bytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = dst.data_ptr() + ((-dst.data_ptr()) % 256)
+        self._chk(L.lib().ehdlb_save_state(self.h, C.c_void_p(ptr)))
+        return dst
+
+    def load_state(self, src):
+        ptr = src.data_ptr() + ((-src.data_ptr()) % 256)
+        self._chk(L.lib().ehdlb_load_state(self.h, C.c_void_p(ptr)))

@@ -1,0 +1,131 @@
+"""HIP path against the FP64 oracle, element by element, through the C ABI.
+
+Tolerances: FP64 path <= 1e-10 relative (max-norm over the field, per field);
+FP32-deviation path <= 1e-4 relative on the droplet centroid trajectory.
+"""
+import numpy as np
+import pytest
+
+from inputs import make_case
+
+import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+def _gpu(case, precision=None, **over):
+    from paper_2608_12868_amd import Simulation
+    gu.require_gpu()
+    return Simulation.from_case(case, precision=precision, **over)
+
+
+def _compare(sim, o, s, aux, tol, fields=None):
+    ref = gu.oracle_fields(o, s, aux)
+    errs = {}
+    for k, v in ref.items():
+        if fields and k not in fields:
+            continue
+        errs[k] = gu.rel_err(sim.field(k), v)
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, bad
+    return errs
+
+
+@pytest.mark.parametrize("name,steps", [("c1s", 300), ("c2s", 150), ("c4s", 150)])
+def test_fp64_parity_2d(name, steps):
+    case = make_case(name, precision="fp64")
+    print("case", name, case.n, "steps", steps, flush=True)
+    sim = _gpu(case)
+    sim.step(steps)
+    o, s, aux = gu.oracle_run(case, steps)
+    _compare(sim, o, s, aux, FP64_TOL)
+    pops = sim.field("pops")
+    assert gu.rel_err(pops, gu.oracle_pops(o, s)) <= FP64_TOL
+
+
+def test_fp64_parity_config1_full():
+    """The 128x64 flat-film configuration at its full 1000 steps."""
+    case = make_case("c1")
+    sim = _gpu(case)
+    sim.step(case.steps)
+    o, s, aux = gu.oracle_run(case, case.steps)
+    _compare(sim, o, s, aux, FP64_TOL)
+    ob = sim.observables()
+    ref = o.observables(s)
+    assert np.allclose(ob["mass"], ref["mass"].numpy(), rtol=1e-12, atol=0)
+    assert np.allclose(ob["centroid"], ref["centroid"].numpy(), rtol=1e-12, atol=1e-12)
+    assert np.allclose(ob["velocity"], ref["velocity"].numpy(), rtol=1e-9, atol=1e-15)
+
+
+def test_fp64_parity_3d():
+    case = make_case("c3s", precision="fp64")
+    sim = _gpu(case)
+    steps = 12
+    sim.step(steps)
+    o, s, aux = gu.oracle_run(case, steps)
+    _compare(sim, o, s, aux, FP64_TOL)
+
+
+def test_fp64_parity_variable_viscosity_and_schedule():
+    """Per-phase tau (second-order moments away from equilibrium) and a voltage schedule."""
+    case = make_case("c4s", precision="fp64")
+    over = dict(tau_flow=(0.8, 1.3, 0.65))
+    sim = _gpu(case, **over)
+    sim.set_schedule(0, case.schedule, case.t_total)
+    steps = 120
+    sim.step(steps)
+    nseg = len(case.schedule)
+
+    def volts(t):
+        import torch
+        seg = min(t * nseg // case.t_total, nseg - 1)
+        return torch.tensor([case.schedule[seg], 0, 0, 0], dtype=torch.float64)
+    o, s, aux = gu.oracle_run(case, steps, params=over, volts_fn=volts)
+    _compare(sim, o, s, aux, FP64_TOL)
+
+
+def test_fp32_centroid_trajectory():
+    case = make_case("c2s")
+    sim = _gpu(case, precision="fp32", poisson_tol=1e-6)
+    from oracle import Oracle
+    o = Oracle(case.dim, case.n, case.periodic, case.params, case.flags)
+    s = o.init_state(case.phi)
+    x0 = o.observables(s)["centroid"].numpy()
+    worst = 0.0
+    for k in range(6):
+        sim.step(50)
+        s, _ = o.run(s, 50)
+        xg = sim.observables()["centroid"]
+        xo = o.observables(s)["centroid"].numpy()
+        worst = max(worst, float(np.abs(xg[:2] - xo[:2]).max() / np.abs(xo[:2]).max()))
+    print("fp32 centroid rel err", worst, "displacement", xo - x0, flush=True)
+    assert worst <= 1e-4
+
+
+def test_determinism_and_checkpoint_replay():
+    case = make_case("c2s", precision="fp64")
+    a = _gpu(case)
+    a.step(20)
+    blob = a.save_state()
+    a.step(30)
+    pa = a.field("pops")
+    b = _gpu(case)
+    b.step(50)
+    assert np.array_equal(pa, b.field("pops")), "two runs differ"
+    b.load_state(blob)
+    b.step(30)
+    assert np.array_equal(pa, b.field("pops")), "replay from checkpoint differs"
+    assert b.observables()["step"] == 50
+
+
+def test_mass_conservation_config2_full():
+    case = make_case("c2")
+    sim = _gpu(case)
+    m0 = sim.observables()["mass"]
+    sim.step(200)
+    ob = sim.observables()
+    assert np.all(np.abs(ob["mass"] - m0) / m0 <= 1e-12)
+    assert ob["poisson_residual"] <= case.params["poisson_tol"]
