@@ -183,6 +183,22 @@ ehdlb_status ehdlb_load_state(ehdlb_ctx* ctx, const void* device_src);
  * cap entries and returns the total count (or a negative status). */
 int64_t ehdlb_wetting_links(const ehdlb_ctx* ctx, int64_t* nodes, int32_t* dirs, int64_t cap);
 
+/* Options of the potential solver: conjugate gradients preconditioned by one
+ * symmetric multigrid V-cycle (aggregation of 2 cells per axis, Galerkin coarse
+ * operators, dense solve on the coarsest level).  omega in (0, 2): damped-
+ * Jacobi weight; sweeps in [1, 8]: pre- and post-smoothing sweeps; overcorrect
+ * in (0, 4]: scale of the coarse-grid correction.  EINVAL outside the ranges. */
+ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* ctx, double omega, int32_t sweeps, double overcorrect);
+
+/* Optional timing of the step's three phases with HIP events recorded on the
+ * bound stream: [0] moments and wetting ghosts, [1] potential solve (setup,
+ * multigrid-preconditioned CG, residual checks), [2] fused collide-stream.
+ * set_timing(1) resets the accumulators (it creates events: needs a device);
+ * ehdlb_timing synchronises and returns the summed milliseconds per phase and
+ * the number of timed steps. */
+ehdlb_status ehdlb_set_timing(ehdlb_ctx* ctx, int32_t on);
+ehdlb_status ehdlb_timing(ehdlb_ctx* ctx, double* ms3, int64_t* steps);
+
 const char* ehdlb_last_error(const ehdlb_ctx* ctx);
 void ehdlb_destroy(ehdlb_ctx* ctx);
 

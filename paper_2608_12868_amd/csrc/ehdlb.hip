@@ -69,6 +69,16 @@ struct ehdlb_ctx {
   int64_t max_ghost = 0;
   int64_t nparts = 0;
   int64_t hdr[4]{};  // host staging of the state header (kept alive for async copies)
+  // potential-solver options (ehdlb_set_solver_options)
+  double mg_omega = 0.8;       // damped-Jacobi weight
+  int mg_nu = 2;               // pre- and post-smoothing sweeps
+  double mg_overcorrect = 2.0; // scale of the coarse-grid correction
+  // optional timing: one event per phase boundary per step (moments | potential | step)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  int64_t timed_steps = 0;
+  double acc_ms[3]{};
 
   template <class T>
   T* ptr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -261,8 +271,8 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout) {
     *zout = z;
     return EHDLB_OK;
   }
-  const T omega = T(0.8);
-  const int nu = 2;
+  const T omega = (T)c->mg_omega;
+  const int nu = c->mg_nu;
   T* z = c->ptr<T>(m.z);
   T* t = c->ptr<T>(m.t);
   hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nblocks(L.N)), dim3(kBlock), 0, s, L, cp, dg, r, (const T*)nullptr, z, omega);
@@ -277,7 +287,8 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout) {
   T* zc = nullptr;
   ehdlb_status st = vcycle<D, T>(c, lvl + 1, rc, &zc);
   if (st) return st;
-  hipLaunchKernelGGL((k_prolong<D, T>), dim3(nblocks(L.N)), dim3(kBlock), 0, s, L, dg, z, mc.L, (const T*)zc, T(1));
+  hipLaunchKernelGGL((k_prolong<D, T>), dim3(nblocks(L.N)), dim3(kBlock), 0, s, L, dg, z, mc.L, (const T*)zc,
+                     (T)c->mg_overcorrect);
   for (int k = 0; k < nu; ++k) {
     hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nblocks(L.N)), dim3(kBlock), 0, s, L, cp, dg, r, z, t, omega);
     std::swap(z, t);
@@ -384,6 +395,22 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
   return EHDLB_OK;
 }
 
+// ============================================================================ timing
+// Sum the elapsed times of the recorded event quadruples (synchronises on the last event).
+static ehdlb_status flush_timing(ehdlb_ctx* c) {
+  if (c->ev_used == 0) return EHDLB_OK;
+  HIPCHK(hipEventSynchronize(c->ev[c->ev_used - 1]));
+  for (size_t k = 0; k + 3 < c->ev_used; k += 4) {
+    for (int j = 0; j < 3; ++j) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, c->ev[k + j], c->ev[k + j + 1]));
+      c->acc_ms[j] += ms;
+    }
+  }
+  c->ev_used = 0;
+  return EHDLB_OK;
+}
+
 // ============================================================================ step
 template <class LT, class T, bool EHD>
 static ehdlb_status step_impl(ehdlb_ctx* c, int64_t n) {
@@ -402,16 +429,28 @@ static ehdlb_status step_impl(ehdlb_ctx* c, int64_t n) {
     T* rho = c->ptr<T>(c->off_rho[pi]);
     const T* pin = c->ptr<T>(c->off_pop[c->cur]);
     T* pout = c->ptr<T>(c->off_pop[1 - c->cur]);
+    hipEvent_t* ev = nullptr;
+    if (c->timing) {
+      if (c->ev_used + 4 > c->ev.size()) {
+        ehdlb_status st = flush_timing(c);
+        if (st) return st;
+      }
+      ev = &c->ev[c->ev_used];
+      c->ev_used += 4;
+      HIPCHK(hipEventRecord(ev[0], s));
+    }
     hipLaunchKernelGGL((k_moments<LT, T, EHD>), dim3(nblocks(N)), dim3(kBlock), 0, s, dm, flags, pin, phi, rho,
                        (T*)nullptr);
     if (G > 0)
       hipLaunchKernelGGL(k_ghosts<T>, dim3(nblocks(G)), dim3(kBlock), 0, s, N, G, c->ptr<int32_t>(c->off_gnode),
                          c->ptr<int32_t>(c->off_gsrc), c->ptr<T>(c->off_glen), phi, ph);
     LAUNCHCHK();
+    if (ev) HIPCHK(hipEventRecord(ev[1], s));
     if (EHD) {
       ehdlb_status st = potential_solve<LT, T>(c, phi, rho, v);
       if (st) return st;
     }
+    if (ev) HIPCHK(hipEventRecord(ev[2], s));
     StepArgs<T> a{};
     a.d = dm;
     a.flags = flags;
@@ -431,6 +470,10 @@ static ehdlb_status step_impl(ehdlb_ctx* c, int64_t n) {
     a.dt_on = t == 0 ? T(0) : T(1);
     hipLaunchKernelGGL((k_step<LT, T, EHD>), dim3(nblocks(N)), dim3(kBlock), 0, s, a);
     LAUNCHCHK();
+    if (ev) {
+      HIPCHK(hipEventRecord(ev[3], s));
+      c->timed_steps++;
+    }
     c->cur = 1 - c->cur;
     c->t = t + 1;
   }
@@ -911,8 +954,45 @@ int64_t ehdlb_wetting_links(const ehdlb_ctx* c, int64_t* nodes, int32_t* dirs, i
   return G;
 }
 
+ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* c, double omega, int32_t sweeps, double overcorrect) {
+  if (!c) return EHDLB_EINVAL;
+  if (!(omega > 0.0 && omega < 2.0)) return fail(c, EHDLB_EINVAL, "Jacobi weight must lie in (0, 2)");
+  if (sweeps < 1 || sweeps > 8) return fail(c, EHDLB_EINVAL, "smoothing sweeps must lie in [1, 8]");
+  if (!(overcorrect > 0.0 && overcorrect <= 4.0)) return fail(c, EHDLB_EINVAL, "over-correction must lie in (0, 4]");
+  c->mg_omega = omega;
+  c->mg_nu = sweeps;
+  c->mg_overcorrect = overcorrect;
+  return EHDLB_OK;
+}
+
+ehdlb_status ehdlb_set_timing(ehdlb_ctx* c, int32_t on) {
+  if (!c) return EHDLB_EINVAL;
+  if (on && c->ev.empty()) {
+    c->ev.resize(4 * 256);
+    for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+  }
+  c->timing = on != 0;
+  c->ev_used = 0;
+  c->timed_steps = 0;
+  c->acc_ms[0] = c->acc_ms[1] = c->acc_ms[2] = 0.0;
+  return EHDLB_OK;
+}
+
+ehdlb_status ehdlb_timing(ehdlb_ctx* c, double* ms3, int64_t* steps) {
+  if (!c || !ms3) return EHDLB_EINVAL;
+  ehdlb_status st = flush_timing(c);
+  if (st) return st;
+  for (int j = 0; j < 3; ++j) ms3[j] = c->acc_ms[j];
+  if (steps) *steps = c->timed_steps;
+  return EHDLB_OK;
+}
+
 const char* ehdlb_last_error(const ehdlb_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-void ehdlb_destroy(ehdlb_ctx* c) { delete c; }
+void ehdlb_destroy(ehdlb_ctx* c) {
+  if (!c) return;
+  for (auto& e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
 
 }  // extern "C"

@@ -51,8 +51,9 @@ class Context:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
-            L.lib().ehdlb_destroy(h)
+        lib = L._LIB
+        if h and lib is not None:
+            lib.ehdlb_destroy(h)
             self.h = None
 
     def _chk(self, st):
@@ -132,6 +133,19 @@ class Simulation(Context):
                     velocity=np.array(o.velocity[:]), total_charge=o.total_charge,
                     sum_phi_drift=o.sum_phi_drift, poisson_residual=o.poisson_residual,
                     poisson_iters=o.poisson_iters, flags=o.flags, status=st)
+
+    def set_solver_options(self, omega=0.8, sweeps=2, overcorrect=2.0):
+        self._chk(L.lib().ehdlb_set_solver_options(self.h, float(omega), int(sweeps), float(overcorrect)))
+
+    def set_timing(self, on=True):
+        self._chk(L.lib().ehdlb_set_timing(self.h, int(bool(on))))
+
+    def timing(self):
+        """(ms_moments, ms_potential, ms_step) summed over the timed steps, and their count."""
+        ms = (C.c_double * 3)()
+        n = C.c_int64()
+        self._chk(L.lib().ehdlb_timing(self.h, ms, C.byref(n)))
+        return list(ms), int(n.value)
 
     @property
     def state_bytes(self):
