@@ -111,6 +111,7 @@ typedef struct {
   double total_charge;      /* sum of rho_e over fluid nodes                            */
   double sum_phi_drift;     /* max |Phi_1 + Phi_2 + Phi_3 - 1| over fluid nodes         */
   double poisson_residual;  /* last relative FP64 residual of the potential solve       */
+  double poisson_initial_residual; /* its relative residual before iterating (warm start) */
   int32_t poisson_iters;    /* iterations of the last potential solve                   */
   int32_t flags;            /* bit 0: non-finite seen; bit 1: solve hit its cap         */
 } ehdlb_obs;

@@ -42,6 +42,7 @@ class Obs(C.Structure):
         ("step", C.c_int64),
         ("mass", C.c_double * 3), ("centroid", C.c_double * 3), ("velocity", C.c_double * 3),
         ("total_charge", C.c_double), ("sum_phi_drift", C.c_double), ("poisson_residual", C.c_double),
+        ("poisson_initial_residual", C.c_double),
         ("poisson_iters", C.c_int32), ("flags", C.c_int32),
     ]
 

@@ -22,6 +22,9 @@ struct Status {
 
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+// grid of the grid-stride reduction kernels (fixed, so the reduction order is fixed)
+constexpr int kRedBlocks = 1024;
+int rblocks(int64_t n) { return std::min(nblocks(n), kRedBlocks); }
 
 struct MGLevel {
   Level L;
@@ -57,7 +60,7 @@ struct ehdlb_ctx {
   int64_t t = 0;
   int cur = 0;
   int sticky = 0;
-  double last_resid = 0.0;
+  double last_resid = 0.0, last_resid0 = 0.0;
   int last_iters = 0;
   // layout (byte offsets into ws)
   size_t off_pop[2]{}, off_phi[2]{}, off_rho[2]{}, off_u[2]{}, off_q[2]{}, off_pot = 0;
@@ -79,6 +82,7 @@ struct ehdlb_ctx {
   size_t ev_used = 0;
   int64_t timed_steps = 0;
   double acc_ms[3]{};
+  double hres[2]{};  // host copy of the residual check
 
   template <class T>
   T* ptr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -316,32 +320,21 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
   double* red = c->ptr<double>(c->off_red);
   double* cg = c->ptr<double>(c->off_cg);
   const Phys<T> ph = make_phys<T>(c->prm);
-  const int nb0 = nblocks(N);
+  const int nb0 = nblocks(N), rb0 = rblocks(N);
 
+  // fine-level operator and right-hand side; the last solution is the initial guess
   hipLaunchKernelGGL((k_pois_setup<LT, T>), dim3(nb0), dim3(kBlock), 0, s, dm, c->ptr<uint8_t>(c->off_flags), phi, rho,
                      ph, volts, cp0, dg0, b);
-  for (size_t l = 0; l + 1 < c->mg.size(); ++l) {
-    MGLevel& f = c->mg[l];
-    MGLevel& g = c->mg[l + 1];
-    hipLaunchKernelGGL((k_coarsen<D, T>), dim3(nblocks(g.L.N)), dim3(kBlock), 0, s, f.L, c->ptr<T>(f.cp),
-                       c->ptr<T>(f.diag), g.L, c->ptr<T>(g.cp), c->ptr<T>(g.diag));
-  }
-  {
-    MGLevel& g = c->mg.back();
-    hipLaunchKernelGGL((k_coarse_invert<D, T>), dim3(1), dim3(kBlock), 0, s, g.L, c->ptr<T>(g.cp), c->ptr<T>(g.diag),
-                       c->ptr<double>(c->off_inv));
-  }
   LAUNCHCHK();
 
   auto check = [&](double& rel, double& bmax) -> ehdlb_status {
-    hipLaunchKernelGGL((k_true_resid<D, T>), dim3(nb0), dim3(kBlock), 0, s, m0.L, cp0, dg0, b, x, r, part);
-    hipLaunchKernelGGL((k_final<2, true>), dim3(1), dim3(kBlock), 0, s, part, nb0, red);
+    hipLaunchKernelGGL((k_true_resid<D, T>), dim3(rb0), dim3(kBlock), 0, s, m0.L, cp0, dg0, b, x, r, part);
+    hipLaunchKernelGGL((k_final<2, true>), dim3(1), dim3(kBlock), 0, s, part, rb0, red);
     LAUNCHCHK();
-    double h[2];
-    HIPCHK(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->hres, red, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    bmax = h[1];
-    rel = bmax > 0.0 ? h[0] / bmax : 0.0;
+    bmax = c->hres[1];
+    rel = bmax > 0.0 ? c->hres[0] / bmax : 0.0;
     return EHDLB_OK;
   };
 
@@ -349,6 +342,7 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
   ehdlb_status st = check(rel, bmax);
   if (st) return st;
   c->last_iters = 0;
+  c->last_resid0 = rel;
   if (bmax == 0.0) {
     hipLaunchKernelGGL(k_zero<T>, dim3(nb0), dim3(kBlock), 0, s, N, x);
     c->last_resid = 0.0;
@@ -356,11 +350,23 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
   }
   const double tol = c->prm.poisson_tol;
   if (!(rel <= tol) && std::isfinite(rel)) {
+    // coarse hierarchy (Galerkin aggregation) and the dense coarsest inverse, only when iterating
+    for (size_t l = 0; l + 1 < c->mg.size(); ++l) {
+      MGLevel& f = c->mg[l];
+      MGLevel& g = c->mg[l + 1];
+      hipLaunchKernelGGL((k_coarsen<D, T>), dim3(nblocks(g.L.N)), dim3(kBlock), 0, s, f.L, c->ptr<T>(f.cp),
+                         c->ptr<T>(f.diag), g.L, c->ptr<T>(g.cp), c->ptr<T>(g.diag));
+    }
+    {
+      MGLevel& g = c->mg.back();
+      hipLaunchKernelGGL((k_coarse_invert<D, T>), dim3(1), dim3(kBlock), 0, s, g.L, c->ptr<T>(g.cp),
+                         c->ptr<T>(g.diag), c->ptr<double>(c->off_inv));
+    }
+    LAUNCHCHK();
     T* z = nullptr;
     if ((st = vcycle<D, T>(c, 0, r, &z))) return st;
-    hipLaunchKernelGGL(k_dot<T>, dim3(nb0), dim3(kBlock), 0, s, N, r, z, part);
-    hipLaunchKernelGGL((k_final<1, false>), dim3(1), dim3(kBlock), 0, s, part, nb0, red);
-    hipLaunchKernelGGL(k_cg_init_rz, dim3(1), dim3(1), 0, s, red, cg);
+    hipLaunchKernelGGL(k_dot<T>, dim3(rb0), dim3(kBlock), 0, s, N, r, z, part);
+    hipLaunchKernelGGL(k_final_beta, dim3(1), dim3(kBlock), 0, s, part, rb0, cg, 1);
     hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb0), dim3(kBlock), 0, s, N, cg, z, p, 1);
     LAUNCHCHK();
     int it = 0;
@@ -368,9 +374,8 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
     bool conv = false;
     while (it < maxit) {
       ++it;
-      hipLaunchKernelGGL((k_spmv<D, T, true>), dim3(nb0), dim3(kBlock), 0, s, m0.L, cp0, dg0, p, qv, part);
-      hipLaunchKernelGGL((k_final<1, false>), dim3(1), dim3(kBlock), 0, s, part, nb0, red);
-      hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1), 0, s, red, cg);
+      hipLaunchKernelGGL((k_spmv<D, T, true>), dim3(rb0), dim3(kBlock), 0, s, m0.L, cp0, dg0, p, qv, part);
+      hipLaunchKernelGGL(k_final_alpha, dim3(1), dim3(kBlock), 0, s, part, rb0, cg);
       hipLaunchKernelGGL(k_cg_update<T>, dim3(nb0), dim3(kBlock), 0, s, N, cg, p, qv, x, r);
       LAUNCHCHK();
       if (it % every == 0 || it == maxit) {
@@ -381,9 +386,8 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
         }
       }
       if ((st = vcycle<D, T>(c, 0, r, &z))) return st;
-      hipLaunchKernelGGL(k_dot<T>, dim3(nb0), dim3(kBlock), 0, s, N, r, z, part);
-      hipLaunchKernelGGL((k_final<1, false>), dim3(1), dim3(kBlock), 0, s, part, nb0, red);
-      hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1), 0, s, red, cg);
+      hipLaunchKernelGGL(k_dot<T>, dim3(rb0), dim3(kBlock), 0, s, N, r, z, part);
+      hipLaunchKernelGGL(k_final_beta, dim3(1), dim3(kBlock), 0, s, part, rb0, cg, 0);
       hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb0), dim3(kBlock), 0, s, N, cg, z, p, 0);
       LAUNCHCHK();
     }
@@ -522,6 +526,7 @@ static ehdlb_status observables_impl(ehdlb_ctx* c, ehdlb_obs* o) {
   o->total_charge = h[10];
   o->sum_phi_drift = h[kObs];
   o->poisson_residual = c->last_resid;
+  o->poisson_initial_residual = c->last_resid0;
   o->poisson_iters = c->last_iters;
   if (h[11] != 0.0 || !std::isfinite(h[0] + h[1] + h[2])) c->sticky |= 1;
   o->flags = c->sticky;

@@ -583,32 +583,36 @@ __global__ __launch_bounds__(kBlock) void k_pois_setup(Dims d, const uint8_t* __
   b[node] = rhs;
 }
 
-// y = A x at one level (explicit coefficients), optionally with per-block FP64 partials of x.y
+// y = A x at one level (explicit coefficients), optionally with per-block FP64 partials of x.y.
+// Grid-stride loop: the grid is capped so the partials stay few.
+template <int D, class T>
+__device__ __forceinline__ T apply_row(const Level& L, const T* __restrict__ cp, T dg, const T* __restrict__ x,
+                                       int64_t i) {
+  int cx, cy, cz;
+  cell_xyz<D>(L, i, cx, cy, cz);
+  T r = dg * x[i];
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    int xp = cx, yp = cy, zp = cz, xm = cx, ym = cy, zm = cz;
+    if (ax == 0) { xp = wrap(cx + 1, L.n[0]); xm = wrap(cx - 1, L.n[0]); }
+    if (ax == 1) { yp = wrap(cy + 1, L.n[1]); ym = wrap(cy - 1, L.n[1]); }
+    if (ax == 2) { zp = wrap(cz + 1, L.n[2]); zm = wrap(cz - 1, L.n[2]); }
+    const int64_t jp = cell_id<D>(L, xp, yp, zp), jm = cell_id<D>(L, xm, ym, zm);
+    r -= cp[(int64_t)ax * L.N + i] * x[jp] + cp[(int64_t)ax * L.N + jm] * x[jm];
+  }
+  return r;
+}
+
 template <int D, class T, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmv(Level L, const T* __restrict__ cp, const T* __restrict__ diag,
                                                   const T* __restrict__ x, T* __restrict__ y,
                                                   double* __restrict__ part) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double acc[1] = {0.0};
-  if (i < L.N) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
     const T dg = diag[i];
-    T r = 0;
-    if (dg != T(0)) {
-      int cx, cy, cz;
-      cell_xyz<D>(L, i, cx, cy, cz);
-      r = dg * x[i];
-#pragma unroll
-      for (int ax = 0; ax < D; ++ax) {
-        int xp = cx, yp = cy, zp = cz, xm = cx, ym = cy, zm = cz;
-        if (ax == 0) { xp = wrap(cx + 1, L.n[0]); xm = wrap(cx - 1, L.n[0]); }
-        if (ax == 1) { yp = wrap(cy + 1, L.n[1]); ym = wrap(cy - 1, L.n[1]); }
-        if (ax == 2) { zp = wrap(cz + 1, L.n[2]); zm = wrap(cz - 1, L.n[2]); }
-        const int64_t jp = cell_id<D>(L, xp, yp, zp), jm = cell_id<D>(L, xm, ym, zm);
-        r -= cp[(int64_t)ax * L.N + i] * x[jp] + cp[(int64_t)ax * L.N + jm] * x[jm];
-      }
-    }
+    const T r = dg != T(0) ? apply_row<D, T>(L, cp, dg, x, i) : T(0);
     y[i] = r;
-    if (DOT) acc[0] = (double)x[i] * (double)r;
+    if (DOT) acc[0] += (double)x[i] * (double)r;
   }
   if (DOT) block_reduce<1, false>(acc, part + blockIdx.x);
 }
@@ -804,18 +808,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_apply(int n, const double* __
   z[i] = diag[i] == T(0) ? T(0) : (T)acc;
 }
 
-// CG scalars, FP64, on the device.  s[0] = rz, s[1] = alpha, s[2] = beta.
-__global__ void k_cg_alpha(const double* __restrict__ pq, double* __restrict__ s) {
-  const double d = pq[0];
-  s[1] = d != 0.0 ? s[0] / d : 0.0;
-}
-__global__ void k_cg_beta(const double* __restrict__ rz_new, double* __restrict__ s) {
-  const double n = rz_new[0];
-  s[2] = s[0] != 0.0 ? n / s[0] : 0.0;
-  s[0] = n;
-}
-__global__ void k_cg_init_rz(const double* __restrict__ rz, double* __restrict__ s) { s[0] = rz[0]; }
-
+// CG scalars live on the device: s[0] = rz, s[1] = alpha, s[2] = beta.
 // x += alpha p, r -= alpha q
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t N, const double* __restrict__ s,
@@ -837,23 +830,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(int64_t N, const double* __re
   p[i] = first ? z[i] : z[i] + (T)s[2] * p[i];
 }
 
-// per-block FP64 partial of a.b
+// per-block FP64 partial of a.b (grid-stride)
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_dot(int64_t N, const T* __restrict__ a, const T* __restrict__ b,
                                                  double* __restrict__ part) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[1] = {i < N ? (double)a[i] * (double)b[i] : 0.0};
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    v[0] += (double)a[i] * (double)b[i];
   block_reduce<1, false>(v, part + blockIdx.x);
 }
 
-// FP64 true residual: r = b - A x (stored in T), per-block partials of max|r| and max|b|
+// FP64 true residual: r = b - A x (stored in T), per-block partials of max|r| and max|b| (grid-stride)
 template <int D, class T>
 __global__ __launch_bounds__(kBlock) void k_true_resid(Level L, const T* __restrict__ cp, const T* __restrict__ diag,
                                                         const T* __restrict__ b, const T* __restrict__ x,
                                                         T* __restrict__ r, double* __restrict__ part) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double m[2] = {0.0, 0.0};
-  if (i < L.N) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
     const double dg = diag[i];
     double res = 0.0;
     if (dg != 0.0) {
@@ -870,12 +863,39 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Level L, const T* __restr
         ax_ -= (double)cp[(int64_t)ax * L.N + i] * (double)x[jp] + (double)cp[(int64_t)ax * L.N + jm] * (double)x[jm];
       }
       res = (double)b[i] - ax_;
-      m[1] = fabs((double)b[i]);
+      m[1] = fmax(m[1], fabs((double)b[i]));
     }
     r[i] = (T)res;
-    m[0] = fabs(res);
+    m[0] = fmax(m[0], fabs(res));
   }
   block_reduce<2, true>(m, part + (int64_t)blockIdx.x * 2);
+}
+
+// Final reduction of p.q partials fused with alpha = rz / pq  (s[0] = rz, s[1] = alpha)
+__global__ __launch_bounds__(kBlock) void k_final_alpha(const double* __restrict__ part, int nblk,
+                                                         double* __restrict__ s) {
+  double v[1] = {0.0};
+  for (int b = threadIdx.x; b < nblk; b += kBlock) v[0] += part[b];
+  __shared__ double out[1];
+  block_reduce<1, false>(v, out);
+  __syncthreads();
+  if (threadIdx.x == 0) s[1] = out[0] != 0.0 ? s[0] / out[0] : 0.0;
+}
+
+// Final reduction of r.z partials fused with beta = rz_new / rz and rz <- rz_new (s[2] = beta).
+// init != 0: only rz <- rz_new.
+__global__ __launch_bounds__(kBlock) void k_final_beta(const double* __restrict__ part, int nblk,
+                                                        double* __restrict__ s, int init) {
+  double v[1] = {0.0};
+  for (int b = threadIdx.x; b < nblk; b += kBlock) v[0] += part[b];
+  __shared__ double out[1];
+  block_reduce<1, false>(v, out);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double n = out[0];
+    if (!init) s[2] = s[0] != 0.0 ? n / s[0] : 0.0;
+    s[0] = n;
+  }
 }
 
 template <class T>

@@ -132,6 +132,7 @@ class Simulation(Context):
         return dict(step=o.step, mass=np.array(o.mass[:]), centroid=np.array(o.centroid[:]),
                     velocity=np.array(o.velocity[:]), total_charge=o.total_charge,
                     sum_phi_drift=o.sum_phi_drift, poisson_residual=o.poisson_residual,
+                    poisson_initial_residual=o.poisson_initial_residual,
                     poisson_iters=o.poisson_iters, flags=o.flags, status=st)
 
     def set_solver_options(self, omega=0.8, sweeps=2, overcorrect=2.0):
