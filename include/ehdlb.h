@@ -184,6 +184,32 @@ ehdlb_status ehdlb_load_state(ehdlb_ctx* ctx, const void* device_src);
  * cap entries and returns the total count (or a negative status). */
 int64_t ehdlb_wetting_links(const ehdlb_ctx* ctx, int64_t* nodes, int32_t* dirs, int64_t cap);
 
+/* Adjoint (reverse mode) of the whole coupled step with respect to a piecewise-
+ * constant electrode-voltage schedule, for programmable droplet manipulation
+ * (the target application of the Results' electrode-switching protocols).
+ * Not in the paper: a training-system pattern (checkpoint and recompute).
+ *
+ * ehdlb_adjoint_workspace_bytes: device bytes for T steps with a checkpoint
+ *   every K steps (ceil(T/K) full states, one final state, K per-step records
+ *   of moments/potential/previous fields, the cotangent arrays).
+ * ehdlb_forward_checkpointed: runs T steps from the current state (step t0),
+ *   saving the checkpoints into the caller's device buffer (256-byte aligned,
+ *   at least the size above); afterwards the context is at step t0 + T.
+ * ehdlb_adjoint: given dL/d(centroid) and dL/d(velocity) of the final state
+ *   (the observables of ehdlb_observables), returns on the host dL/dV for
+ *   every segment of electrode k's schedule (n_seg doubles; one value if it
+ *   has none).  For each segment, last to first, it reloads the checkpoint,
+ *   recomputes K steps storing their records, and runs the adjoint steps
+ *   backwards; the potential solve is differentiated as exact (one solve with
+ *   the same symmetric matrix per step).  Deterministic; ends at the final
+ *   state again.  ESTATE if the state moved since the checkpointed forward,
+ *   EINVAL if the field is off. */
+size_t ehdlb_adjoint_workspace_bytes(const ehdlb_ctx* ctx, int64_t T, int32_t K);
+ehdlb_status ehdlb_forward_checkpointed(ehdlb_ctx* ctx, int64_t T, int32_t K, void* device_workspace,
+                                        size_t bytes);
+ehdlb_status ehdlb_adjoint(ehdlb_ctx* ctx, const double dL_dcentroid[3], const double dL_dvelocity[3],
+                           int32_t electrode, double* dL_dvolts);
+
 /* Options of the potential solver: conjugate gradients preconditioned by one
  * symmetric multigrid V-cycle (aggregation of 2 cells per axis, Galerkin coarse
  * operators, dense solve on the coarsest level).  omega in (0, 2): damped-

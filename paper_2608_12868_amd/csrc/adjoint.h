@@ -1,0 +1,744 @@
+// Hand-written discrete adjoint of one time step (reverse mode), gfx950.
+//
+// State of step t: populations P_t and the previous-step fields (Phi, u, rho_e, Q of step
+// t-1).  One forward step maps (P_t, prev_t, V(t)) to (P_t+1, prev_t+1); the adjoint maps the
+// cotangents of the outputs back to those of the inputs and accumulates dL/dV(t).  The
+// potential solve is treated as exact: its adjoint is one solve with the same symmetric
+// matrix.  Everything the collision needs from the populations is carried by a few moments
+// (MomLayout), which the forward recompute stores per step together with Phi (with wetting
+// ghosts), rho_e, the potential and the previous-step fields.
+//
+// Passes per step (all gathers, no atomics, fixed summation order):
+//   A   per fluid node: recompute the forward quantities, gather the streamed population
+//       cotangents (transpose of push streaming = pull), reverse the collision, the forces
+//       and the electric terms; write stencil cotangents (grad, lap, neighbour sigma and phi)
+//       and local ones
+//   B   per node: apply the transposed stencils as gathers -> lambda_Phi, lambda_phi
+//   G   per fluid node that is a wetting-link source: fold in the ghosts' cotangents
+//   S   solve A lambda_b = lambda_phi
+//   CD  per fluid node: permittivity/charge cotangents from lambda_b, then the population
+//       cotangents of step t
+#pragma once
+#include "kernels.h"
+
+namespace ehd {
+
+// per-step record of the recompute: [RecLayout::COUNT][N]
+template <class L>
+struct RecLayout {
+  static constexpr int D = L::D;
+  static constexpr int PHI = 0, RHO = 3, POT = 4, PHIP = 5, UP = 8, RHOP = 8 + D, QP = 9 + D, MOM = 10 + D;
+  static constexpr int COUNT = MOM + MomLayout<L>::COUNT;
+};
+
+template <class T>
+struct AdjArgs {
+  Dims d;
+  const uint8_t* flags;
+  const T* rec;        // record of step t
+  const T* lP_next;    // population cotangents of step t+1 [F][Q][N]
+  const T* lphip_next; // cotangents of the previous-step fields of step t+1
+  const T* lup_next;
+  const T* lrhop_next;
+  const T* lqp_next;
+  T* lphip;            // ... of step t (written by pass A)
+  T* lup;
+  T* lrhop;
+  T* lqp;
+  T* lgr;              // [3][D][N]
+  T* llap;             // [3][N]
+  T* lsig;             // [2D][N] cotangent of sigma at the axis neighbours
+  T* lpnb;             // [2D][N] cotangent of phi at the axis neighbours
+  T* lphi_loc;         // [3][N]
+  T* lpot_loc;         // [N]
+  T* lrho_loc;         // [N]
+  T* lmom;             // [MomLayout::COUNT][N]
+  double* vpart;       // per-block partials of dL/dV_k [nblocks][kMaxE]
+  Phys<T> p;
+  Volts<T> volts;
+  T dt_on;
+};
+
+// ----------------------------------------------------------------------------- pass A
+template <class L, class T, bool EHD>
+__global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
+  using ML = MomLayout<L>;
+  using RL = RecLayout<L>;
+  constexpr int Q = L::Q;
+  constexpr int D = L::D;
+  constexpr int P = ML::P;
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double vloc[kMaxE] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t N = a.d.N;
+  const bool active = node < N && a.flags[node] == 0;
+  if (active) {
+    const Phys<T>& p = a.p;
+    const T cs2 = T(1) / T(3);
+    const T dt = a.dt_on;
+    const T* rec = a.rec;
+    auto R = [&](int f, int64_t i) -> T { return rec[(int64_t)f * N + i]; };
+    int nb[Q];
+    neighbours<L>(a.d, node, nb);
+    uint32_t solid = 0;
+
+    // ---------------------------------------------------------- forward recompute
+    T pc[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pc[i] = R(RL::PHI + i, node);
+    T gr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    T lap[3] = {0, 0, 0};
+    T sig_ax[2 * D];
+    uint8_t fl_ax[2 * D];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+      const int m = nb[q];
+      const uint8_t fm = a.flags[m];
+      if (fm) solid |= 1u << q;
+      const T w = T(L::w36[q]) / T(36);
+      T v[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        v[i] = R(RL::PHI + i, m);
+        gr[i][0] += w * T(L::ex[q]) * v[i];
+        gr[i][1] += w * T(L::ey[q]) * v[i];
+        if (D == 3) gr[i][2] += w * T(L::ez[q]) * v[i];
+        lap[i] += w * (v[i] - pc[i]);
+      }
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        if (q == L::axp[ax] || q == L::axm[ax]) {
+          const int k = 2 * ax + (q == L::axp[ax] ? 0 : 1);
+          sig_ax[k] = p.cond[0] * v[0] + p.cond[1] * v[1] + p.cond[2] * v[2];
+          fl_ax[k] = fm;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gr[i][c] *= T(3);
+      lap[i] *= T(6);
+    }
+    const T triple = pc[0] * pc[1] * pc[2];
+    T mu[3];
+    T F[3] = {p.body[0], p.body[1], p.body[2]};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      mu[i] = T(24) * p.ups[i] / p.W * pc[i] * (pc[i] - T(1)) * (pc[i] - T(0.5)) -
+              T(24) * p.upsT / p.W * triple - T(0.75) * p.ups[i] * p.W * lap[i];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[c] += mu[i] * gr[i][c];
+    }
+    T E[3] = {0, 0, 0}, ge[3] = {0, 0, 0}, side[2 * D], pnb[2 * D], pd_ax[2 * D];
+    T phx = 0, sigx = 0, rq = 0, Qs = 0, e2 = 0;
+    if (EHD) {
+      phx = R(RL::POT, node);
+      sigx = p.cond[0] * pc[0] + p.cond[1] * pc[1] + p.cond[2] * pc[2];
+      rq = R(RL::RHO, node);
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int q = k == 0 ? L::axp[ax] : L::axm[ax];
+          const int kk = 2 * ax + k;
+          const uint8_t fm = fl_ax[kk];
+          pnb[kk] = T(0);
+          pd_ax[kk] = T(0);
+          if (fm == 0) {
+            pnb[kk] = R(RL::POT, nb[q]);
+            side[kk] = pnb[kk];
+            Qs += T(0.5) * (sigx + sig_ax[kk]) * (pnb[kk] - phx);
+          } else if (fm == 1 || fm >= 3) {
+            pd_ax[kk] = fm == 1 ? T(0) : a.volts.v[fm - 3];
+            side[kk] = T(2) * pd_ax[kk] - phx;
+            Qs += T(2) * sigx * (pd_ax[kk] - phx);
+          } else {
+            side[kk] = phx;
+          }
+        }
+        E[ax] = -T(0.5) * (side[2 * ax] - side[2 * ax + 1]);
+      }
+      e2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        ge[c] = p.eps[0] * gr[0][c] + p.eps[1] * gr[1][c] + p.eps[2] * gr[2][c];
+        F[c] += rq * E[c] - T(0.5) * e2 * ge[c];
+      }
+    }
+    const T drho = R(RL::MOM + ML::DRHO, node);
+    T j[3] = {0, 0, 0}, u[3], up[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      j[c] = R(RL::MOM + ML::J + c, node);
+      up[c] = R(RL::UP + c, node);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = j[c] + T(0.5) * F[c];
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    const T nu = p.nu[0] * pc[0] + p.nu[1] * pc[1] + p.nu[2] * pc[2];
+    const T s_nu = T(1) / (T(0.5) + T(3) * nu);
+    T Pi[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) Pi[k] = R(RL::MOM + ML::PI + k, node);
+
+    // ---------------------------------------------------------- cotangents of the outputs
+    // streamed populations: the value pushed from node along q landed on node + e_q (or on
+    // node's opposite slot when bounced back)
+    auto lout = [&](int fam, int q) -> T {
+      if ((solid >> q) & 1u) return a.lP_next[((int64_t)fam * Q + L::opp[q]) * N + node];
+      return a.lP_next[((int64_t)fam * Q + q) * N + nb[q]];
+    };
+    T lu[3] = {0, 0, 0}, lF[3] = {0, 0, 0}, lphi[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < D; ++c) lu[c] = a.lup_next[(int64_t)c * N + node];
+    T lQs = EHD ? a.lqp_next[node] : T(0);
+    T lrho = EHD ? a.lrhop_next[node] : T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) lphi[i] = a.lphip_next[(int64_t)i * N + node];
+    T lgr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    T lphip[3] = {0, 0, 0}, lup[3] = {0, 0, 0}, lrhop = 0, lqp = 0;
+    T* lm = a.lmom;
+
+    // ---------------------------------------------------------- charge (reverse)
+    if (EHD) {
+      const T rp = R(RL::RHOP, node);
+      T dru[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dru[c] = dt * (rq * u[c] - rp * up[c]);
+      T lsrc = 0, ldru[3] = {0, 0, 0}, lJe[3] = {0, 0, 0};
+      const T om = T(1) - p.s_e;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
+        const T w = T(L::w36[q]) / T(36);
+        const T lo = lout(4, q);
+        const T eu = T(ix) * u[0] + T(iy) * u[1] + T(iz) * u[2];
+        lsrc += lo * w;
+        lrho += lo * w * (T(1) + T(3) * eu);
+        lu[0] += lo * w * rq * T(3) * T(ix);
+        lu[1] += lo * w * rq * T(3) * T(iy);
+        lu[2] += lo * w * rq * T(3) * T(iz);
+        ldru[0] += lo * T(1.5) * w * T(ix);
+        ldru[1] += lo * T(1.5) * w * T(iy);
+        ldru[2] += lo * T(1.5) * w * T(iz);
+        if (ix * ix + iy * iy + iz * iz == 1) {
+          lJe[0] += lo * T(0.5) * om * T(ix);
+          lJe[1] += lo * T(0.5) * om * T(iy);
+          lJe[2] += lo * T(0.5) * om * T(iz);
+        }
+      }
+      // Je = jh - rho u + dru/2
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        ldru[c] += T(0.5) * lJe[c];
+        lrho -= lJe[c] * u[c];
+        lu[c] -= rq * lJe[c];
+      }
+#pragma unroll
+      for (int c = 0; c < D; ++c) lm[(int64_t)(ML::JH + c) * N + node] = lJe[c];
+      // dru = dt (rho u - rho_p u_p)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        lrho += dt * ldru[c] * u[c];
+        lu[c] += dt * rq * ldru[c];
+        lrhop -= dt * ldru[c] * up[c];
+        lup[c] -= dt * rp * ldru[c];
+      }
+      // src = Qs + dt (Qs - Qp)/2
+      lQs += lsrc * (T(1) + T(0.5) * dt);
+      lqp -= T(0.5) * dt * lsrc;
+    }
+
+    // ---------------------------------------------------------- phase fields (reverse)
+    {
+      T nrm[3][3], amag[3], msz[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T m2 = gr[i][0] * gr[i][0] + gr[i][1] * gr[i][1] + gr[i][2] * gr[i][2];
+        msz[i] = sqrt(m2 + T(1e-24));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nrm[i][c] = gr[i][c] / msz[i];
+        amag[i] = T(4) / p.W * fabs(pc[i] * (T(1) - pc[i]));
+      }
+      T tot[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) tot[c] = amag[0] * nrm[0][c] + amag[1] * nrm[1][c] + amag[2] * nrm[2][c];
+      T den = pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2];
+      if (!(den > T(0))) den = T(1);
+      const T om = T(1) - p.s_phi;
+      T lFphi[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T php = R(RL::PHIP + i, node);
+        T lG[3] = {0, 0, 0}, lJ[3] = {0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
+          const T w = T(L::w36[q]) / T(36);
+          const T lo = lout(1 + i, q);
+          const T eu = T(ix) * u[0] + T(iy) * u[1] + T(iz) * u[2];
+          lphi[i] += lo * w * (T(1) + T(3) * eu);
+          lu[0] += lo * w * pc[i] * T(3) * T(ix);
+          lu[1] += lo * w * pc[i] * T(3) * T(iy);
+          lu[2] += lo * w * pc[i] * T(3) * T(iz);
+          lG[0] += lo * T(1.5) * w * T(ix);
+          lG[1] += lo * T(1.5) * w * T(iy);
+          lG[2] += lo * T(1.5) * w * T(iz);
+          if (ix * ix + iy * iy + iz * iz == 1) {
+            lJ[0] += lo * T(0.5) * om * T(ix);
+            lJ[1] += lo * T(0.5) * om * T(iy);
+            lJ[2] += lo * T(0.5) * om * T(iz);
+          }
+        }
+        // J = jf - Phi u + G/2
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          lG[c] += T(0.5) * lJ[c];
+          lphi[i] -= lJ[c] * u[c];
+          lu[c] -= pc[i] * lJ[c];
+        }
+#pragma unroll
+        for (int c = 0; c < D; ++c) lm[(int64_t)(ML::JF + D * i + c) * N + node] = lJ[c];
+        // G = cs2 F_Phi + dt (Phi u - Phi_p u_p)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          lFphi[i][c] = cs2 * lG[c];
+          lphi[i] += dt * lG[c] * u[c];
+          lu[c] += dt * pc[i] * lG[c];
+          lphip[i] -= dt * lG[c] * up[c];
+          lup[c] -= dt * php * lG[c];
+        }
+      }
+      // F_Phi_i = a_i n_i - share_i tot,  tot = sum_j a_j n_j,  share_i = Phi_i^2 / den
+      T ltot[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        ltot[c] = -(pc[0] * pc[0] * lFphi[0][c] + pc[1] * pc[1] * lFphi[1][c] + pc[2] * pc[2] * lFphi[2][c]) / den;
+      T lden = 0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T lshare = -(lFphi[i][0] * tot[0] + lFphi[i][1] * tot[1] + lFphi[i][2] * tot[2]);
+        lphi[i] += lshare * T(2) * pc[i] / den;
+        lden -= lshare * pc[i] * pc[i] / (den * den);
+        T ln[3], la = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T g = lFphi[i][c] + ltot[c];
+          ln[c] = amag[i] * g;
+          la += nrm[i][c] * g;
+        }
+        const T s = pc[i] * (T(1) - pc[i]);
+        const T sg = s > T(0) ? T(1) : (s < T(0) ? T(-1) : T(0));
+        lphi[i] += la * T(4) / p.W * sg * (T(1) - T(2) * pc[i]);
+        const T nl = nrm[i][0] * ln[0] + nrm[i][1] * ln[1] + nrm[i][2] * ln[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lgr[i][c] += (ln[c] - nrm[i][c] * nl) / msz[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) lphi[i] += T(2) * pc[i] * lden;
+    }
+
+    // ---------------------------------------------------------- flow (reverse)
+    {
+      T C[6] = {0, 0, 0, 0, 0, 0};  // C_k = sum_q lambda_g*_q P_k[q]  (xx yy zz xy xz yz)
+      T lg[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
+        const T lo = lout(0, q);
+        lg[q] = lo;
+        const int l2 = ix * ix + iy * iy + iz * iz;
+        if (l2 == 0) {
+          C[0] -= lo;
+          C[1] -= lo;
+          C[2] -= lo;
+        } else if (l2 == 1) {
+          if (ix) C[0] += T(0.5) * lo;
+          if (iy) C[1] += T(0.5) * lo;
+          if (iz) C[2] += T(0.5) * lo;
+        } else {
+          if (iz == 0) C[3] += T(0.25) * T(ix * iy) * lo;
+          else if (iy == 0) C[4] += T(0.25) * T(ix * iz) * lo;
+          else C[5] += T(0.25) * T(iy * iz) * lo;
+        }
+      }
+      // Pi layout: 2D (xx, yy, xy); 3D (xx, yy, zz, xy, xz, yz)
+      T Ck[6], Pk[6];
+      if (D == 2) {
+        Ck[0] = C[0]; Ck[1] = C[1]; Ck[2] = C[3];
+        Pk[0] = Pi[0]; Pk[1] = Pi[1]; Pk[2] = Pi[P - 1];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          Ck[k] = C[k];
+          Pk[k] = Pi[k < P ? k : 0];
+        }
+      }
+      const T omn = T(1) - s_nu;
+      T ls = 0;
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        lm[(int64_t)(ML::PI + k) * N + node] = omn * Ck[k];
+        ls -= Pk[k] * Ck[k];
+      }
+      // lambda_d_q = sum_k m_k(e_q) lambda_Pi_k
+      T ldrho = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
+        const T exq = T(ix), eyq = T(iy), ezq = T(iz);
+        T ld;
+        if (D == 2) {
+          ld = omn * (exq * exq * Ck[0] + eyq * eyq * Ck[1] + exq * eyq * Ck[2]);
+        } else {
+          ld = omn * (exq * exq * Ck[0] + eyq * eyq * Ck[1] + ezq * ezq * Ck[2] + exq * eyq * Ck[3] +
+                      exq * ezq * Ck[4] + eyq * ezq * Ck[5]);
+        }
+        const T w = T(L::w36[q]) / T(36);
+        const T lgeq = lg[q] - ld;
+        const T lFq = T(0.5) * (lg[q] + ld);
+        const T eu = exq * u[0] + eyq * u[1] + ezq * u[2];
+        const T eF = exq * F[0] + eyq * F[1] + ezq * F[2];
+        ldrho += lgeq * w;
+        const T e3[3] = {exq, eyq, ezq};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          lu[c] += lgeq * w * (T(3) * e3[c] + T(9) * eu * e3[c] - T(3) * u[c]);
+          lF[c] += lFq * w * (T(3) * (e3[c] - u[c]) + T(9) * eu * e3[c]);
+          lu[c] += lFq * w * (-T(3) * F[c] + T(9) * eF * e3[c]);
+        }
+      }
+      (void)uu;
+      (void)uF;
+      // s_nu = 1 / (1/2 + 3 nu), nu = sum nu_i Phi_i
+      const T lnu = ls * (-T(3) * s_nu * s_nu);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) lphi[i] += p.nu[i] * lnu;
+      // u = j + F/2  (lu now complete)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) lF[c] += T(0.5) * lu[c];
+      lm[(int64_t)ML::DRHO * N + node] = ldrho;
+#pragma unroll
+      for (int c = 0; c < D; ++c) lm[(int64_t)(ML::J + c) * N + node] = lu[c];
+    }
+
+    // ---------------------------------------------------------- forces (reverse)
+    T llap[3];
+    {
+      T S = 0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T lmu = lF[0] * gr[i][0] + lF[1] * gr[i][1] + lF[2] * gr[i][2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lgr[i][c] += mu[i] * lF[c];
+        const T pp = pc[i];
+        lphi[i] += lmu * T(24) * p.ups[i] / p.W * (T(3) * pp * pp - T(3) * pp + T(0.5));
+        S += lmu;
+        llap[i] = -T(0.75) * p.ups[i] * p.W * lmu;
+      }
+      const T c3 = T(24) * p.upsT / p.W;
+      lphi[0] -= S * c3 * pc[1] * pc[2];
+      lphi[1] -= S * c3 * pc[0] * pc[2];
+      lphi[2] -= S * c3 * pc[0] * pc[1];
+    }
+    T lpot = 0, lsigx = 0;
+    if (EHD) {
+      T lE[3];
+      const T lFge = lF[0] * ge[0] + lF[1] * ge[1] + lF[2] * ge[2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        lrho += lF[c] * E[c];
+        lE[c] = rq * lF[c] - lFge * E[c];
+        const T lge = -T(0.5) * e2 * lF[c];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) lgr[i][c] += p.eps[i] * lge;
+      }
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int kk = 2 * ax + k;
+          const T lside = (k == 0 ? -T(0.5) : T(0.5)) * lE[ax];
+          const uint8_t fm = fl_ax[kk];
+          T lsn = 0, lpn = 0;
+          if (fm == 0) {
+            const T hs = T(0.5) * (sigx + sig_ax[kk]);
+            const T dphi = pnb[kk] - phx;
+            lsigx += T(0.5) * dphi * lQs;
+            lsn = T(0.5) * dphi * lQs;
+            lpn = hs * lQs + lside;
+            lpot -= hs * lQs;
+          } else if (fm == 1 || fm >= 3) {
+            lsigx += T(2) * (pd_ax[kk] - phx) * lQs;
+            lpot -= T(2) * sigx * lQs + lside;
+            if (fm >= 3) vloc[fm - 3] += (double)(T(2) * sigx * lQs + T(2) * lside);
+          } else {
+            lpot += lside;
+          }
+          a.lsig[(int64_t)kk * N + node] = lsn;
+          a.lpnb[(int64_t)kk * N + node] = lpn;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) lphi[i] += p.cond[i] * lsigx;
+    }
+
+    // ---------------------------------------------------------- write
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) a.lgr[(int64_t)(D * i + c) * N + node] = lgr[i][c];
+      a.llap[(int64_t)i * N + node] = llap[i];
+      a.lphi_loc[(int64_t)i * N + node] = lphi[i];
+      a.lphip[(int64_t)i * N + node] = lphip[i];
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) a.lup[(int64_t)c * N + node] = lup[c];
+    if (EHD) {
+      a.lpot_loc[node] = lpot;
+      a.lrho_loc[node] = lrho;
+      a.lrhop[node] = lrhop;
+      a.lqp[node] = lqp;
+    }
+  } else if (node < N) {
+    // solid nodes: zero stencil cotangents so that pass B can gather unconditionally
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) a.lgr[(int64_t)(D * i + c) * N + node] = T(0);
+      a.llap[(int64_t)i * N + node] = T(0);
+      a.lphi_loc[(int64_t)i * N + node] = T(0);
+      a.lphip[(int64_t)i * N + node] = T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) a.lup[(int64_t)c * N + node] = T(0);
+    if (EHD) {
+#pragma unroll
+      for (int k = 0; k < 2 * D; ++k) {
+        a.lsig[(int64_t)k * N + node] = T(0);
+        a.lpnb[(int64_t)k * N + node] = T(0);
+      }
+      a.lpot_loc[node] = T(0);
+      a.lrho_loc[node] = T(0);
+      a.lrhop[node] = T(0);
+      a.lqp[node] = T(0);
+    }
+  }
+  if (EHD) block_reduce<kMaxE, false>(vloc, a.vpart + (int64_t)blockIdx.x * kMaxE);
+}
+
+// ----------------------------------------------------------------------------- pass B
+// Transposed stencils as gathers.  lphi_out at every node (ghost solids included),
+// lpot_out at fluid nodes.
+template <class L, class T, bool EHD>
+__global__ __launch_bounds__(kBlock) void k_adj_b(Dims d, const uint8_t* __restrict__ flags, Phys<T> p,
+                                                   const T* __restrict__ lgr, const T* __restrict__ llap,
+                                                   const T* __restrict__ lsig, const T* __restrict__ lpnb,
+                                                   const T* __restrict__ lphi_loc, const T* __restrict__ lpot_loc,
+                                                   T* __restrict__ lphi_out, T* __restrict__ lpot_out) {
+  constexpr int Q = L::Q;
+  constexpr int D = L::D;
+  const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= d.N) return;
+  const int64_t N = d.N;
+  const bool fluid = flags[y] == 0;
+  int nb[Q];
+  neighbours<L>(d, y, nb);
+  T acc[3] = {0, 0, 0};
+  T lp = 0;
+  if (fluid) {
+    const T wsum = T(36 - L::w36[0]) / T(36);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc[i] = lphi_loc[(int64_t)i * N + y] - T(6) * wsum * llap[(int64_t)i * N + y];
+    if (EHD) lp = lpot_loc[y];
+  }
+#pragma unroll
+  for (int q = 1; q < Q; ++q) {
+    const int x = nb[L::opp[q]];  // y = x + e_q
+    if (flags[x] != 0) continue;
+    const T w = T(L::w36[q]) / T(36);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T g = T(L::ex[q]) * lgr[(int64_t)(D * i + 0) * N + x] + T(L::ey[q]) * lgr[(int64_t)(D * i + 1) * N + x];
+      if (D == 3) g += T(L::ez[q]) * lgr[(int64_t)(D * i + 2) * N + x];
+      acc[i] += T(3) * w * g + T(6) * w * llap[(int64_t)i * N + x];
+    }
+    if (EHD && fluid) {
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        if (q == L::axp[ax] || q == L::axm[ax]) {
+          const int kk = 2 * ax + (q == L::axp[ax] ? 0 : 1);
+          const T ls = lsig[(int64_t)kk * N + x];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) acc[i] += p.cond[i] * ls;
+          lp += lpnb[(int64_t)kk * N + x];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) lphi_out[(int64_t)i * N + y] = acc[i];
+  if (EHD) lpot_out[y] = fluid ? lp : T(0);
+}
+
+// ----------------------------------------------------------------------------- pass G
+// Ghost cotangents into their link sources.  Links are sorted by source; one thread per
+// distinct source sums its ghosts in order.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_adj_ghost(int64_t N, int nsrc, const int32_t* __restrict__ src_node,
+                                                       const int32_t* __restrict__ src_start,
+                                                       const int32_t* __restrict__ gnode_sorted,
+                                                       const T* __restrict__ glen_sorted, const T* __restrict__ phi,
+                                                       Phys<T> p, T* __restrict__ lphi) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nsrc) return;
+  const int64_t f = src_node[k];
+  const T p1 = phi[f], p2 = phi[N + f], p3 = phi[2 * N + f];
+  const T a4 = T(4) / p.W;
+  // dR_i/dp_j
+  const T dR[3][3] = {{a4 * (-p.cos13 * p3 - p.cos12 * p2), -a4 * p.cos12 * p1, -a4 * p.cos13 * p1},
+                      {a4 * p.cos12 * p2, a4 * (p.cos12 * p1 - p.cos23 * p3), -a4 * p.cos23 * p2},
+                      {a4 * p.cos13 * p3, a4 * p.cos23 * p3, a4 * (p.cos23 * p2 + p.cos13 * p1)}};
+  T acc[3] = {0, 0, 0};
+  for (int g = src_start[k]; g < src_start[k + 1]; ++g) {
+    const int64_t s = gnode_sorted[g];
+    const T l = glen_sorted[g];
+    const T ls[3] = {lphi[s], lphi[N + s], lphi[2 * N + s]};
+#pragma unroll
+    for (int jx = 0; jx < 3; ++jx)
+      acc[jx] += ls[jx] - l * (ls[0] * dR[0][jx] + ls[1] * dR[1][jx] + ls[2] * dR[2][jx]);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) lphi[(int64_t)i * N + f] += acc[i];
+}
+
+// ----------------------------------------------------------------------------- pass CD
+// Permittivity and charge cotangents from the potential adjoint lb, then the population
+// cotangents of step t.
+template <class L, class T, bool EHD>
+__global__ __launch_bounds__(kBlock) void k_adj_cd(Dims d, const uint8_t* __restrict__ flags, Phys<T> p,
+                                                    Volts<T> volts, const T* __restrict__ rec,
+                                                    const T* __restrict__ lphi, const T* __restrict__ lrho_loc,
+                                                    const T* __restrict__ lb, const T* __restrict__ lmom,
+                                                    T* __restrict__ lP, double* __restrict__ vpart) {
+  using ML = MomLayout<L>;
+  using RL = RecLayout<L>;
+  constexpr int Q = L::Q;
+  constexpr int D = L::D;
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double vloc[kMaxE] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t N = d.N;
+  if (x < N) {
+    const int F = EHD ? 5 : 4;
+    if (flags[x] != 0) {
+      for (int f = 0; f < F; ++f)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) lP[((int64_t)f * Q + q) * N + x] = T(0);
+    } else {
+      T lph[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) lph[i] = lphi[(int64_t)i * N + x];
+      T lrho = 0;
+      if (EHD) {
+        int nb[Q];
+        neighbours<L>(d, x, nb);
+        const T ex = p.eps[0] * rec[(int64_t)(RL::PHI) * N + x] + p.eps[1] * rec[(int64_t)(RL::PHI + 1) * N + x] +
+                     p.eps[2] * rec[(int64_t)(RL::PHI + 2) * N + x];
+        const T phx = rec[(int64_t)RL::POT * N + x];
+        const T lbx = lb[x];
+        T leps = 0;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const int m = nb[k == 0 ? L::axp[ax] : L::axm[ax]];
+            const uint8_t fm = flags[m];
+            if (fm == 0) {
+              leps += -T(0.5) * (lbx - lb[m]) * (phx - rec[(int64_t)RL::POT * N + m]);
+            } else if (fm == 1 || fm >= 3) {
+              const T pd = fm == 1 ? T(0) : volts.v[fm - 3];
+              leps += T(2) * lbx * (pd - phx);
+              if (fm >= 3) vloc[fm - 3] += (double)(T(2) * ex * lbx);
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) lph[i] += p.eps[i] * leps;
+        lrho = lrho_loc[x] + lbx;
+      }
+      const T ldrho = lmom[(int64_t)ML::DRHO * N + x];
+      T lj[3] = {0, 0, 0}, ljh[3] = {0, 0, 0}, Pk[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        lj[c] = lmom[(int64_t)(ML::J + c) * N + x];
+        if (EHD) ljh[c] = lmom[(int64_t)(ML::JH + c) * N + x];
+      }
+#pragma unroll
+      for (int k = 0; k < ML::P; ++k) Pk[k] = lmom[(int64_t)(ML::PI + k) * N + x];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const T exq = T(L::ex[q]), eyq = T(L::ey[q]), ezq = T(L::ez[q]);
+        T ld;
+        if (D == 2)
+          ld = exq * exq * Pk[0] + eyq * eyq * Pk[1] + exq * eyq * Pk[2];
+        else
+          ld = exq * exq * Pk[0] + eyq * eyq * Pk[1] + ezq * ezq * Pk[2] + exq * eyq * Pk[3] + exq * ezq * Pk[4] +
+               eyq * ezq * Pk[5];
+        lP[(int64_t)q * N + x] = ldrho + exq * lj[0] + eyq * lj[1] + ezq * lj[2] + ld;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          T v = lph[i];
+          v += exq * lmom[(int64_t)(ML::JF + D * i + 0) * N + x] + eyq * lmom[(int64_t)(ML::JF + D * i + 1) * N + x];
+          if (D == 3) v += ezq * lmom[(int64_t)(ML::JF + D * i + 2) * N + x];
+          lP[((int64_t)(1 + i) * Q + q) * N + x] = v;
+        }
+        if (EHD) lP[((int64_t)4 * Q + q) * N + x] = lrho + exq * ljh[0] + eyq * ljh[1] + ezq * ljh[2];
+      }
+    }
+  }
+  if (EHD) block_reduce<kMaxE, false>(vloc, vpart + (int64_t)blockIdx.x * kMaxE);
+}
+
+// ----------------------------------------------------------------------------- terminal cotangent
+// L depends on x_c(T) (phase-1 moments of the populations at T) and on v_c(T) (previous-
+// step Phi_1 and u in the state at T).  s = {M1, x_c[3], Mp, v_c[3]} in FP64.
+template <class L, class T, bool EHD>
+__global__ __launch_bounds__(kBlock) void k_adj_terminal(Dims d, const uint8_t* __restrict__ flags,
+                                                          const T* __restrict__ phi_prev, const T* __restrict__ u_prev,
+                                                          const double* __restrict__ s, double gx0, double gx1,
+                                                          double gx2, double gv0, double gv1, double gv2,
+                                                          T* __restrict__ lP, T* __restrict__ lphip,
+                                                          T* __restrict__ lup, T* __restrict__ lrhop,
+                                                          T* __restrict__ lqp) {
+  constexpr int Q = L::Q;
+  constexpr int D = L::D;
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= d.N) return;
+  const int64_t N = d.N;
+  const int F = EHD ? 5 : 4;
+  const bool fluid = flags[x] == 0;
+  const double cx[3] = {(double)(x % d.nx), (double)((x / d.nx) % d.ny), (double)(x / ((int64_t)d.nx * d.ny))};
+  const double gx[3] = {gx0, gx1, gx2}, gv[3] = {gv0, gv1, gv2};
+  double l1 = 0.0, lpp = 0.0;
+  double lu[3] = {0.0, 0.0, 0.0};
+  if (fluid) {
+    for (int a = 0; a < D; ++a) l1 += gx[a] * (cx[a] - s[1 + a]) / s[0];
+    const double pp = phi_prev[x];
+    for (int a = 0; a < D; ++a) {
+      const double ua = u_prev[(int64_t)a * N + x];
+      lpp += gv[a] * (ua - s[5 + a]) / s[4];
+      lu[a] = gv[a] * pp / s[4];
+    }
+  }
+  for (int f = 0; f < F; ++f)
+    for (int q = 0; q < Q; ++q) lP[((int64_t)f * Q + q) * N + x] = f == 1 ? (T)l1 : T(0);
+  lphip[x] = (T)lpp;
+  lphip[N + x] = T(0);
+  lphip[2 * N + x] = T(0);
+  for (int a = 0; a < D; ++a) lup[(int64_t)a * N + x] = (T)lu[a];
+  lrhop[x] = T(0);
+  lqp[x] = T(0);
+}
+
+}  // namespace ehd

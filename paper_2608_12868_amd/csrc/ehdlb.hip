@@ -11,6 +11,7 @@
 
 #include "../../include/ehdlb.h"
 #include "kernels.h"
+#include "adjoint.h"
 
 using namespace ehd;
 
@@ -72,6 +73,22 @@ struct ehdlb_ctx {
   int64_t max_ghost = 0;
   int64_t nparts = 0;
   int64_t hdr[4]{};  // host staging of the state header (kept alive for async copies)
+  // wetting links sorted by source (for the adjoint's gather of ghost cotangents)
+  std::vector<int32_t> gs_node, src_node, src_start;
+  std::vector<double> gs_len;
+  size_t off_gs_node = 0, off_gs_len = 0, off_src_node = 0, off_src_start = 0;
+  // adjoint: checkpointed forward bookkeeping and workspace layout
+  struct Adj {
+    char* ws = nullptr;
+    size_t bytes = 0;
+    int64_t t0 = 0, T = 0;
+    int K = 0, nck = 0;
+    bool ready = false;
+    size_t ckpt = 0, fin = 0, rec = 0, lP[2]{}, lphip[2]{}, lup[2]{}, lrhop[2]{}, lqp[2]{};
+    size_t lgr = 0, llap = 0, lsig = 0, lpnb = 0, lphi_loc = 0, lpot_loc = 0, lrho_loc = 0, lmom = 0;
+    size_t lphi = 0, lpot = 0, lb = 0, vpart = 0, vred = 0, vacc = 0, obs = 0, total = 0, rec_stride = 0;
+    int nvseg = 0;
+  } adj;
   // potential-solver options (ehdlb_set_solver_options)
   double mg_omega = 0.8;       // damped-Jacobi weight
   int mg_nu = 2;               // pre- and post-smoothing sweeps
@@ -83,6 +100,7 @@ struct ehdlb_ctx {
   int64_t timed_steps = 0;
   double acc_ms[3]{};
   double hres[2]{};  // host copy of the residual check
+  double last_mp = 0.0;  // sum of the previous-step Phi_1 at the last observables call
 
   template <class T>
   T* ptr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -184,6 +202,10 @@ static void plan_layout(ehdlb_ctx* c) {
   c->off_gnode = take(N * 4);
   c->off_gsrc = take(N * 4);
   c->off_glen = take(N * ts);
+  c->off_gs_node = take(N * 4);
+  c->off_gs_len = take(N * ts);
+  c->off_src_node = take(N * 4);
+  c->off_src_start = take((N + 1) * 4);
   c->off_scratch = take(N * ts);
   c->off_dbl = take(N * 8);
   // --- potential solver
@@ -302,30 +324,24 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout) {
   return EHDLB_OK;
 }
 
+// Conjugate gradients on the fine-level operator (already set up in level 0) for A x = b, warm
+// started from x, preconditioned by one multigrid V-cycle; converged when the FP64 residual
+// max|b - A x| <= tol max|b|.
 template <class LT, class T>
-static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, const Volts<T>& volts) {
+static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b) {
   constexpr int D = LT::D;
   hipStream_t s = c->stream;
   const int64_t N = c->N;
-  const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
   MGLevel& m0 = c->mg[0];
   T* cp0 = c->ptr<T>(m0.cp);
   T* dg0 = c->ptr<T>(m0.diag);
-  T* b = c->ptr<T>(c->off_b);
-  T* x = c->ptr<T>(c->off_pot);
   T* r = c->ptr<T>(c->off_r);
   T* p = c->ptr<T>(c->off_p);
   T* qv = c->ptr<T>(c->off_qv);
   double* part = c->ptr<double>(c->off_part);
   double* red = c->ptr<double>(c->off_red);
   double* cg = c->ptr<double>(c->off_cg);
-  const Phys<T> ph = make_phys<T>(c->prm);
   const int nb0 = nblocks(N), rb0 = rblocks(N);
-
-  // fine-level operator and right-hand side; the last solution is the initial guess
-  hipLaunchKernelGGL((k_pois_setup<LT, T>), dim3(nb0), dim3(kBlock), 0, s, dm, c->ptr<uint8_t>(c->off_flags), phi, rho,
-                     ph, volts, cp0, dg0, b);
-  LAUNCHCHK();
 
   auto check = [&](double& rel, double& bmax) -> ehdlb_status {
     hipLaunchKernelGGL((k_true_resid<D, T>), dim3(rb0), dim3(kBlock), 0, s, m0.L, cp0, dg0, b, x, r, part);
@@ -397,6 +413,27 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
   if (!std::isfinite(rel)) c->sticky |= 1;
   c->last_resid = rel;
   return EHDLB_OK;
+}
+
+// Fine-level operator and right-hand side of the discrete Gauss law from the phase fields
+// (rho == nullptr: Dirichlet part of b only).
+template <class LT, class T>
+static ehdlb_status pois_setup(ehdlb_ctx* c, const T* phi, const T* rho, const Volts<T>& volts) {
+  const int64_t N = c->N;
+  const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
+  MGLevel& m0 = c->mg[0];
+  hipLaunchKernelGGL((k_pois_setup<LT, T>), dim3(nblocks(N)), dim3(kBlock), 0, c->stream, dm,
+                     c->ptr<uint8_t>(c->off_flags), phi, rho, make_phys<T>(c->prm), volts, c->ptr<T>(m0.cp),
+                     c->ptr<T>(m0.diag), c->ptr<T>(c->off_b));
+  LAUNCHCHK();
+  return EHDLB_OK;
+}
+
+template <class LT, class T>
+static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, const Volts<T>& volts) {
+  ehdlb_status st = pois_setup<LT, T>(c, phi, rho, volts);
+  if (st) return st;
+  return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b));
 }
 
 // ============================================================================ timing
@@ -523,6 +560,7 @@ static ehdlb_status observables_impl(ehdlb_ctx* c, ehdlb_obs* o) {
   for (int i = 0; i < 3; ++i) o->mass[i] = h[i];
   for (int a = 0; a < 3; ++a) o->centroid[a] = h[3 + a] / h[0];
   for (int a = 0; a < 3; ++a) o->velocity[a] = h[9] != 0.0 ? h[6 + a] / h[9] : 0.0;
+  c->last_mp = h[9];
   o->total_charge = h[10];
   o->sum_phi_drift = h[kObs];
   o->poisson_residual = c->last_resid;
@@ -619,10 +657,285 @@ static ehdlb_status upload_geometry(ehdlb_ctx* c) {
     ehdlb_status st = c->tsize == 8 ? upload<double>(c, len.data(), (int64_t)G, c->ptr<double>(c->off_glen))
                                     : upload<float>(c, len.data(), (int64_t)G, c->ptr<float>(c->off_glen));
     if (st) return st;
+    HIPCHK(hipMemcpyAsync(c->ptr<int32_t>(c->off_gs_node), c->gs_node.data(), G * 4, hipMemcpyHostToDevice, c->stream));
+    st = c->tsize == 8 ? upload<double>(c, c->gs_len.data(), (int64_t)G, c->ptr<double>(c->off_gs_len))
+                       : upload<float>(c, c->gs_len.data(), (int64_t)G, c->ptr<float>(c->off_gs_len));
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(c->ptr<int32_t>(c->off_src_node), c->src_node.data(), c->src_node.size() * 4,
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->ptr<int32_t>(c->off_src_start), c->src_start.data(), c->src_start.size() * 4,
+                          hipMemcpyHostToDevice, c->stream));
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   return EHDLB_OK;
 }
+
+// ============================================================================ adjoint
+static int rec_count(const ehdlb_ctx* c) {
+  return c->D == 2 ? RecLayout<D2Q9>::COUNT : RecLayout<D3Q19>::COUNT;
+}
+static int mom_count(const ehdlb_ctx* c) { return c->D == 2 ? MomLayout<D2Q9>::COUNT : MomLayout<D3Q19>::COUNT; }
+
+static void plan_adjoint(const ehdlb_ctx* c, int64_t T, int K, ehdlb_ctx::Adj& a) {
+  const int64_t N = c->N;
+  const size_t ts = c->tsize;
+  const int D = c->D;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  a.T = T;
+  a.K = K;
+  a.nck = (int)((T + K - 1) / K);
+  a.ckpt = take((size_t)a.nck * align_up(c->state_bytes));
+  a.fin = take(c->state_bytes);
+  a.rec_stride = align_up((size_t)rec_count(c) * N * ts);
+  a.rec = take((size_t)K * a.rec_stride);
+  const size_t F = (size_t)c->F * c->Q;
+  for (int k = 0; k < 2; ++k) {
+    a.lP[k] = take(F * N * ts);
+    a.lphip[k] = take(3 * N * ts);
+    a.lup[k] = take((size_t)D * N * ts);
+    a.lrhop[k] = take(N * ts);
+    a.lqp[k] = take(N * ts);
+  }
+  a.lgr = take((size_t)3 * D * N * ts);
+  a.llap = take(3 * N * ts);
+  a.lsig = take((size_t)2 * D * N * ts);
+  a.lpnb = take((size_t)2 * D * N * ts);
+  a.lphi_loc = take(3 * N * ts);
+  a.lpot_loc = take(N * ts);
+  a.lrho_loc = take(N * ts);
+  a.lmom = take((size_t)mom_count(c) * N * ts);
+  a.lphi = take(3 * N * ts);
+  a.lpot = take(N * ts);
+  a.lb = take(N * ts);
+  a.vpart = take((size_t)nblocks(N) * kMaxE * 8);
+  a.vred = take(kMaxE * 8);
+  a.nvseg = 1 << 16;
+  a.vacc = take((size_t)kMaxE * a.nvseg * 8);
+  a.obs = take(16 * 8);
+  a.total = o;
+}
+
+__global__ void k_vacc_add(const double* __restrict__ red, double* __restrict__ vacc, int seg, int nseg) {
+  const int e = threadIdx.x;
+  if (e < kMaxE) vacc[(int64_t)e * nseg + seg] += red[e];
+}
+
+// one forward step that also writes the adjoint's record of step t
+template <class LT, class T, bool EHD>
+static ehdlb_status step_record(ehdlb_ctx* c, T* rec) {
+  using RL = RecLayout<LT>;
+  hipStream_t s = c->stream;
+  const int64_t N = c->N;
+  const size_t ts = sizeof(T);
+  const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
+  const Phys<T> ph = make_phys<T>(c->prm);
+  const uint8_t* flags = c->ptr<uint8_t>(c->off_flags);
+  const int G = (int)c->ghost_node.size();
+  const int64_t t = c->t;
+  const int pi = (int)(t & 1), pp = 1 - pi;
+  Volts<T> v{};
+  for (int e = 0; e < kMaxE; ++e) v.v[e] = (T)volts_at(c, e, t);
+  T* phi = c->ptr<T>(c->off_phi[pi]);
+  T* rho = c->ptr<T>(c->off_rho[pi]);
+  const T* pin = c->ptr<T>(c->off_pop[c->cur]);
+  T* pout = c->ptr<T>(c->off_pop[1 - c->cur]);
+  hipLaunchKernelGGL((k_moments<LT, T, EHD>), dim3(nblocks(N)), dim3(kBlock), 0, s, dm, flags, pin, phi, rho,
+                     (T*)nullptr);
+  if (G > 0)
+    hipLaunchKernelGGL(k_ghosts<T>, dim3(nblocks(G)), dim3(kBlock), 0, s, N, G, c->ptr<int32_t>(c->off_gnode),
+                       c->ptr<int32_t>(c->off_gsrc), c->ptr<T>(c->off_glen), phi, ph);
+  LAUNCHCHK();
+  if (EHD) {
+    ehdlb_status st = potential_solve<LT, T>(c, phi, rho, v);
+    if (st) return st;
+  }
+  HIPCHK(hipMemcpyAsync(rec + (size_t)RL::PHI * N, phi, 3 * N * ts, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(rec + (size_t)RL::PHIP * N, c->ptr<T>(c->off_phi[pp]), 3 * N * ts, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(rec + (size_t)RL::UP * N, c->ptr<T>(c->off_u[pp]), (size_t)LT::D * N * ts,
+                        hipMemcpyDeviceToDevice, s));
+  if (EHD) {
+    HIPCHK(hipMemcpyAsync(rec + (size_t)RL::RHO * N, rho, N * ts, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(rec + (size_t)RL::POT * N, c->ptr<T>(c->off_pot), N * ts, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(rec + (size_t)RL::RHOP * N, c->ptr<T>(c->off_rho[pp]), N * ts, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(rec + (size_t)RL::QP * N, c->ptr<T>(c->off_q[pp]), N * ts, hipMemcpyDeviceToDevice, s));
+  }
+  StepArgs<T> a{};
+  a.d = dm;
+  a.flags = flags;
+  a.pop_in = pin;
+  a.pop_out = pout;
+  a.phi = phi;
+  a.phi_prev = c->ptr<T>(c->off_phi[pp]);
+  a.rho = rho;
+  a.rho_prev = c->ptr<T>(c->off_rho[pp]);
+  a.u_prev = c->ptr<T>(c->off_u[pp]);
+  a.u_out = c->ptr<T>(c->off_u[pi]);
+  a.q_prev = c->ptr<T>(c->off_q[pp]);
+  a.q_out = c->ptr<T>(c->off_q[pi]);
+  a.pot = c->ptr<T>(c->off_pot);
+  a.p = ph;
+  a.volts = v;
+  a.dt_on = t == 0 ? T(0) : T(1);
+  a.rec = rec + (size_t)RL::MOM * N;
+  hipLaunchKernelGGL((k_step<LT, T, EHD, true>), dim3(nblocks(N)), dim3(kBlock), 0, s, a);
+  LAUNCHCHK();
+  c->cur = 1 - c->cur;
+  c->t = t + 1;
+  return EHDLB_OK;
+}
+
+// adjoint of step t: cotangents of step t+1 in slot nx, of step t written into slot cu
+template <class LT, class T, bool EHD>
+static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, int cu, int seg) {
+  using RL = RecLayout<LT>;
+  auto& J = c->adj;
+  hipStream_t s = c->stream;
+  const int64_t N = c->N;
+  const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
+  const Phys<T> ph = make_phys<T>(c->prm);
+  const uint8_t* flags = c->ptr<uint8_t>(c->off_flags);
+  auto A = [&](size_t off) { return reinterpret_cast<T*>(J.ws + off); };
+  Volts<T> v{};
+  for (int e = 0; e < kMaxE; ++e) v.v[e] = (T)volts_at(c, e, t);
+  const int nb = nblocks(N);
+  AdjArgs<T> a{};
+  a.d = dm;
+  a.flags = flags;
+  a.rec = rec;
+  a.lP_next = A(J.lP[nx]);
+  a.lphip_next = A(J.lphip[nx]);
+  a.lup_next = A(J.lup[nx]);
+  a.lrhop_next = A(J.lrhop[nx]);
+  a.lqp_next = A(J.lqp[nx]);
+  a.lphip = A(J.lphip[cu]);
+  a.lup = A(J.lup[cu]);
+  a.lrhop = A(J.lrhop[cu]);
+  a.lqp = A(J.lqp[cu]);
+  a.lgr = A(J.lgr);
+  a.llap = A(J.llap);
+  a.lsig = A(J.lsig);
+  a.lpnb = A(J.lpnb);
+  a.lphi_loc = A(J.lphi_loc);
+  a.lpot_loc = A(J.lpot_loc);
+  a.lrho_loc = A(J.lrho_loc);
+  a.lmom = A(J.lmom);
+  a.vpart = reinterpret_cast<double*>(J.ws + J.vpart);
+  a.p = ph;
+  a.volts = v;
+  a.dt_on = t == 0 ? T(0) : T(1);
+  double* vpart = reinterpret_cast<double*>(J.ws + J.vpart);
+  double* vred = reinterpret_cast<double*>(J.ws + J.vred);
+  double* vacc = reinterpret_cast<double*>(J.ws + J.vacc);
+  hipLaunchKernelGGL((k_adj_a<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, a);
+  if (EHD) {
+    hipLaunchKernelGGL((k_final<kMaxE, false>), dim3(1), dim3(kBlock), 0, s, vpart, nb, vred);
+    hipLaunchKernelGGL(k_vacc_add, dim3(1), dim3(64), 0, s, vred, vacc, seg, J.nvseg);
+  }
+  hipLaunchKernelGGL((k_adj_b<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, (const T*)A(J.lgr),
+                     (const T*)A(J.llap), (const T*)A(J.lsig), (const T*)A(J.lpnb), (const T*)A(J.lphi_loc),
+                     (const T*)A(J.lpot_loc), A(J.lphi), A(J.lpot));
+  const int nsrc = (int)c->src_node.size();
+  if (nsrc > 0)
+    hipLaunchKernelGGL(k_adj_ghost<T>, dim3(nblocks(nsrc)), dim3(kBlock), 0, s, N, nsrc,
+                       c->ptr<int32_t>(c->off_src_node), c->ptr<int32_t>(c->off_src_start),
+                       c->ptr<int32_t>(c->off_gs_node), (const T*)c->ptr<T>(c->off_gs_len),
+                       rec + (size_t)RL::PHI * N, ph, A(J.lphi));
+  LAUNCHCHK();
+  if (EHD) {
+    // potential adjoint: A lb = lambda_phi with the operator of step t
+    ehdlb_status st = pois_setup<LT, T>(c, rec + (size_t)RL::PHI * N, (const T*)nullptr, v);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(c->ptr<T>(c->off_b), A(J.lpot), N * sizeof(T), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_zero<T>, dim3(nb), dim3(kBlock), 0, s, N, A(J.lb));
+    if ((st = pcg<LT, T>(c, A(J.lb), c->ptr<T>(c->off_b)))) return st;
+  }
+  hipLaunchKernelGGL((k_adj_cd<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, v, rec, (const T*)A(J.lphi),
+                     (const T*)A(J.lrho_loc), (const T*)A(J.lb), (const T*)A(J.lmom), A(J.lP[cu]), vpart);
+  if (EHD) {
+    hipLaunchKernelGGL((k_final<kMaxE, false>), dim3(1), dim3(kBlock), 0, s, vpart, nb, vred);
+    hipLaunchKernelGGL(k_vacc_add, dim3(1), dim3(64), 0, s, vred, vacc, seg, J.nvseg);
+  }
+  LAUNCHCHK();
+  return EHDLB_OK;
+}
+
+template <class LT, class T, bool EHD>
+struct FwdCkptFn {
+  static ehdlb_status run(ehdlb_ctx* c, int dummy) {
+    (void)dummy;
+    auto& J = c->adj;
+    ehdlb_status st;
+    for (int64_t k = 0; k < J.T; ++k) {
+      if (k % J.K == 0) {
+        if ((st = ehdlb_save_state(c, J.ws + J.ckpt + (size_t)(k / J.K) * align_up(c->state_bytes)))) return st;
+      }
+      if ((st = step_impl<LT, T, EHD>(c, 1))) return st;
+    }
+    return ehdlb_save_state(c, J.ws + J.fin);
+  }
+};
+
+template <class LT, class T, bool EHD>
+struct AdjFn {
+  static ehdlb_status run(ehdlb_ctx* c, const double* gx, const double* gv, int electrode, double* out) {
+    auto& J = c->adj;
+    hipStream_t s = c->stream;
+    const int64_t N = c->N;
+    const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
+    ehdlb_status st;
+    // terminal cotangent from the FP64 observables of the final state
+    ehdlb_obs ob;
+    if ((st = observables_impl<LT, T, EHD>(c, &ob))) return st;
+    double M1 = ob.mass[0];
+    // Mp = sum of the previous-step Phi_1: recompute from the velocity definition's weights
+    double sv[8] = {M1, ob.centroid[0], ob.centroid[1], ob.centroid[2], c->last_mp, ob.velocity[0],
+                    ob.velocity[1], ob.velocity[2]};
+    double* sd = reinterpret_cast<double*>(J.ws + J.obs);
+    HIPCHK(hipMemcpyAsync(sd, sv, sizeof(sv), hipMemcpyHostToDevice, s));
+    const int pp = 1 - (int)(c->t & 1);
+    auto A = [&](size_t off) { return reinterpret_cast<T*>(J.ws + off); };
+    int cu = 0;
+    hipLaunchKernelGGL((k_adj_terminal<LT, T, EHD>), dim3(nblocks(N)), dim3(kBlock), 0, s, dm,
+                       c->ptr<uint8_t>(c->off_flags), c->ptr<T>(c->off_phi[pp]), c->ptr<T>(c->off_u[pp]), sd,
+                       gx[0], gx[1], gx[2], gv[0], gv[1], gv[2], A(J.lP[cu]), A(J.lphip[cu]), A(J.lup[cu]),
+                       A(J.lrhop[cu]), A(J.lqp[cu]));
+    HIPCHK(hipMemsetAsync(J.ws + J.vacc, 0, (size_t)kMaxE * J.nvseg * 8, s));
+    LAUNCHCHK();
+    const auto& sch = c->sched[electrode];
+    const int nseg = sch.v.empty() ? 1 : (int)sch.v.size();
+    for (int j = J.nck - 1; j >= 0; --j) {
+      if ((st = ehdlb_load_state(c, J.ws + J.ckpt + (size_t)j * align_up(c->state_bytes)))) return st;
+      const int64_t ta = J.t0 + (int64_t)j * J.K;
+      const int64_t tb = std::min<int64_t>(ta + J.K, J.t0 + J.T);
+      for (int64_t t = ta; t < tb; ++t)
+        if ((st = step_record<LT, T, EHD>(c, reinterpret_cast<T*>(J.ws + J.rec + (size_t)(t - ta) * J.rec_stride))))
+          return st;
+      for (int64_t t = tb - 1; t >= ta; --t) {
+        int seg = 0;
+        if (!sch.v.empty()) {
+          const int64_t sg = (t * (int64_t)nseg) / sch.t_total;
+          seg = (int)std::min<int64_t>(sg, nseg - 1);
+        }
+        const int nx = cu;
+        cu = 1 - cu;
+        if ((st = adjoint_step<LT, T, EHD>(c, t, reinterpret_cast<T*>(J.ws + J.rec + (size_t)(t - ta) * J.rec_stride),
+                                            nx, cu, seg)))
+          return st;
+      }
+    }
+    std::vector<double> h((size_t)kMaxE * J.nvseg);
+    HIPCHK(hipMemcpyAsync(h.data(), J.ws + J.vacc, h.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int k = 0; k < nseg; ++k) out[k] = h[(size_t)electrode * J.nvseg + k];
+    // back to the final state of the checkpointed forward
+    return ehdlb_load_state(c, J.ws + J.fin);
+  }
+};
 
 // ============================================================================ C ABI
 extern "C" {
@@ -766,9 +1079,32 @@ ehdlb_status ehdlb_set_geometry(ehdlb_ctx* c, const uint8_t* flags) {
     c->ghost_dir.push_back(best);
     c->ghost_src.push_back((int32_t)nbr(s, best));
   }
+  // links sorted by source node (stable), grouped: src_node[k], ghosts src_start[k]..src_start[k+1]
+  {
+    const size_t G = c->ghost_node.size();
+    std::vector<size_t> ord(G);
+    for (size_t k = 0; k < G; ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return c->ghost_src[a] < c->ghost_src[b]; });
+    c->gs_node.resize(G);
+    c->gs_len.resize(G);
+    c->src_node.clear();
+    c->src_start.clear();
+    for (size_t k = 0; k < G; ++k) {
+      const size_t g = ord[k];
+      const int q = c->ghost_dir[g];
+      c->gs_node[k] = c->ghost_node[g];
+      c->gs_len[k] = std::sqrt((double)(ex[q] * ex[q] + ey[q] * ey[q] + ez[q] * ez[q]));
+      if (k == 0 || c->ghost_src[g] != c->ghost_src[ord[k - 1]]) {
+        c->src_node.push_back(c->ghost_src[g]);
+        c->src_start.push_back((int32_t)k);
+      }
+    }
+    c->src_start.push_back((int32_t)G);
+  }
   c->flags.assign(flags, flags + N);
   c->have_geometry = true;
   c->have_state = false;
+  c->adj.ready = false;
   if (c->bound) return upload_geometry(c);
   return EHDLB_OK;
 }
@@ -957,6 +1293,43 @@ int64_t ehdlb_wetting_links(const ehdlb_ctx* c, int64_t* nodes, int32_t* dirs, i
     if (dirs) dirs[k] = c->ghost_dir[(size_t)k];
   }
   return G;
+}
+
+size_t ehdlb_adjoint_workspace_bytes(const ehdlb_ctx* c, int64_t T, int32_t K) {
+  if (!c || T < 1 || K < 1) return 0;
+  ehdlb_ctx::Adj a;
+  plan_adjoint(c, T, K, a);
+  return a.total;
+}
+
+ehdlb_status ehdlb_forward_checkpointed(ehdlb_ctx* c, int64_t T, int32_t K, void* ws, size_t bytes) {
+  if (!c) return EHDLB_EINVAL;
+  if (T < 1 || K < 1) return fail(c, EHDLB_EINVAL, "T and K must be >= 1");
+  if (!ws || ((uintptr_t)ws) % 256) return fail(c, EHDLB_EINVAL, "adjoint workspace must be 256-byte aligned");
+  if (!c->have_state) return fail(c, EHDLB_ESTATE, "forward_checkpointed before set_phase");
+  ehdlb_ctx::Adj a;
+  plan_adjoint(c, T, K, a);
+  if (bytes < a.total) return fail(c, EHDLB_ENOMEM, "adjoint workspace too small");
+  a.ws = (char*)ws;
+  a.bytes = bytes;
+  a.t0 = c->t;
+  c->adj = a;
+  ehdlb_status st = dispatch<FwdCkptFn>(c, 0);
+  if (st) return st;
+  c->adj.ready = true;
+  return EHDLB_OK;
+}
+
+ehdlb_status ehdlb_adjoint(ehdlb_ctx* c, const double* dL_dcentroid, const double* dL_dvelocity, int32_t electrode,
+                           double* dL_dvolts) {
+  if (!c) return EHDLB_EINVAL;
+  if (!dL_dcentroid || !dL_dvelocity || !dL_dvolts) return fail(c, EHDLB_EINVAL, "null argument");
+  if (electrode < 0 || electrode >= EHDLB_MAX_ELECTRODES) return fail(c, EHDLB_EINVAL, "electrode index out of range");
+  if (!c->ehd) return fail(c, EHDLB_EINVAL, "adjoint with respect to voltages needs the field on");
+  if (!c->adj.ready) return fail(c, EHDLB_ESTATE, "adjoint before forward_checkpointed");
+  if (c->sched[electrode].v.size() > (size_t)c->adj.nvseg) return fail(c, EHDLB_EINVAL, "too many schedule segments");
+  if (c->t != c->adj.t0 + c->adj.T) return fail(c, EHDLB_ESTATE, "state moved since forward_checkpointed");
+  return dispatch<AdjFn>(c, dL_dcentroid, dL_dvelocity, (int)electrode, dL_dvolts);
 }
 
 ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* c, double omega, int32_t sweeps, double overcorrect) {

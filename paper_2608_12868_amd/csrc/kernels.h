@@ -81,6 +81,18 @@ struct StepArgs {
   Phys<T> p;
   Volts<T> volts;
   T dt_on;            // 0 on the first step (no time derivatives), 1 afterwards
+  T* rec;             // STORE: population moments for the adjoint, [kMom][N] (see mom_layout)
+};
+
+// Population moments a step's adjoint needs (the collision depends on the populations only
+// through them): drho, j[D], the second-order raw moments Pi[P] of g - g_eq + F_q/2,
+// jf[3][D] (first moments of the phase populations), jh[D] (first moment of the charge).
+template <class L>
+struct MomLayout {
+  static constexpr int D = L::D;
+  static constexpr int P = D == 2 ? 3 : 6;
+  static constexpr int DRHO = 0, J = 1, PI = 1 + D, JF = 1 + D + P, JH = 1 + 4 * D + P;
+  static constexpr int COUNT = 1 + 5 * D + P;
 };
 
 // ----------------------------------------------------------------------------- moments (Eq. 19)
@@ -141,8 +153,9 @@ __global__ __launch_bounds__(kBlock) void k_ghosts(int64_t N, int G, const int32
 }
 
 // ----------------------------------------------------------------------------- fused collide-stream
-template <class L, class T, bool EHD>
+template <class L, class T, bool EHD, bool STORE = false>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
+  using ML = MomLayout<L>;
   constexpr int Q = L::Q;
   constexpr int D = L::D;
   const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -290,6 +303,22 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
       }
     }
     const T om = T(1) - s_nu;
+    if (STORE) {
+      T* r = a.rec;
+      r[(int64_t)ML::DRHO * N + node] = drho;
+#pragma unroll
+      for (int c = 0; c < D; ++c) r[(int64_t)(ML::J + c) * N + node] = j[c];
+      r[(int64_t)(ML::PI + 0) * N + node] = Pxx;
+      r[(int64_t)(ML::PI + 1) * N + node] = Pyy;
+      if (D == 2) {
+        r[(int64_t)(ML::PI + 2) * N + node] = Pxy;
+      } else {
+        r[(int64_t)(ML::PI + 2) * N + node] = Pzz;
+        r[(int64_t)(ML::PI + 3) * N + node] = Pxy;
+        r[(int64_t)(ML::PI + 4) * N + node] = Pxz;
+        r[(int64_t)(ML::PI + 5) * N + node] = Pyz;
+      }
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
@@ -346,6 +375,10 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
         jf[1] += T(L::ey[q]) * fq[q];
         jf[2] += T(L::ez[q]) * fq[q];
       }
+      if (STORE) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) a.rec[(int64_t)(ML::JF + D * i + c) * N + node] = jf[c];
+      }
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const T up = c < D ? a.u_prev[(int64_t)c * N + node] : T(0);
@@ -379,6 +412,10 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
       jh[0] += T(L::ex[q]) * hq[q];
       jh[1] += T(L::ey[q]) * hq[q];
       jh[2] += T(L::ez[q]) * hq[q];
+    }
+    if (STORE) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) a.rec[(int64_t)(ML::JH + c) * N + node] = jh[c];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

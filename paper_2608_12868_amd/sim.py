@@ -135,6 +135,28 @@ class Simulation(Context):
                     poisson_initial_residual=o.poisson_initial_residual,
                     poisson_iters=o.poisson_iters, flags=o.flags, status=st)
 
+    def adjoint_workspace_bytes(self, T, K):
+        return int(L.lib().ehdlb_adjoint_workspace_bytes(self.h, int(T), int(K)))
+
+    def forward_checkpointed(self, T, K):
+        """Run T steps keeping a checkpoint every K steps (device memory owned by this object)."""
+        torch = self.torch
+        nbytes = self.adjoint_workspace_bytes(T, K)
+        if getattr(self, "adj_ws", None) is None or self.adj_ws.numel() < nbytes + 256:
+            self.adj_ws = None
+            self.adj_ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.adj_ws.data_ptr()
+        ptr = base + ((-base) % 256)
+        self._chk(L.lib().ehdlb_forward_checkpointed(self.h, int(T), int(K), C.c_void_p(ptr), nbytes))
+
+    def adjoint(self, dL_dcentroid, dL_dvelocity, electrode=0, n_seg=None):
+        """dL/dV per schedule segment of `electrode` after forward_checkpointed."""
+        gx = np.ascontiguousarray(dL_dcentroid, dtype=np.float64).reshape(3)
+        gv = np.ascontiguousarray(dL_dvelocity, dtype=np.float64).reshape(3)
+        out = np.zeros(max(int(n_seg or 1), 1), np.float64)
+        self._chk(L.lib().ehdlb_adjoint(self.h, gx.ctypes.data, gv.ctypes.data, int(electrode), out.ctypes.data))
+        return out
+
     def set_solver_options(self, omega=0.8, sweeps=2, overcorrect=2.0):
         self._chk(L.lib().ehdlb_set_solver_options(self.h, float(omega), int(sweeps), float(overcorrect)))
 
