@@ -86,7 +86,7 @@ struct ehdlb_ctx {
     bool ready = false;
     size_t ckpt = 0, fin = 0, rec = 0, lP[2]{}, lphip[2]{}, lup[2]{}, lrhop[2]{}, lqp[2]{};
     size_t lgr = 0, llap = 0, lsig = 0, lpnb = 0, lphi_loc = 0, lpot_loc = 0, lrho_loc = 0, lmom = 0;
-    size_t lphi = 0, lpot = 0, lb = 0, vpart = 0, vred = 0, vacc = 0, obs = 0, total = 0, rec_stride = 0;
+    size_t lphi = 0, lpot = 0, lb = 0, lb2 = 0, vpart = 0, vred = 0, vacc = 0, obs = 0, total = 0, rec_stride = 0;
     int nvseg = 0;
   } adj;
   // potential-solver options (ehdlb_set_solver_options)
@@ -712,6 +712,7 @@ static void plan_adjoint(const ehdlb_ctx* c, int64_t T, int K, ehdlb_ctx::Adj& a
   a.lphi = take(3 * N * ts);
   a.lpot = take(N * ts);
   a.lb = take(N * ts);
+  a.lb2 = take(N * ts);
   a.vpart = take((size_t)nblocks(N) * kMaxE * 8);
   a.vred = take(kMaxE * 8);
   a.nvseg = 1 << 16;
@@ -803,6 +804,7 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
   Volts<T> v{};
   for (int e = 0; e < kMaxE; ++e) v.v[e] = (T)volts_at(c, e, t);
   const int nb = nblocks(N);
+  const size_t lbx = (t & 1) ? J.lb2 : J.lb;
   AdjArgs<T> a{};
   a.d = dm;
   a.flags = flags;
@@ -851,11 +853,12 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
     ehdlb_status st = pois_setup<LT, T>(c, rec + (size_t)RL::PHI * N, (const T*)nullptr, v);
     if (st) return st;
     HIPCHK(hipMemcpyAsync(c->ptr<T>(c->off_b), A(J.lpot), N * sizeof(T), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_zero<T>, dim3(nb), dim3(kBlock), 0, s, N, A(J.lb));
-    if ((st = pcg<LT, T>(c, A(J.lb), c->ptr<T>(c->off_b)))) return st;
+    // warm start from the adjoint potential of step t+2 (same parity: the adjoint of the
+    // over-relaxed first moments alternates in sign from step to step); zero at the start
+    if ((st = pcg<LT, T>(c, A(lbx), c->ptr<T>(c->off_b)))) return st;
   }
   hipLaunchKernelGGL((k_adj_cd<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, v, rec, (const T*)A(J.lphi),
-                     (const T*)A(J.lrho_loc), (const T*)A(J.lb), (const T*)A(J.lmom), A(J.lP[cu]), vpart);
+                     (const T*)A(J.lrho_loc), (const T*)A(lbx), (const T*)A(J.lmom), A(J.lP[cu]), vpart);
   if (EHD) {
     hipLaunchKernelGGL((k_final<kMaxE, false>), dim3(1), dim3(kBlock), 0, s, vpart, nb, vred);
     hipLaunchKernelGGL(k_vacc_add, dim3(1), dim3(64), 0, s, vred, vacc, seg, J.nvseg);
@@ -905,6 +908,8 @@ struct AdjFn {
                        gx[0], gx[1], gx[2], gv[0], gv[1], gv[2], A(J.lP[cu]), A(J.lphip[cu]), A(J.lup[cu]),
                        A(J.lrhop[cu]), A(J.lqp[cu]));
     HIPCHK(hipMemsetAsync(J.ws + J.vacc, 0, (size_t)kMaxE * J.nvseg * 8, s));
+    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, N, A(J.lb));
+    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, N, A(J.lb2));
     LAUNCHCHK();
     const auto& sch = c->sched[electrode];
     const int nseg = sch.v.empty() ? 1 : (int)sch.v.size();

@@ -295,3 +295,26 @@ def test_v11_potential_adjoint_gradcheck():
             args_m = [tm if tens is a else a for a in (eps, rho, volts)]
             fd = (float(f(*args_p)) - float(f(*args_m))) / (2 * h)
             assert abs(fd - float(grad[idx])) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_v11_oracle_schedule_gradient_vs_finite_differences():
+    """The CPU adjoint (reverse-mode autograd through the oracle) against central differences
+    of the oracle itself, on a small EHD lattice with a 3-segment voltage schedule."""
+    from oracle.adjoint import observables_after, schedule_gradient
+    case = make_case("c4s")
+    o = Oracle(case.dim, case.n, case.periodic, case.params, case.flags)
+    sched = np.array([0.03, 0.07, 0.05])
+    T = t_total = 9
+    gx = np.array([1.0, -0.5, 0.0])
+    gv = np.array([30.0, 10.0, 0.0])
+    g, _, _ = schedule_gradient(o, case.phi, sched, T, t_total, gx, gv)
+    h = 1e-4
+    for k in range(3):
+        vals = []
+        for sgn in (1, -1):
+            v = torch.tensor(sched, dtype=F64)
+            v[k] += sgn * h
+            xc, vc = observables_after(o, case.phi, v, T, t_total)
+            vals.append(float((torch.tensor(gx) * xc).sum() + (torch.tensor(gv) * vc).sum()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - float(g[k])) <= 1e-5 * max(abs(fd), 1e-300) + 1e-16
