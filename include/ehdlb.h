@@ -98,7 +98,9 @@ typedef struct {
   double charge_diffusion;  /* alpha of Eq. 14 (>= 0)                                     */
   double body_force[3];     /* uniform body force density                                 */
   double electrode_volts[EHDLB_MAX_ELECTRODES];  /* constant V_k unless a schedule is set */
-  double poisson_tol;       /* stop when max|b - A phi| <= tol * max|b|, residual in FP64 */
+  double poisson_tol;       /* stop when max|b - A phi| <= tol * max|b| (residual in FP64),
+                               or when it reaches the rounding floor of phi stored in the
+                               path's precision, 8 eps max_i sum_j |A_ij phi_j|           */
   int32_t poisson_max_iter; /* iteration cap of the potential solve (>= 1)                */
   int32_t poisson_check_every;  /* residual check period in iterations (>= 1)             */
 } ehdlb_params;

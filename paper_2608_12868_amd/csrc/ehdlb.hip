@@ -25,6 +25,8 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 // grid of the grid-stride reduction kernels (fixed, so the reduction order is fixed)
 constexpr int kRedBlocks = 1024;
+// levels with at most this many cells run inside the single-workgroup V-cycle tail
+constexpr int64_t kTailMaxCells = 2048;
 int rblocks(int64_t n) { return std::min(nblocks(n), kRedBlocks); }
 
 struct MGLevel {
@@ -70,6 +72,7 @@ struct ehdlb_ctx {
   size_t off_part = 0, off_red = 0, off_cg = 0, off_inv = 0, off_dbl = 0;
   size_t state_bytes = 0, total = 0;
   std::vector<MGLevel> mg;
+  size_t tail_first = 0;  // first level handled by the single-workgroup tail kernel
   int64_t max_ghost = 0;
   int64_t nparts = 0;
   int64_t hdr[4]{};  // host staging of the state header (kept alive for async copies)
@@ -99,7 +102,7 @@ struct ehdlb_ctx {
   size_t ev_used = 0;
   int64_t timed_steps = 0;
   double acc_ms[3]{};
-  double hres[2]{};  // host copy of the residual check
+  double hres[3]{};  // host copy of the residual check
   double last_mp = 0.0;  // sum of the previous-step Phi_1 at the last observables call
 
   template <class T>
@@ -242,6 +245,8 @@ static void plan_layout(ehdlb_ctx* c) {
     }
     const int64_t nc = c->mg.back().L.N;
     c->off_inv = take((size_t)nc * nc * 8);
+    c->tail_first = c->mg.size() - 1;
+    while (c->tail_first > 0 && c->mg[c->tail_first - 1].L.N <= kTailMaxCells) --c->tail_first;
   }
   c->nparts = nblocks(N);
   c->off_part = take((size_t)c->nparts * kObs * 8 + 64);
@@ -282,28 +287,60 @@ static ehdlb_status validate(ehdlb_ctx* c, const ehdlb_lattice* L, const ehdlb_p
 }
 
 // ============================================================================ potential solve
+template <class T>
+static TailArgs<T> tail_args(ehdlb_ctx* c) {
+  TailArgs<T> t{};
+  t.first = (int)c->tail_first;
+  t.last = (int)c->mg.size() - 1;
+  for (int l = t.first; l <= t.last; ++l) {
+    MGLevel& m = c->mg[l];
+    t.L[l] = m.L;
+    t.cp[l] = c->ptr<T>(m.cp);
+    t.dg[l] = c->ptr<T>(m.diag);
+    t.r[l] = c->ptr<T>(m.r);
+    t.z[l] = c->ptr<T>(m.z);
+    t.t[l] = c->ptr<T>(m.t);
+  }
+  t.inv = c->ptr<double>(c->off_inv);
+  t.w = (T)c->mg_omega;
+  t.a = (T)c->mg_overcorrect;
+  t.nu = c->mg_nu;
+  return t;
+}
+
+// One symmetric V-cycle z = M r at level lvl.  At level 0 with dot_part != nullptr the last
+// post-smoothing sweep also writes per-block partials of r.z (grid of rblocks(N)); returns
+// whether it did.
 template <int D, class T>
-static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout) {
+static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot_part, bool* dotted) {
   hipStream_t s = c->stream;
   MGLevel& m = c->mg[lvl];
   const Level L = m.L;
-  T* cp = c->ptr<T>(m.cp);
-  T* dg = c->ptr<T>(m.diag);
-  if (lvl + 1 == c->mg.size()) {
-    T* z = c->ptr<T>(m.z);
-    hipLaunchKernelGGL(k_coarse_apply<T>, dim3(1), dim3(kBlock), 0, s, (int)L.N,
-                       c->ptr<double>(c->off_inv), dg, r, z);
+  if (dotted) *dotted = false;
+  if (lvl == c->tail_first) {
+    TailArgs<T> ta = tail_args<T>(c);
+    if (r != ta.r[lvl]) {
+      HIPCHK(hipMemcpyAsync(ta.r[lvl], r, L.N * sizeof(T), hipMemcpyDeviceToDevice, s));
+    }
+    hipLaunchKernelGGL((k_vcycle_tail<D, T>), dim3(1), dim3(kTailThreads), 0, s, ta);
     LAUNCHCHK();
-    *zout = z;
+    *zout = ta.z[lvl];
     return EHDLB_OK;
   }
+  T* cp = c->ptr<T>(m.cp);
+  T* dg = c->ptr<T>(m.diag);
   const T omega = (T)c->mg_omega;
   const int nu = c->mg_nu;
   T* z = c->ptr<T>(m.z);
   T* t = c->ptr<T>(m.t);
-  hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nblocks(L.N)), dim3(kBlock), 0, s, L, cp, dg, r, (const T*)nullptr, z, omega);
-  for (int k = 1; k < nu; ++k) {
-    hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nblocks(L.N)), dim3(kBlock), 0, s, L, cp, dg, r, z, t, omega);
+  const int nb = nblocks(L.N);
+  if (nu >= 2) {
+    hipLaunchKernelGGL((k_smooth2<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, r, z, omega);
+  } else {
+    hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, r, (const T*)nullptr, z, omega);
+  }
+  for (int k = 2; k < nu; ++k) {
+    hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, r, z, t, omega);
     std::swap(z, t);
   }
   MGLevel& mc = c->mg[lvl + 1];
@@ -311,12 +348,19 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout) {
   hipLaunchKernelGGL((k_restrict_resid<D, T>), dim3(nblocks(mc.L.N)), dim3(kBlock), 0, s, L, cp, dg, r, z, mc.L, rc);
   LAUNCHCHK();
   T* zc = nullptr;
-  ehdlb_status st = vcycle<D, T>(c, lvl + 1, rc, &zc);
+  ehdlb_status st = vcycle<D, T>(c, lvl + 1, rc, &zc, nullptr, nullptr);
   if (st) return st;
-  hipLaunchKernelGGL((k_prolong<D, T>), dim3(nblocks(L.N)), dim3(kBlock), 0, s, L, dg, z, mc.L, (const T*)zc,
-                     (T)c->mg_overcorrect);
-  for (int k = 0; k < nu; ++k) {
-    hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nblocks(L.N)), dim3(kBlock), 0, s, L, cp, dg, r, z, t, omega);
+  hipLaunchKernelGGL((k_prolong_smooth<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, r, z, mc.L, (const T*)zc,
+                     (T)c->mg_overcorrect, omega, t);
+  std::swap(z, t);
+  for (int k = 1; k < nu; ++k) {
+    if (k == nu - 1 && dot_part) {
+      hipLaunchKernelGGL((k_smooth_dot<D, T>), dim3(rblocks(L.N)), dim3(kBlock), 0, s, L, cp, dg, r, z, omega, t,
+                         dot_part);
+      if (dotted) *dotted = true;
+    } else {
+      hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, r, z, t, omega);
+    }
     std::swap(z, t);
   }
   LAUNCHCHK();
@@ -342,17 +386,24 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b) {
   double* red = c->ptr<double>(c->off_red);
   double* cg = c->ptr<double>(c->off_cg);
   const int nb0 = nblocks(N), rb0 = rblocks(N);
+  const double tol = c->prm.poisson_tol;
 
+  // FP64 residual check.  rel = max|r| / max|b|; the solve has converged when rel <= tol or
+  // when max|r| is at the rounding floor of x stored in T: 8 eps_T max_i sum_j |A_ij x_j|.
+  double floor_rel = 0.0;
   auto check = [&](double& rel, double& bmax) -> ehdlb_status {
     hipLaunchKernelGGL((k_true_resid<D, T>), dim3(rb0), dim3(kBlock), 0, s, m0.L, cp0, dg0, b, x, r, part);
-    hipLaunchKernelGGL((k_final<2, true>), dim3(1), dim3(kBlock), 0, s, part, rb0, red);
+    hipLaunchKernelGGL((k_final<3, true>), dim3(1), dim3(kBlock), 0, s, part, rb0, red);
     LAUNCHCHK();
-    HIPCHK(hipMemcpyAsync(c->hres, red, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->hres, red, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     bmax = c->hres[1];
     rel = bmax > 0.0 ? c->hres[0] / bmax : 0.0;
+    const double eps = sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
+    floor_rel = bmax > 0.0 ? 8.0 * eps * c->hres[2] / bmax : 0.0;
     return EHDLB_OK;
   };
+  auto done = [&](double rel) { return rel <= tol || rel <= floor_rel; };
 
   double rel = 0.0, bmax = 0.0;
   ehdlb_status st = check(rel, bmax);
@@ -364,27 +415,32 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b) {
     c->last_resid = 0.0;
     return EHDLB_OK;
   }
-  const double tol = c->prm.poisson_tol;
-  if (!(rel <= tol) && std::isfinite(rel)) {
+  if (!done(rel) && std::isfinite(rel)) {
     // coarse hierarchy (Galerkin aggregation) and the dense coarsest inverse, only when iterating
-    for (size_t l = 0; l + 1 < c->mg.size(); ++l) {
+    for (size_t l = 0; l < c->tail_first; ++l) {
       MGLevel& f = c->mg[l];
       MGLevel& g = c->mg[l + 1];
       hipLaunchKernelGGL((k_coarsen<D, T>), dim3(nblocks(g.L.N)), dim3(kBlock), 0, s, f.L, c->ptr<T>(f.cp),
                          c->ptr<T>(f.diag), g.L, c->ptr<T>(g.cp), c->ptr<T>(g.diag));
     }
-    {
-      MGLevel& g = c->mg.back();
-      hipLaunchKernelGGL((k_coarse_invert<D, T>), dim3(1), dim3(kBlock), 0, s, g.L, c->ptr<T>(g.cp),
-                         c->ptr<T>(g.diag), c->ptr<double>(c->off_inv));
-    }
+    hipLaunchKernelGGL((k_tail_setup<D, T>), dim3(1), dim3(kTailThreads), 0, s, tail_args<T>(c),
+                       c->ptr<double>(c->off_inv));
     LAUNCHCHK();
-    T* z = nullptr;
-    if ((st = vcycle<D, T>(c, 0, r, &z))) return st;
-    hipLaunchKernelGGL(k_dot<T>, dim3(rb0), dim3(kBlock), 0, s, N, r, z, part);
-    hipLaunchKernelGGL(k_final_beta, dim3(1), dim3(kBlock), 0, s, part, rb0, cg, 1);
-    hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb0), dim3(kBlock), 0, s, N, cg, z, p, 1);
-    LAUNCHCHK();
+    auto precondition = [&](bool first) -> ehdlb_status {
+      T* z = nullptr;
+      bool dotted = false;
+      ehdlb_status e = vcycle<D, T>(c, 0, r, &z, part, &dotted);
+      if (e) return e;
+      int nbp = rb0;
+      if (!dotted) {
+        hipLaunchKernelGGL(k_dot<T>, dim3(rb0), dim3(kBlock), 0, s, N, r, z, part);
+      }
+      hipLaunchKernelGGL(k_final_beta, dim3(1), dim3(kBlock), 0, s, part, nbp, cg, first ? 1 : 0);
+      hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb0), dim3(kBlock), 0, s, N, cg, z, p, first ? 1 : 0);
+      LAUNCHCHK();
+      return EHDLB_OK;
+    };
+    if ((st = precondition(true))) return st;
     int it = 0;
     const int maxit = c->prm.poisson_max_iter, every = c->prm.poisson_check_every;
     bool conv = false;
@@ -392,20 +448,23 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b) {
       ++it;
       hipLaunchKernelGGL((k_spmv<D, T, true>), dim3(rb0), dim3(kBlock), 0, s, m0.L, cp0, dg0, p, qv, part);
       hipLaunchKernelGGL(k_final_alpha, dim3(1), dim3(kBlock), 0, s, part, rb0, cg);
-      hipLaunchKernelGGL(k_cg_update<T>, dim3(nb0), dim3(kBlock), 0, s, N, cg, p, qv, x, r);
+      hipLaunchKernelGGL(k_cg_update_max<T>, dim3(rb0), dim3(kBlock), 0, s, N, cg, p, qv, x, r, part);
       LAUNCHCHK();
       if (it % every == 0 || it == maxit) {
-        if ((st = check(rel, bmax))) return st;
-        if (rel <= tol || !std::isfinite(rel)) {
-          conv = rel <= tol;
-          break;
+        // cheap trigger: the recursively updated residual; the FP64 true residual decides
+        hipLaunchKernelGGL((k_final<1, true>), dim3(1), dim3(kBlock), 0, s, part, rb0, red);
+        HIPCHK(hipMemcpyAsync(c->hres, red, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double est = c->hres[0] / bmax;
+        if (est <= tol || est <= floor_rel || !std::isfinite(est) || it == maxit) {
+          if ((st = check(rel, bmax))) return st;
+          if (done(rel) || !std::isfinite(rel)) {
+            conv = done(rel);
+            break;
+          }
         }
       }
-      if ((st = vcycle<D, T>(c, 0, r, &z))) return st;
-      hipLaunchKernelGGL(k_dot<T>, dim3(rb0), dim3(kBlock), 0, s, N, r, z, part);
-      hipLaunchKernelGGL(k_final_beta, dim3(1), dim3(kBlock), 0, s, part, rb0, cg, 0);
-      hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb0), dim3(kBlock), 0, s, N, cg, z, p, 0);
-      LAUNCHCHK();
+      if ((st = precondition(false))) return st;
     }
     c->last_iters = it;
     if (!conv) c->sticky |= 2;

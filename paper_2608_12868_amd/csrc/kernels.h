@@ -22,6 +22,7 @@ namespace ehd {
 constexpr int kBlock = 256;
 constexpr int kMaxE = 4;
 constexpr int kObs = 16;   // observable accumulators per block
+constexpr int kCoarseMax = 48;  // cells of the coarsest potential level (dense inverse)
 
 // ----------------------------------------------------------------------------- geometry helpers
 struct Dims {
@@ -32,10 +33,13 @@ struct Dims {
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 template <class L>
-__device__ __forceinline__ void neighbours(const Dims& d, int64_t node, int (&nb)[L::Q]) {
-  const int x = (int)(node % d.nx);
-  const int y = (int)((node / d.nx) % d.ny);
-  const int z = (int)(node / ((int64_t)d.nx * d.ny));
+__device__ __forceinline__ void neighbours(const Dims& d, int64_t node64, int (&nb)[L::Q]) {
+  // node counts are validated below 2^31: 32-bit index arithmetic
+  const int node = (int)node64;
+  const int x = node % d.nx;
+  const int t = node / d.nx;
+  const int y = t % d.ny;
+  const int z = t / d.ny;
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) {
     const int xx = wrap(x + L::ex[q], d.nx);
@@ -565,15 +569,39 @@ struct Level {
 };
 
 template <int D>
-__device__ __forceinline__ void cell_xyz(const Level& L, int64_t i, int& x, int& y, int& z) {
-  x = (int)(i % L.n[0]);
-  y = (int)((i / L.n[0]) % L.n[1]);
-  z = D == 3 ? (int)(i / ((int64_t)L.n[0] * L.n[1])) : 0;
+__device__ __forceinline__ void cell_xyz(const Level& L, int64_t i64, int& x, int& y, int& z) {
+  const int i = (int)i64;
+  x = i % L.n[0];
+  const int t = i / L.n[0];
+  if (D == 3) {
+    y = t % L.n[1];
+    z = t / L.n[1];
+  } else {
+    y = t;
+    z = 0;
+  }
 }
 
 template <int D>
 __device__ __forceinline__ int64_t cell_id(const Level& L, int x, int y, int z) {
-  return x + (int64_t)L.n[0] * (y + (int64_t)L.n[1] * z);
+  return (int64_t)(x + L.n[0] * (y + L.n[1] * z));
+}
+
+// index of the +axis and -axis neighbours of cell i at (x, y, z), periodic wrap, 32-bit
+template <int D>
+__device__ __forceinline__ void axis_pm(const Level& L, int i, int x, int y, int z, int ax, int& jp, int& jm) {
+  if (ax == 0) {
+    jp = x + 1 < L.n[0] ? i + 1 : i - (L.n[0] - 1);
+    jm = x > 0 ? i - 1 : i + (L.n[0] - 1);
+  } else if (ax == 1) {
+    const int s = L.n[0];
+    jp = y + 1 < L.n[1] ? i + s : i - (L.n[1] - 1) * s;
+    jm = y > 0 ? i - s : i + (L.n[1] - 1) * s;
+  } else {
+    const int s = L.n[0] * L.n[1];
+    jp = z + 1 < L.n[2] ? i + s : i - (L.n[2] - 1) * s;
+    jm = z > 0 ? i - s : i + (L.n[2] - 1) * s;
+  }
 }
 
 // Fine-level coefficients, right-hand side and permittivity from the phase fields.
@@ -624,18 +652,17 @@ __global__ __launch_bounds__(kBlock) void k_pois_setup(Dims d, const uint8_t* __
 // Grid-stride loop: the grid is capped so the partials stay few.
 template <int D, class T>
 __device__ __forceinline__ T apply_row(const Level& L, const T* __restrict__ cp, T dg, const T* __restrict__ x,
-                                       int64_t i) {
+                                       int64_t i64) {
+  const int i = (int)i64;
   int cx, cy, cz;
   cell_xyz<D>(L, i, cx, cy, cz);
+  const int N = (int)L.N;
   T r = dg * x[i];
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) {
-    int xp = cx, yp = cy, zp = cz, xm = cx, ym = cy, zm = cz;
-    if (ax == 0) { xp = wrap(cx + 1, L.n[0]); xm = wrap(cx - 1, L.n[0]); }
-    if (ax == 1) { yp = wrap(cy + 1, L.n[1]); ym = wrap(cy - 1, L.n[1]); }
-    if (ax == 2) { zp = wrap(cz + 1, L.n[2]); zm = wrap(cz - 1, L.n[2]); }
-    const int64_t jp = cell_id<D>(L, xp, yp, zp), jm = cell_id<D>(L, xm, ym, zm);
-    r -= cp[(int64_t)ax * L.N + i] * x[jp] + cp[(int64_t)ax * L.N + jm] * x[jm];
+    int jp, jm;
+    axis_pm<D>(L, i, cx, cy, cz, ax, jp, jm);
+    r -= cp[ax * N + i] * x[jp] + cp[ax * N + jm] * x[jm];
   }
   return r;
 }
@@ -670,19 +697,312 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(Level L, const T* __restrict_
     z_out[i] = omega * r[i] / dg;
     return;
   }
+  z_out[i] = z_in[i] + omega * (r[i] - apply_row<D, T>(L, cp, dg, z_in, i)) / dg;
+}
+
+// ---- fused smoothing kernels of the V-cycle (damped Jacobi, weight w) ----------------------
+template <int D>
+__device__ __forceinline__ void axis_nbrs(const Level& L, int64_t i, int ax, int64_t& jp, int64_t& jm) {
   int cx, cy, cz;
   cell_xyz<D>(L, i, cx, cy, cz);
-  T az = dg * z_in[i];
+  int p, m;
+  axis_pm<D>(L, (int)i, cx, cy, cz, ax, p, m);
+  jp = p;
+  jm = m;
+}
+
+// Two sweeps from zero in one pass: z1 = w r/d, z2 = z1 + w (r - A z1)/d, with z1 at the
+// neighbours recomputed from r and d there.
+template <int D, class T>
+__global__ __launch_bounds__(kBlock) void k_smooth2(Level L, const T* __restrict__ cp, const T* __restrict__ dg,
+                                                     const T* __restrict__ r, T* __restrict__ z, T w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int)L.N) return;
+  const T d = dg[i];
+  if (d == T(0)) {
+    z[i] = T(0);
+    return;
+  }
+  const int N = (int)L.N;
+  int cx, cy, cz;
+  cell_xyz<D>(L, i, cx, cy, cz);
+  const T z1 = w * r[i] / d;
+  T off = 0;  // sum over faces c * z1(nb)
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) {
+    int jp, jm;
+    axis_pm<D>(L, i, cx, cy, cz, ax, jp, jm);
+    const T cpp = cp[ax * N + i], cpm = cp[ax * N + jm];
+    if (cpp != T(0)) off += cpp * w * r[jp] / dg[jp];
+    if (cpm != T(0)) off += cpm * w * r[jm] / dg[jm];
+  }
+  z[i] = z1 + w * (r[i] - d * z1 + off) / d;
+}
+
+// Prolongation fused with one sweep: z' = z + a zc(parent) (on the fly at the neighbours too),
+// z_out = z' + w (r - A z')/d.
+template <int D, class T>
+__global__ __launch_bounds__(kBlock) void k_prolong_smooth(Level L, const T* __restrict__ cp, const T* __restrict__ dg,
+                                                            const T* __restrict__ r, const T* __restrict__ z,
+                                                            Level Lc, const T* __restrict__ zc, T a, T w,
+                                                            T* __restrict__ zo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int)L.N) return;
+  const T d = dg[i];
+  if (d == T(0)) {
+    zo[i] = T(0);
+    return;
+  }
+  const int N = (int)L.N;
+  int cx, cy, cz;
+  cell_xyz<D>(L, i, cx, cy, cz);
+  // parent of a cell at (x, y, z)
+  auto par = [&](int x, int y, int z) -> int { return (x >> 1) + Lc.n[0] * ((y >> 1) + Lc.n[1] * (z >> 1)); };
+  const T zi = z[i] + a * zc[par(cx, cy, cz)];
+  T az = d * zi;
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    int jp, jm;
+    axis_pm<D>(L, i, cx, cy, cz, ax, jp, jm);
+    const T cpp = cp[ax * N + i], cpm = cp[ax * N + jm];
     int xp = cx, yp = cy, zp = cz, xm = cx, ym = cy, zm = cz;
     if (ax == 0) { xp = wrap(cx + 1, L.n[0]); xm = wrap(cx - 1, L.n[0]); }
     if (ax == 1) { yp = wrap(cy + 1, L.n[1]); ym = wrap(cy - 1, L.n[1]); }
     if (ax == 2) { zp = wrap(cz + 1, L.n[2]); zm = wrap(cz - 1, L.n[2]); }
-    const int64_t jp = cell_id<D>(L, xp, yp, zp), jm = cell_id<D>(L, xm, ym, zm);
-    az -= cp[(int64_t)ax * L.N + i] * z_in[jp] + cp[(int64_t)ax * L.N + jm] * z_in[jm];
+    // a nonzero face coefficient implies an active neighbour
+    if (cpp != T(0)) az -= cpp * (z[jp] + a * zc[par(xp, yp, zp)]);
+    if (cpm != T(0)) az -= cpm * (z[jm] + a * zc[par(xm, ym, zm)]);
   }
-  z_out[i] = z_in[i] + omega * (r[i] - az) / dg;
+  zo[i] = zi + w * (r[i] - az) / d;
+}
+
+// One sweep with per-block FP64 partials of r.z_out (grid-stride, capped grid)
+template <int D, class T>
+__global__ __launch_bounds__(kBlock) void k_smooth_dot(Level L, const T* __restrict__ cp, const T* __restrict__ dg,
+                                                        const T* __restrict__ r, const T* __restrict__ z, T w,
+                                                        T* __restrict__ zo, double* __restrict__ part) {
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
+    const T d = dg[i];
+    T v = T(0);
+    if (d != T(0)) v = z[i] + w * (r[i] - apply_row<D, T>(L, cp, d, z, i)) / d;
+    zo[i] = v;
+    acc[0] += (double)r[i] * (double)v;
+  }
+  block_reduce<1, false>(acc, part + blockIdx.x);
+}
+
+// x += alpha p, r -= alpha q, with per-block FP64 partials of max|r| (grid-stride)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_cg_update_max(int64_t N, const double* __restrict__ s,
+                                                           const T* __restrict__ p, const T* __restrict__ q,
+                                                           T* __restrict__ x, T* __restrict__ r,
+                                                           double* __restrict__ part) {
+  const T al = (T)s[1];
+  double m[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += al * p[i];
+    const T rn = r[i] - al * q[i];
+    r[i] = rn;
+    m[0] = fmax(m[0], fabs((double)rn));
+  }
+  block_reduce<1, true>(m, part + blockIdx.x);
+}
+
+// ---- V-cycle tail: every level from `first` to the coarsest in one workgroup ---------------
+constexpr int kMaxLevels = 16;
+constexpr int kTailThreads = 1024;
+template <class T>
+struct TailArgs {
+  int first, last;  // level indices handled here; last = coarsest
+  Level L[kMaxLevels];
+  T* cp[kMaxLevels];
+  T* dg[kMaxLevels];
+  T* r[kMaxLevels];
+  T* z[kMaxLevels];
+  T* t[kMaxLevels];
+  const double* inv;  // dense inverse of the coarsest operator
+  T w, a;
+  int nu;
+};
+
+template <int D, class T>
+__device__ void tail_sweep(const Level& L, const T* cp, const T* dg, const T* r, const T* zin, T* zout, T w) {
+  for (int64_t i = threadIdx.x; i < L.N; i += blockDim.x) {
+    const T d = dg[i];
+    if (d == T(0)) {
+      zout[i] = T(0);
+      continue;
+    }
+    zout[i] = zin ? zin[i] + w * (r[i] - apply_row<D, T>(L, cp, d, zin, i)) / d : w * r[i] / d;
+  }
+}
+
+template <int D, class T>
+__global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> a) {
+  // descend
+  for (int l = a.first; l < a.last; ++l) {
+    const Level& L = a.L[l];
+    T* z = a.z[l];
+    T* t = a.t[l];
+    tail_sweep<D, T>(L, a.cp[l], a.dg[l], a.r[l], nullptr, z, a.w);
+    __syncthreads();
+    for (int k = 1; k < a.nu; ++k) {
+      tail_sweep<D, T>(L, a.cp[l], a.dg[l], a.r[l], z, t, a.w);
+      __syncthreads();
+      T* tmp = z; z = t; t = tmp;
+    }
+    // keep the result in a.z[l]
+    if (z != a.z[l]) {
+      for (int64_t i = threadIdx.x; i < L.N; i += blockDim.x) a.z[l][i] = z[i];
+      __syncthreads();
+    }
+    const Level& Lc = a.L[l + 1];
+    for (int64_t I = threadIdx.x; I < Lc.N; I += blockDim.x) {
+      int X, Y, Z;
+      cell_xyz<D>(Lc, I, X, Y, Z);
+      T acc = 0;
+      for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            const int cx = 2 * X + dx, cy = 2 * Y + dy, cz = 2 * Z + dz;
+            if (cx >= L.n[0] || cy >= L.n[1] || (D == 3 && cz >= L.n[2])) continue;
+            const int64_t i = cell_id<D>(L, cx, cy, cz);
+            const T d = a.dg[l][i];
+            if (d == T(0)) continue;
+            acc += a.r[l][i] - apply_row<D, T>(L, a.cp[l], d, a.z[l], i);
+          }
+      a.r[l + 1][I] = acc;
+    }
+    __syncthreads();
+  }
+  // coarsest: dense inverse
+  {
+    const Level& L = a.L[a.last];
+    const int n = (int)L.N;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) acc += a.inv[i * n + j] * (double)a.r[a.last][j];
+      a.z[a.last][i] = a.dg[a.last][i] == T(0) ? T(0) : (T)acc;
+    }
+    __syncthreads();
+  }
+  // ascend
+  for (int l = a.last - 1; l >= a.first; --l) {
+    const Level& L = a.L[l];
+    const Level& Lc = a.L[l + 1];
+    T* z = a.z[l];
+    T* t = a.t[l];
+    for (int64_t i = threadIdx.x; i < L.N; i += blockDim.x) {
+      if (a.dg[l][i] == T(0)) continue;
+      int cx, cy, cz;
+      cell_xyz<D>(L, i, cx, cy, cz);
+      z[i] += a.a * a.z[l + 1][cell_id<D>(Lc, cx >> 1, cy >> 1, cz >> 1)];
+    }
+    __syncthreads();
+    for (int k = 0; k < a.nu; ++k) {
+      tail_sweep<D, T>(L, a.cp[l], a.dg[l], a.r[l], z, t, a.w);
+      __syncthreads();
+      T* tmp = z; z = t; t = tmp;
+    }
+    if (z != a.z[l]) {
+      for (int64_t i = threadIdx.x; i < L.N; i += blockDim.x) a.z[l][i] = z[i];
+      __syncthreads();
+    }
+  }
+}
+
+// Tail setup: Galerkin coarsening of levels first+1..last and the dense coarsest inverse
+// (Gauss-Jordan, FP64, one workgroup).
+template <int D, class T>
+__device__ void coarsen_level(const Level& Lf, const T* cpf, const T* diagf, const Level& Lc, T* cpc, T* diagc) {
+  for (int64_t I = threadIdx.x; I < Lc.N; I += blockDim.x) {
+    int X, Y, Z;
+    cell_xyz<D>(Lc, I, X, Y, Z);
+    T dg = 0;
+    T c[3] = {0, 0, 0};
+    for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const int cx = 2 * X + dx, cy = 2 * Y + dy, cz = 2 * Z + dz;
+          if (cx >= Lf.n[0] || cy >= Lf.n[1] || (D == 3 && cz >= Lf.n[2])) continue;
+          const int64_t i = cell_id<D>(Lf, cx, cy, cz);
+          dg += diagf[i];
+          for (int ax = 0; ax < D; ++ax) {
+            const T f = cpf[(int64_t)ax * Lf.N + i];
+            int jx = cx, jy = cy, jz = cz;
+            if (ax == 0) jx = wrap(cx + 1, Lf.n[0]);
+            if (ax == 1) jy = wrap(cy + 1, Lf.n[1]);
+            if (ax == 2) jz = wrap(cz + 1, Lf.n[2]);
+            if ((jx >> 1) == X && (jy >> 1) == Y && (jz >> 1) == Z)
+              dg -= T(2) * f;
+            else
+              c[ax] += f;
+          }
+        }
+    diagc[I] = dg;
+    for (int ax = 0; ax < D; ++ax) cpc[(int64_t)ax * Lc.N + I] = c[ax];
+  }
+}
+
+template <int D, class T>
+__global__ __launch_bounds__(kTailThreads) void k_tail_setup(TailArgs<T> a, double* __restrict__ inv) {
+  for (int l = a.first; l < a.last; ++l) {
+    coarsen_level<D, T>(a.L[l], a.cp[l], a.dg[l], a.L[l + 1], a.cp[l + 1], a.dg[l + 1]);
+    __syncthreads();
+  }
+  __shared__ double A[kCoarseMax][2 * kCoarseMax + 1];
+  const Level& L = a.L[a.last];
+  const int n = (int)L.N;
+  const T* cp = a.cp[a.last];
+  const T* dg = a.dg[a.last];
+  // augmented [A | I]
+  for (int k = threadIdx.x; k < n * 2 * n; k += blockDim.x) {
+    const int r = k / (2 * n), c = k % (2 * n);
+    A[r][c] = c >= n ? (c - n == r ? 1.0 : 0.0) : 0.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double d = dg[i];
+    A[i][i] = d == 0.0 ? 1.0 : d;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < n; ++i) {
+      if (dg[i] == T(0)) continue;
+      int cx, cy, cz;
+      cell_xyz<D>(L, i, cx, cy, cz);
+      for (int ax = 0; ax < D; ++ax) {
+        int xp = cx, yp = cy, zp = cz;
+        if (ax == 0) xp = wrap(cx + 1, L.n[0]);
+        if (ax == 1) yp = wrap(cy + 1, L.n[1]);
+        if (ax == 2) zp = wrap(cz + 1, L.n[2]);
+        const int j = (int)cell_id<D>(L, xp, yp, zp);
+        const double c = cp[(int64_t)ax * L.N + i];
+        if (c != 0.0 && j != i) {
+          A[i][j] -= c;
+          A[j][i] -= c;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double piv = A[k][k];
+    __syncthreads();
+    for (int c = threadIdx.x; c < 2 * n; c += blockDim.x) A[k][c] /= piv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * 2 * n; e += blockDim.x) {
+      const int r = e / (2 * n), c = e % (2 * n);
+      if (r == k || c == k) continue;
+      A[r][c] -= A[r][k] * A[k][c];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += blockDim.x)
+      if (r != k) A[r][k] = 0.0;
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < n * n; k += blockDim.x) inv[k] = A[k / n][n + k % n];
 }
 
 // Restriction of the residual r - A z to the coarse level (sum over the children), fused:
@@ -771,80 +1091,6 @@ __global__ __launch_bounds__(kBlock) void k_coarsen(Level Lf, const T* __restric
   for (int ax = 0; ax < D; ++ax) cpc[(int64_t)ax * Lc.N + I] = c[ax];
 }
 
-// Coarsest level: dense inverse by Gauss-Jordan (SPD, no pivoting) in one block, FP64.
-// Inactive cells (diag 0) become identity rows.  n <= kCoarseMax.
-constexpr int kCoarseMax = 48;
-template <int D, class T>
-__global__ __launch_bounds__(kBlock) void k_coarse_invert(Level L, const T* __restrict__ cp,
-                                                           const T* __restrict__ diag, double* __restrict__ inv) {
-  __shared__ double A[kCoarseMax][kCoarseMax + 1];
-  __shared__ double B[kCoarseMax][kCoarseMax + 1];
-  const int n = (int)L.N;
-  for (int k = threadIdx.x; k < n * n; k += blockDim.x) {
-    const int r = k / n, c = k % n;
-    A[r][c] = 0.0;
-    B[r][c] = r == c ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < n; ++i) {
-      const double dg = diag[i];
-      if (dg == 0.0) {
-        A[i][i] = 1.0;
-        continue;
-      }
-      A[i][i] += dg;
-      int cx, cy, cz;
-      cell_xyz<D>(L, i, cx, cy, cz);
-      for (int ax = 0; ax < D; ++ax) {
-        int xp = cx, yp = cy, zp = cz;
-        if (ax == 0) xp = wrap(cx + 1, L.n[0]);
-        if (ax == 1) yp = wrap(cy + 1, L.n[1]);
-        if (ax == 2) zp = wrap(cz + 1, L.n[2]);
-        const int j = (int)cell_id<D>(L, xp, yp, zp);
-        const double c = cp[(int64_t)ax * L.N + i];
-        if (c != 0.0 && j != i) {
-          A[i][j] -= c;
-          A[j][i] -= c;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double piv = A[k][k];
-    __syncthreads();
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-      A[k][c] /= piv;
-      B[k][c] /= piv;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const int r = e / n, c = e % n;
-      if (r == k) continue;
-      const double f = A[r][k];
-      if (c != k) A[r][c] -= f * A[k][c];
-      B[r][c] -= f * B[k][c];
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < n; r += blockDim.x)
-      if (r != k) A[r][k] = 0.0;
-    __syncthreads();
-  }
-  for (int k = threadIdx.x; k < n * n; k += blockDim.x) inv[k] = B[k / n][k % n];
-}
-
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_coarse_apply(int n, const double* __restrict__ inv,
-                                                          const T* __restrict__ diag, const T* __restrict__ r,
-                                                          T* __restrict__ z) {
-  const int i = threadIdx.x;
-  if (i >= n) return;
-  double acc = 0.0;
-  for (int j = 0; j < n; ++j) acc += inv[i * n + j] * (double)r[j];
-  z[i] = diag[i] == T(0) ? T(0) : (T)acc;
-}
-
 // CG scalars live on the device: s[0] = rz, s[1] = alpha, s[2] = beta.
 // x += alpha p, r -= alpha q
 template <class T>
@@ -877,12 +1123,13 @@ __global__ __launch_bounds__(kBlock) void k_dot(int64_t N, const T* __restrict__
   block_reduce<1, false>(v, part + blockIdx.x);
 }
 
-// FP64 true residual: r = b - A x (stored in T), per-block partials of max|r| and max|b| (grid-stride)
+// FP64 true residual: r = b - A x (stored in T), per-block partials of max|r|, max|b| and
+// max_i sum_j |A_ij x_j| (the rounding floor of the residual of an x stored in T) (grid-stride)
 template <int D, class T>
 __global__ __launch_bounds__(kBlock) void k_true_resid(Level L, const T* __restrict__ cp, const T* __restrict__ diag,
                                                         const T* __restrict__ b, const T* __restrict__ x,
                                                         T* __restrict__ r, double* __restrict__ part) {
-  double m[2] = {0.0, 0.0};
+  double m[3] = {0.0, 0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
     const double dg = diag[i];
     double res = 0.0;
@@ -890,6 +1137,7 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Level L, const T* __restr
       int cx, cy, cz;
       cell_xyz<D>(L, i, cx, cy, cz);
       double ax_ = dg * (double)x[i];
+      double mag = fabs(ax_);
 #pragma unroll
       for (int ax = 0; ax < D; ++ax) {
         int xp = cx, yp = cy, zp = cz, xm = cx, ym = cy, zm = cz;
@@ -897,15 +1145,19 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Level L, const T* __restr
         if (ax == 1) { yp = wrap(cy + 1, L.n[1]); ym = wrap(cy - 1, L.n[1]); }
         if (ax == 2) { zp = wrap(cz + 1, L.n[2]); zm = wrap(cz - 1, L.n[2]); }
         const int64_t jp = cell_id<D>(L, xp, yp, zp), jm = cell_id<D>(L, xm, ym, zm);
-        ax_ -= (double)cp[(int64_t)ax * L.N + i] * (double)x[jp] + (double)cp[(int64_t)ax * L.N + jm] * (double)x[jm];
+        const double tp = (double)cp[(int64_t)ax * L.N + i] * (double)x[jp];
+        const double tm = (double)cp[(int64_t)ax * L.N + jm] * (double)x[jm];
+        ax_ -= tp + tm;
+        mag += fabs(tp) + fabs(tm);
       }
       res = (double)b[i] - ax_;
       m[1] = fmax(m[1], fabs((double)b[i]));
+      m[2] = fmax(m[2], mag);
     }
     r[i] = (T)res;
     m[0] = fmax(m[0], fabs(res));
   }
-  block_reduce<2, true>(m, part + (int64_t)blockIdx.x * 2);
+  block_reduce<3, true>(m, part + (int64_t)blockIdx.x * 3);
 }
 
 // Final reduction of p.q partials fused with alpha = rz / pq  (s[0] = rz, s[1] = alpha)
