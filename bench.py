@@ -46,8 +46,9 @@ def step_kernel_bytes(dim, ehd, tsize):
 
 
 def source_hash():
+    """Hash of the fused collide-stream kernel's source (its own header and the lattice tables)."""
     h = hashlib.sha256()
-    for n in ("kernels.h", "lattice.h"):
+    for n in ("step.h", "lattice.h"):
         with open(os.path.join(ROOT, "paper_2608_12868_amd", "csrc", n), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -64,6 +65,23 @@ def measured_traffic(workload):
     if d.get("source_hash") != source_hash():
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def copy_ceiling(nbytes=1 << 30, reps=10):
+    """Practical HBM ceiling: a plain device-to-device copy of nbytes (read + write counted),
+    timed with HIP events on torch's stream."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return dict(bytes_per_copy=2 * nbytes, gbs=2 * nbytes / (ms * 1e-3) / 1e9)
 
 
 def cpu_baseline(budget_s=12.0):
@@ -93,6 +111,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also time a plain 1 GiB device copy (practical bandwidth ceiling; the "
+                         "calibration kernel of the rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the step is built for a single MI355X (multi-GPU slab "
@@ -152,6 +173,8 @@ def main():
         "potential_iters_last_step": obs["poisson_iters"],
         "potential_residual_last_step": obs["poisson_residual"],
     }
+    if args.copy_probe:
+        out["copy_ceiling"] = copy_ceiling()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -20,6 +20,7 @@
 //       cotangents of step t
 #pragma once
 #include "kernels.h"
+#include "step.h"
 
 namespace ehd {
 
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
   constexpr int P = ML::P;
-  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t node = gidx();
   double vloc[kMaxE] = {0.0, 0.0, 0.0, 0.0};
   const int64_t N = a.d.N;
   const bool active = node < N && a.flags[node] == 0;
@@ -539,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(Dims d, const uint8_t* __restr
                                                    T* __restrict__ lphi_out, T* __restrict__ lpot_out) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
-  const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t y = gidx();
   if (y >= d.N) return;
   const int64_t N = d.N;
   const bool fluid = flags[y] == 0;
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_cd(Dims d, const uint8_t* __rest
   using RL = RecLayout<L>;
   constexpr int Q = L::Q;
   constexpr int D = L::D;
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t x = gidx();
   double vloc[kMaxE] = {0.0, 0.0, 0.0, 0.0};
   const int64_t N = d.N;
   if (x < N) {
@@ -713,7 +714,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_terminal(Dims d, const uint8_t* 
                                                           T* __restrict__ lqp) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t x = gidx();
   if (x >= d.N) return;
   const int64_t N = d.N;
   const int F = EHD ? 5 : 4;

@@ -11,6 +11,7 @@
 
 #include "../../include/ehdlb.h"
 #include "kernels.h"
+#include "step.h"
 #include "adjoint.h"
 
 using namespace ehd;
@@ -31,7 +32,7 @@ int rblocks(int64_t n) { return std::min(nblocks(n), kRedBlocks); }
 
 struct MGLevel {
   Level L;
-  size_t cp, diag, r, z, t;  // byte offsets
+  size_t cp, diag, dinv, r, z, t;  // byte offsets
 };
 
 }  // namespace
@@ -224,6 +225,7 @@ static void plan_layout(ehdlb_ctx* c) {
     m0.L = L0;
     m0.cp = take((size_t)c->D * N * ts);
     m0.diag = take(N * ts);
+    m0.dinv = take(N * ts);
     m0.r = c->off_r;
     m0.z = take(N * ts);
     m0.t = take(N * ts);
@@ -238,6 +240,7 @@ static void plan_layout(ehdlb_ctx* c) {
       m.L = l;
       m.cp = take((size_t)c->D * l.N * ts);
       m.diag = take(l.N * ts);
+      m.dinv = take(l.N * ts);
       m.r = take(l.N * ts);
       m.z = take(l.N * ts);
       m.t = take(l.N * ts);
@@ -297,6 +300,7 @@ static TailArgs<T> tail_args(ehdlb_ctx* c) {
     t.L[l] = m.L;
     t.cp[l] = c->ptr<T>(m.cp);
     t.dg[l] = c->ptr<T>(m.diag);
+    t.di[l] = c->ptr<T>(m.dinv);
     t.r[l] = c->ptr<T>(m.r);
     t.z[l] = c->ptr<T>(m.z);
     t.t[l] = c->ptr<T>(m.t);
@@ -329,18 +333,19 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot
   }
   T* cp = c->ptr<T>(m.cp);
   T* dg = c->ptr<T>(m.diag);
+  T* di = c->ptr<T>(m.dinv);
   const T omega = (T)c->mg_omega;
   const int nu = c->mg_nu;
   T* z = c->ptr<T>(m.z);
   T* t = c->ptr<T>(m.t);
   const int nb = nblocks(L.N);
   if (nu >= 2) {
-    hipLaunchKernelGGL((k_smooth2<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, r, z, omega);
+    hipLaunchKernelGGL((k_smooth2<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, di, r, z, omega);
   } else {
-    hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, r, (const T*)nullptr, z, omega);
+    hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, di, r, (const T*)nullptr, z, omega);
   }
   for (int k = 2; k < nu; ++k) {
-    hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, r, z, t, omega);
+    hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, di, r, z, t, omega);
     std::swap(z, t);
   }
   MGLevel& mc = c->mg[lvl + 1];
@@ -350,16 +355,16 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot
   T* zc = nullptr;
   ehdlb_status st = vcycle<D, T>(c, lvl + 1, rc, &zc, nullptr, nullptr);
   if (st) return st;
-  hipLaunchKernelGGL((k_prolong_smooth<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, r, z, mc.L, (const T*)zc,
+  hipLaunchKernelGGL((k_prolong_smooth<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, di, r, z, mc.L, (const T*)zc,
                      (T)c->mg_overcorrect, omega, t);
   std::swap(z, t);
   for (int k = 1; k < nu; ++k) {
     if (k == nu - 1 && dot_part) {
-      hipLaunchKernelGGL((k_smooth_dot<D, T>), dim3(rblocks(L.N)), dim3(kBlock), 0, s, L, cp, dg, r, z, omega, t,
+      hipLaunchKernelGGL((k_smooth_dot<D, T>), dim3(rblocks(L.N)), dim3(kBlock), 0, s, L, cp, dg, di, r, z, omega, t,
                          dot_part);
       if (dotted) *dotted = true;
     } else {
-      hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, r, z, t, omega);
+      hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, di, r, z, t, omega);
     }
     std::swap(z, t);
   }
@@ -417,11 +422,14 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b) {
   }
   if (!done(rel) && std::isfinite(rel)) {
     // coarse hierarchy (Galerkin aggregation) and the dense coarsest inverse, only when iterating
+    hipLaunchKernelGGL(k_dinv<T>, dim3(nb0), dim3(kBlock), 0, s, N, (const T*)dg0, c->ptr<T>(m0.dinv));
     for (size_t l = 0; l < c->tail_first; ++l) {
       MGLevel& f = c->mg[l];
       MGLevel& g = c->mg[l + 1];
       hipLaunchKernelGGL((k_coarsen<D, T>), dim3(nblocks(g.L.N)), dim3(kBlock), 0, s, f.L, c->ptr<T>(f.cp),
                          c->ptr<T>(f.diag), g.L, c->ptr<T>(g.cp), c->ptr<T>(g.diag));
+      hipLaunchKernelGGL(k_dinv<T>, dim3(nblocks(g.L.N)), dim3(kBlock), 0, s, g.L.N, (const T*)c->ptr<T>(g.diag),
+                         c->ptr<T>(g.dinv));
     }
     hipLaunchKernelGGL((k_tail_setup<D, T>), dim3(1), dim3(kTailThreads), 0, s, tail_args<T>(c),
                        c->ptr<double>(c->off_inv));

@@ -32,6 +32,27 @@ struct Dims {
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b mod 8).
+// Remap so that each XCD processes a contiguous eighth of the logical blocks: the stencil
+// neighbours of a block (rows and planes away) then sit in the same XCD's L2.
+constexpr int kXcd = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int per = nb / kXcd;
+  if (b >= per * kXcd) return b;
+  return (b % kXcd) * per + b / kXcd;
+}
+// global thread index over nodes (plain block order: the XCD-aware order did not help the
+// one-thread-per-node kernels on MI355X and slowed the fused step by a few percent)
+__device__ __forceinline__ int64_t gidx() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+// contiguous chunk [lo, hi) of a grid-stride kernel's index space for this block (fixed, so
+// reductions keep a fixed order); chunks are multiples of the block size
+__device__ __forceinline__ void chunk_range(int64_t n, int64_t& lo, int64_t& hi) {
+  const int64_t nb = gridDim.x;
+  const int64_t per = ((n + nb - 1) / nb + blockDim.x - 1) / blockDim.x * blockDim.x;
+  lo = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
+  hi = lo + per < n ? lo + per : n;
+}
+
 template <class L>
 __device__ __forceinline__ void neighbours(const Dims& d, int64_t node64, int (&nb)[L::Q]) {
   // node counts are validated below 2^31: 32-bit index arithmetic
@@ -107,7 +128,7 @@ template <class L, class T, bool EHD>
 __global__ __launch_bounds__(kBlock) void k_moments(Dims d, const uint8_t* __restrict__ flags,
                                                      const T* __restrict__ pop, T* __restrict__ phi,
                                                      T* __restrict__ rho, T* __restrict__ drho) {
-  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t node = gidx();
   if (node >= d.N) return;
   const int64_t N = d.N;
   const bool fluid = flags[node] == 0;
@@ -156,295 +177,6 @@ __global__ __launch_bounds__(kBlock) void k_ghosts(int64_t N, int G, const int32
   phi[2 * N + s] = p3 - l * r3;
 }
 
-// ----------------------------------------------------------------------------- fused collide-stream
-template <class L, class T, bool EHD, bool STORE = false>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
-  using ML = MomLayout<L>;
-  constexpr int Q = L::Q;
-  constexpr int D = L::D;
-  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= a.d.N) return;
-  if (a.flags[node] != 0) return;
-  const int64_t N = a.d.N;
-  const Phys<T>& p = a.p;
-  const T cs2 = T(1) / T(3);
-
-  int nb[Q];
-  neighbours<L>(a.d, node, nb);
-
-  // ---- a3: isotropic gradient and Laplacian of the three phase fields
-  T pc[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) pc[i] = a.phi[(int64_t)i * N + node];
-  T gr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  T lap[3] = {0, 0, 0};
-  uint32_t solid = 0;
-  T sig_ax[2 * D];  // conductivity at the axis neighbours (+a, -a)
-  uint8_t fl_ax[2 * D];
-#pragma unroll
-  for (int q = 1; q < Q; ++q) {
-    const int m = nb[q];
-    const uint8_t fm = a.flags[m];
-    if (fm) solid |= 1u << q;
-    const T w = T(L::w36[q]) / T(36);
-    T v[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      v[i] = a.phi[(int64_t)i * N + m];
-      gr[i][0] += w * T(L::ex[q]) * v[i];
-      gr[i][1] += w * T(L::ey[q]) * v[i];
-      if (D == 3) gr[i][2] += w * T(L::ez[q]) * v[i];
-      lap[i] += w * (v[i] - pc[i]);
-    }
-#pragma unroll
-    for (int ax = 0; ax < D; ++ax) {
-      if (q == L::axp[ax] || q == L::axm[ax]) {
-        const int k = 2 * ax + (q == L::axp[ax] ? 0 : 1);
-        sig_ax[k] = p.cond[0] * v[0] + p.cond[1] * v[1] + p.cond[2] * v[2];
-        fl_ax[k] = fm;
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) gr[i][c] *= T(3);
-    lap[i] *= T(6);
-  }
-
-  // ---- a4: chemical potentials (Eq. 10) and capillary force F_s = sum mu_i grad Phi_i
-  const T triple = pc[0] * pc[1] * pc[2];
-  T F[3] = {p.body[0], p.body[1], p.body[2]};
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const T mu = T(24) * p.ups[i] / p.W * pc[i] * (pc[i] - T(1)) * (pc[i] - T(0.5)) -
-                 T(24) * p.upsT / p.W * triple - T(0.75) * p.ups[i] * p.W * lap[i];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) F[c] += mu * gr[i][c];
-  }
-
-  // ---- a6: electric force (Eq. 12) and Ohmic source of the charge equation
-  T Qs = 0;
-  if (EHD) {
-    const T phx = a.pot[node];
-    const T sigx = p.cond[0] * pc[0] + p.cond[1] * pc[1] + p.cond[2] * pc[2];
-    T E[3] = {0, 0, 0};
-#pragma unroll
-    for (int ax = 0; ax < D; ++ax) {
-      T side[2];
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int q = k == 0 ? L::axp[ax] : L::axm[ax];
-        const uint8_t fm = fl_ax[2 * ax + k];
-        if (fm == 0) {
-          const T v = a.pot[nb[q]];
-          side[k] = v;
-          Qs += T(0.5) * (sigx + sig_ax[2 * ax + k]) * (v - phx);
-        } else if (fm == 1 || fm >= 3) {
-          const T pd = fm == 1 ? T(0) : a.volts.v[fm - 3];
-          side[k] = T(2) * pd - phx;
-          Qs += T(2) * sigx * (pd - phx);
-        } else {
-          side[k] = phx;
-        }
-      }
-      E[ax] = -T(0.5) * (side[0] - side[1]);
-    }
-    const T e2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
-    const T rq = a.rho[node];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const T ge = p.eps[0] * gr[0][c] + p.eps[1] * gr[1][c] + p.eps[2] * gr[2][c];
-      F[c] += rq * E[c] - T(0.5) * e2 * ge;
-    }
-  }
-
-  auto emit = [&](int fam, int q, T val) {
-    if ((solid >> q) & 1u)
-      a.pop_out[((int64_t)fam * Q + L::opp[q]) * N + node] = val;
-    else
-      a.pop_out[((int64_t)fam * Q + q) * N + nb[q]] = val;
-  };
-
-  // ---- a7: flow.  u = j + F/2, incompressible equilibrium, Guo source, raw-moment MRT
-  // with second-order moments at 1/tau(x) and all higher moments at 1.
-  T u[3];
-  {
-    T gq[Q];
-    T drho = 0, j[3] = {0, 0, 0};
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      gq[q] = a.pop_in[(int64_t)q * N + node];
-      drho += gq[q];
-      j[0] += T(L::ex[q]) * gq[q];
-      j[1] += T(L::ey[q]) * gq[q];
-      j[2] += T(L::ez[q]) * gq[q];
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) u[c] = j[c] + T(0.5) * F[c];
-    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-    const T nu = p.nu[0] * pc[0] + p.nu[1] * pc[1] + p.nu[2] * pc[2];
-    const T s_nu = T(1) / (T(0.5) + T(3) * nu);
-    // second-order raw moments of g - g_eq + F_q/2
-    T Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const T exq = T(L::ex[q]), eyq = T(L::ey[q]), ezq = T(L::ez[q]);
-      const T w = T(L::w36[q]) / T(36);
-      const T eu = exq * u[0] + eyq * u[1] + ezq * u[2];
-      const T eF = exq * F[0] + eyq * F[1] + ezq * F[2];
-      const T geq = w * (drho + T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu);
-      const T fq = w * (T(3) * (eF - uF) + T(9) * eu * eF);
-      const T dq = gq[q] - geq + T(0.5) * fq;
-      Pxx += exq * exq * dq;
-      Pyy += eyq * eyq * dq;
-      Pxy += exq * eyq * dq;
-      if (D == 3) {
-        Pzz += ezq * ezq * dq;
-        Pxz += exq * ezq * dq;
-        Pyz += eyq * ezq * dq;
-      }
-    }
-    const T om = T(1) - s_nu;
-    if (STORE) {
-      T* r = a.rec;
-      r[(int64_t)ML::DRHO * N + node] = drho;
-#pragma unroll
-      for (int c = 0; c < D; ++c) r[(int64_t)(ML::J + c) * N + node] = j[c];
-      r[(int64_t)(ML::PI + 0) * N + node] = Pxx;
-      r[(int64_t)(ML::PI + 1) * N + node] = Pyy;
-      if (D == 2) {
-        r[(int64_t)(ML::PI + 2) * N + node] = Pxy;
-      } else {
-        r[(int64_t)(ML::PI + 2) * N + node] = Pzz;
-        r[(int64_t)(ML::PI + 3) * N + node] = Pxy;
-        r[(int64_t)(ML::PI + 4) * N + node] = Pxz;
-        r[(int64_t)(ML::PI + 5) * N + node] = Pyz;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
-      const T exq = T(ix), eyq = T(iy), ezq = T(iz);
-      const T w = T(L::w36[q]) / T(36);
-      const T eu = exq * u[0] + eyq * u[1] + ezq * u[2];
-      const T eF = exq * F[0] + eyq * F[1] + ezq * F[2];
-      const T geq = w * (drho + T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu);
-      const T fq = w * (T(3) * (eF - uF) + T(9) * eu * eF);
-      // columns of M^-1 of the monomial basis for the second-order moments:
-      // xx: +1/2 on the +-x links, -1 at rest; xy: e_x e_y / 4 on the xy-plane diagonals
-      T corr;
-      const int l2 = ix * ix + iy * iy + iz * iz;
-      if (l2 == 0) {
-        corr = -(Pxx + Pyy + Pzz);
-      } else if (l2 == 1) {
-        corr = T(0.5) * (ix ? Pxx : (iy ? Pyy : Pzz));
-      } else {
-        corr = T(0.25) * (iz == 0 ? exq * eyq * Pxy : (iy == 0 ? exq * ezq * Pxz : eyq * ezq * Pyz));
-      }
-      emit(0, q, geq + T(0.5) * fq + om * corr);
-    }
-  }
-
-  // ---- a8: phase fields (Eqs. 15-18).  G_i = cs2 F_Phi_i + d(Phi_i u)/dt; first-order raw
-  // moments at s_phi, others at 1: f* = f_eq + C/2 + (1 - s_phi)/2 e.J on the axis links.
-  {
-    T nrm[3][3], amag[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const T m2 = gr[i][0] * gr[i][0] + gr[i][1] * gr[i][1] + gr[i][2] * gr[i][2];
-      const T inv = T(1) / sqrt(m2 + T(1e-24));
-#pragma unroll
-      for (int c = 0; c < 3; ++c) nrm[i][c] = gr[i][c] * inv;
-      amag[i] = T(4) / p.W * fabs(pc[i] * (T(1) - pc[i]));
-    }
-    T tot[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) tot[c] = amag[0] * nrm[0][c] + amag[1] * nrm[1][c] + amag[2] * nrm[2][c];
-    T den = pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2];
-    if (!(den > T(0))) den = T(1);
-    const T om = T(1) - p.s_phi;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const T share = pc[i] * pc[i] / den;
-      const T php = a.phi_prev[(int64_t)i * N + node];
-      T G[3], J[3];
-      T jf[3] = {0, 0, 0};
-      T fq[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        fq[q] = a.pop_in[((int64_t)(1 + i) * Q + q) * N + node];
-        jf[0] += T(L::ex[q]) * fq[q];
-        jf[1] += T(L::ey[q]) * fq[q];
-        jf[2] += T(L::ez[q]) * fq[q];
-      }
-      if (STORE) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) a.rec[(int64_t)(ML::JF + D * i + c) * N + node] = jf[c];
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T up = c < D ? a.u_prev[(int64_t)c * N + node] : T(0);
-        const T Fphi = amag[i] * nrm[i][c] - share * tot[c];
-        G[c] = cs2 * Fphi + a.dt_on * (pc[i] * u[c] - php * up);
-        J[c] = jf[c] - pc[i] * u[c] + T(0.5) * G[c];
-      }
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
-        const T w = T(L::w36[q]) / T(36);
-        const T eu = T(ix) * u[0] + T(iy) * u[1] + T(iz) * u[2];
-        const T eG = T(ix) * G[0] + T(iy) * G[1] + T(iz) * G[2];
-        T val = w * pc[i] * (T(1) + T(3) * eu) + T(1.5) * w * eG;
-        if (ix * ix + iy * iy + iz * iz == 1) val += T(0.5) * om * (T(ix) * J[0] + T(iy) * J[1] + T(iz) * J[2]);
-        emit(1 + i, q, val);
-      }
-    }
-  }
-
-  // ---- a9: charge (Eq. 14): equilibrium rho_e w (1 + e.u/cs2), R = (w/cs2) e.d(rho_e u)/dt
-  // inside the MRT, Ohmic source w (Q + dQ/dt / 2) after the collision.
-  if (EHD) {
-    const T rq = a.rho[node];
-    const T rp = a.rho_prev[node];
-    T dru[3], J[3], jh[3] = {0, 0, 0};
-    T hq[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      hq[q] = a.pop_in[((int64_t)4 * Q + q) * N + node];
-      jh[0] += T(L::ex[q]) * hq[q];
-      jh[1] += T(L::ey[q]) * hq[q];
-      jh[2] += T(L::ez[q]) * hq[q];
-    }
-    if (STORE) {
-#pragma unroll
-      for (int c = 0; c < D; ++c) a.rec[(int64_t)(ML::JH + c) * N + node] = jh[c];
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const T up = c < D ? a.u_prev[(int64_t)c * N + node] : T(0);
-      dru[c] = a.dt_on * (rq * u[c] - rp * up);
-      J[c] = jh[c] - rq * u[c] + T(0.5) * dru[c];
-    }
-    const T src = Qs + T(0.5) * a.dt_on * (Qs - a.q_prev[node]);
-    const T om = T(1) - p.s_e;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
-      const T w = T(L::w36[q]) / T(36);
-      const T eu = T(ix) * u[0] + T(iy) * u[1] + T(iz) * u[2];
-      const T eR = T(ix) * dru[0] + T(iy) * dru[1] + T(iz) * dru[2];
-      T val = w * rq * (T(1) + T(3) * eu) + T(1.5) * w * eR + w * src;
-      if (ix * ix + iy * iy + iz * iz == 1) val += T(0.5) * om * (T(ix) * J[0] + T(iy) * J[1] + T(iz) * J[2]);
-      emit(4, q, val);
-    }
-    a.q_out[node] = Qs;
-  }
-#pragma unroll
-  for (int c = 0; c < D; ++c) a.u_out[(int64_t)c * N + node] = u[c];
-}
-
 // ----------------------------------------------------------------------------- initial state
 // Populations at rest equilibrium: f_i = w Phi_i, g - w = 0, h = w rho_e.  phi0/rho0 hold the
 // initial fields (they double as the previous-step fields of the first step).
@@ -453,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Dims d, const uint8_t* __restri
                                                   T* __restrict__ pop, T* __restrict__ phi0,
                                                   T* __restrict__ rho0, T* __restrict__ u_prev,
                                                   T* __restrict__ q_prev) {
-  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t node = gidx();
   if (node >= d.N) return;
   const int64_t N = d.N;
   const bool fluid = flags[node] == 0;
@@ -527,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_obs(Dims d, const uint8_t* __restric
                                                  const T* __restrict__ phi, const T* __restrict__ phi_prev,
                                                  const T* __restrict__ u_prev, const T* __restrict__ rho,
                                                  double* __restrict__ part_sum, double* __restrict__ part_max) {
-  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t node = gidx();
   double v[kObs];
 #pragma unroll
   for (int k = 0; k < kObs; ++k) v[k] = 0.0;
@@ -611,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_pois_setup(Dims d, const uint8_t* __
                                                         Phys<T> p, Volts<T> volts,
                                                         T* __restrict__ cp, T* __restrict__ diag,
                                                         T* __restrict__ b) {
-  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t node = gidx();
   if (node >= d.N) return;
   const int64_t N = d.N;
   if (flags[node] != 0) {
@@ -672,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Level L, const T* __restrict__ 
                                                   const T* __restrict__ x, T* __restrict__ y,
                                                   double* __restrict__ part) {
   double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = gidx(); i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
     const T dg = diag[i];
     const T r = dg != T(0) ? apply_row<D, T>(L, cp, dg, x, i) : T(0);
     y[i] = r;
@@ -681,23 +413,20 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Level L, const T* __restrict__ 
   if (DOT) block_reduce<1, false>(acc, part + blockIdx.x);
 }
 
-// Damped Jacobi sweep: z_out = z_in + w (r - A z_in)/diag  (z_in == nullptr: z_out = w r/diag)
+// Damped Jacobi sweep: z_out = z_in + w (r - A z_in)/diag  (z_in == nullptr: z_out = w r/diag);
+// dinv = 1/diag on active cells and 0 on inactive ones
 template <int D, class T>
 __global__ __launch_bounds__(kBlock) void k_jacobi(Level L, const T* __restrict__ cp, const T* __restrict__ diag,
-                                                    const T* __restrict__ r, const T* __restrict__ z_in,
-                                                    T* __restrict__ z_out, T omega) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                    const T* __restrict__ dinv, const T* __restrict__ r,
+                                                    const T* __restrict__ z_in, T* __restrict__ z_out, T omega) {
+  const int64_t i = gidx();
   if (i >= L.N) return;
-  const T dg = diag[i];
-  if (dg == T(0)) {
-    z_out[i] = T(0);
-    return;
-  }
+  const T di = dinv[i];
   if (!z_in) {
-    z_out[i] = omega * r[i] / dg;
+    z_out[i] = omega * r[i] * di;
     return;
   }
-  z_out[i] = z_in[i] + omega * (r[i] - apply_row<D, T>(L, cp, dg, z_in, i)) / dg;
+  z_out[i] = di != T(0) ? z_in[i] + omega * (r[i] - apply_row<D, T>(L, cp, diag[i], z_in, i)) * di : T(0);
 }
 
 // ---- fused smoothing kernels of the V-cycle (damped Jacobi, weight w) ----------------------
@@ -714,78 +443,66 @@ __device__ __forceinline__ void axis_nbrs(const Level& L, int64_t i, int ax, int
 // Two sweeps from zero in one pass: z1 = w r/d, z2 = z1 + w (r - A z1)/d, with z1 at the
 // neighbours recomputed from r and d there.
 template <int D, class T>
-__global__ __launch_bounds__(kBlock) void k_smooth2(Level L, const T* __restrict__ cp, const T* __restrict__ dg,
+__global__ __launch_bounds__(kBlock) void k_smooth2(Level L, const T* __restrict__ cp, const T* __restrict__ dinv,
                                                      const T* __restrict__ r, T* __restrict__ z, T w) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)gidx();
   if (i >= (int)L.N) return;
-  const T d = dg[i];
-  if (d == T(0)) {
-    z[i] = T(0);
-    return;
-  }
+  const T di = dinv[i];
   const int N = (int)L.N;
   int cx, cy, cz;
   cell_xyz<D>(L, i, cx, cy, cz);
-  const T z1 = w * r[i] / d;
-  T off = 0;  // sum over faces c * z1(nb)
+  const T z1 = w * r[i] * di;
+  T off = 0;  // sum over faces c * z1(nb); absent faces have c = 0 and inactive cells dinv = 0
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) {
     int jp, jm;
     axis_pm<D>(L, i, cx, cy, cz, ax, jp, jm);
-    const T cpp = cp[ax * N + i], cpm = cp[ax * N + jm];
-    if (cpp != T(0)) off += cpp * w * r[jp] / dg[jp];
-    if (cpm != T(0)) off += cpm * w * r[jm] / dg[jm];
+    off += cp[ax * N + i] * r[jp] * dinv[jp] + cp[ax * N + jm] * r[jm] * dinv[jm];
   }
-  z[i] = z1 + w * (r[i] - d * z1 + off) / d;
+  z[i] = z1 + w * (r[i] * di - z1 + w * off * di);
 }
 
 // Prolongation fused with one sweep: z' = z + a zc(parent) (on the fly at the neighbours too),
 // z_out = z' + w (r - A z')/d.
 template <int D, class T>
 __global__ __launch_bounds__(kBlock) void k_prolong_smooth(Level L, const T* __restrict__ cp, const T* __restrict__ dg,
-                                                            const T* __restrict__ r, const T* __restrict__ z,
-                                                            Level Lc, const T* __restrict__ zc, T a, T w,
-                                                            T* __restrict__ zo) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+                                                            const T* __restrict__ dinv, const T* __restrict__ r,
+                                                            const T* __restrict__ z, Level Lc, const T* __restrict__ zc,
+                                                            T a, T w, T* __restrict__ zo) {
+  const int i = (int)gidx();
   if (i >= (int)L.N) return;
-  const T d = dg[i];
-  if (d == T(0)) {
-    zo[i] = T(0);
-    return;
-  }
+  const T di = dinv[i];
   const int N = (int)L.N;
   int cx, cy, cz;
   cell_xyz<D>(L, i, cx, cy, cz);
-  // parent of a cell at (x, y, z)
-  auto par = [&](int x, int y, int z) -> int { return (x >> 1) + Lc.n[0] * ((y >> 1) + Lc.n[1] * (z >> 1)); };
-  const T zi = z[i] + a * zc[par(cx, cy, cz)];
-  T az = d * zi;
+  // parent of a cell at (x, y, z); inactive cells hold z = 0, inactive parents zc = 0 and
+  // absent faces c = 0, so every term can be formed unconditionally
+  auto par = [&](int x, int y, int zz) -> int { return (x >> 1) + Lc.n[0] * ((y >> 1) + Lc.n[1] * (zz >> 1)); };
+  const T zi = di != T(0) ? z[i] + a * zc[par(cx, cy, cz)] : T(0);
+  T az = dg[i] * zi;
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) {
     int jp, jm;
     axis_pm<D>(L, i, cx, cy, cz, ax, jp, jm);
-    const T cpp = cp[ax * N + i], cpm = cp[ax * N + jm];
     int xp = cx, yp = cy, zp = cz, xm = cx, ym = cy, zm = cz;
     if (ax == 0) { xp = wrap(cx + 1, L.n[0]); xm = wrap(cx - 1, L.n[0]); }
     if (ax == 1) { yp = wrap(cy + 1, L.n[1]); ym = wrap(cy - 1, L.n[1]); }
     if (ax == 2) { zp = wrap(cz + 1, L.n[2]); zm = wrap(cz - 1, L.n[2]); }
-    // a nonzero face coefficient implies an active neighbour
-    if (cpp != T(0)) az -= cpp * (z[jp] + a * zc[par(xp, yp, zp)]);
-    if (cpm != T(0)) az -= cpm * (z[jm] + a * zc[par(xm, ym, zm)]);
+    az -= cp[ax * N + i] * (z[jp] + a * zc[par(xp, yp, zp)]) + cp[ax * N + jm] * (z[jm] + a * zc[par(xm, ym, zm)]);
   }
-  zo[i] = zi + w * (r[i] - az) / d;
+  zo[i] = zi + w * (r[i] - az) * di;
 }
 
 // One sweep with per-block FP64 partials of r.z_out (grid-stride, capped grid)
 template <int D, class T>
 __global__ __launch_bounds__(kBlock) void k_smooth_dot(Level L, const T* __restrict__ cp, const T* __restrict__ dg,
-                                                        const T* __restrict__ r, const T* __restrict__ z, T w,
-                                                        T* __restrict__ zo, double* __restrict__ part) {
+                                                        const T* __restrict__ dinv, const T* __restrict__ r,
+                                                        const T* __restrict__ z, T w, T* __restrict__ zo,
+                                                        double* __restrict__ part) {
   double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
-    const T d = dg[i];
-    T v = T(0);
-    if (d != T(0)) v = z[i] + w * (r[i] - apply_row<D, T>(L, cp, d, z, i)) / d;
+  for (int64_t i = gidx(); i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
+    const T di = dinv[i];
+    const T v = di != T(0) ? z[i] + w * (r[i] - apply_row<D, T>(L, cp, dg[i], z, i)) * di : T(0);
     zo[i] = v;
     acc[0] += (double)r[i] * (double)v;
   }
@@ -800,7 +517,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_max(int64_t N, const doubl
                                                            double* __restrict__ part) {
   const T al = (T)s[1];
   double m[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = gidx(); i < N; i += (int64_t)gridDim.x * blockDim.x) {
     x[i] += al * p[i];
     const T rn = r[i] - al * q[i];
     r[i] = rn;
@@ -818,6 +535,7 @@ struct TailArgs {
   Level L[kMaxLevels];
   T* cp[kMaxLevels];
   T* dg[kMaxLevels];
+  T* di[kMaxLevels];
   T* r[kMaxLevels];
   T* z[kMaxLevels];
   T* t[kMaxLevels];
@@ -827,14 +545,12 @@ struct TailArgs {
 };
 
 template <int D, class T>
-__device__ void tail_sweep(const Level& L, const T* cp, const T* dg, const T* r, const T* zin, T* zout, T w) {
+__device__ void tail_sweep(const Level& L, const T* cp, const T* dg, const T* dinv, const T* r, const T* zin,
+                           T* zout, T w) {
   for (int64_t i = threadIdx.x; i < L.N; i += blockDim.x) {
-    const T d = dg[i];
-    if (d == T(0)) {
-      zout[i] = T(0);
-      continue;
-    }
-    zout[i] = zin ? zin[i] + w * (r[i] - apply_row<D, T>(L, cp, d, zin, i)) / d : w * r[i] / d;
+    const T di = dinv[i];
+    zout[i] = zin ? (di != T(0) ? zin[i] + w * (r[i] - apply_row<D, T>(L, cp, dg[i], zin, i)) * di : T(0))
+                  : w * r[i] * di;
   }
 }
 
@@ -845,10 +561,10 @@ __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> a) {
     const Level& L = a.L[l];
     T* z = a.z[l];
     T* t = a.t[l];
-    tail_sweep<D, T>(L, a.cp[l], a.dg[l], a.r[l], nullptr, z, a.w);
+    tail_sweep<D, T>(L, a.cp[l], a.dg[l], a.di[l], a.r[l], nullptr, z, a.w);
     __syncthreads();
     for (int k = 1; k < a.nu; ++k) {
-      tail_sweep<D, T>(L, a.cp[l], a.dg[l], a.r[l], z, t, a.w);
+      tail_sweep<D, T>(L, a.cp[l], a.dg[l], a.di[l], a.r[l], z, t, a.w);
       __syncthreads();
       T* tmp = z; z = t; t = tmp;
     }
@@ -901,7 +617,7 @@ __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> a) {
     }
     __syncthreads();
     for (int k = 0; k < a.nu; ++k) {
-      tail_sweep<D, T>(L, a.cp[l], a.dg[l], a.r[l], z, t, a.w);
+      tail_sweep<D, T>(L, a.cp[l], a.dg[l], a.di[l], a.r[l], z, t, a.w);
       __syncthreads();
       T* tmp = z; z = t; t = tmp;
     }
@@ -915,7 +631,8 @@ __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> a) {
 // Tail setup: Galerkin coarsening of levels first+1..last and the dense coarsest inverse
 // (Gauss-Jordan, FP64, one workgroup).
 template <int D, class T>
-__device__ void coarsen_level(const Level& Lf, const T* cpf, const T* diagf, const Level& Lc, T* cpc, T* diagc) {
+__device__ void coarsen_level(const Level& Lf, const T* cpf, const T* diagf, const Level& Lc, T* cpc, T* diagc,
+                              T* dinvc) {
   for (int64_t I = threadIdx.x; I < Lc.N; I += blockDim.x) {
     int X, Y, Z;
     cell_xyz<D>(Lc, I, X, Y, Z);
@@ -941,6 +658,7 @@ __device__ void coarsen_level(const Level& Lf, const T* cpf, const T* diagf, con
           }
         }
     diagc[I] = dg;
+    dinvc[I] = dg != T(0) ? T(1) / dg : T(0);
     for (int ax = 0; ax < D; ++ax) cpc[(int64_t)ax * Lc.N + I] = c[ax];
   }
 }
@@ -948,7 +666,7 @@ __device__ void coarsen_level(const Level& Lf, const T* cpf, const T* diagf, con
 template <int D, class T>
 __global__ __launch_bounds__(kTailThreads) void k_tail_setup(TailArgs<T> a, double* __restrict__ inv) {
   for (int l = a.first; l < a.last; ++l) {
-    coarsen_level<D, T>(a.L[l], a.cp[l], a.dg[l], a.L[l + 1], a.cp[l + 1], a.dg[l + 1]);
+    coarsen_level<D, T>(a.L[l], a.cp[l], a.dg[l], a.L[l + 1], a.cp[l + 1], a.dg[l + 1], a.di[l + 1]);
     __syncthreads();
   }
   __shared__ double A[kCoarseMax][2 * kCoarseMax + 1];
@@ -1012,7 +730,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_resid(Level Lf, const T* __
                                                             const T* __restrict__ diag, const T* __restrict__ r,
                                                             const T* __restrict__ z, Level Lc,
                                                             T* __restrict__ rc) {
-  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t I = gidx();
   if (I >= Lc.N) return;
   int X, Y, Z;
   cell_xyz<D>(Lc, I, X, Y, Z);
@@ -1040,18 +758,6 @@ __global__ __launch_bounds__(kBlock) void k_restrict_resid(Level Lf, const T* __
   rc[I] = acc;
 }
 
-// z_fine += scale * z_coarse[parent] on active fine cells
-template <int D, class T>
-__global__ __launch_bounds__(kBlock) void k_prolong(Level Lf, const T* __restrict__ diag, T* __restrict__ z,
-                                                     Level Lc, const T* __restrict__ zc, T scale) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Lf.N) return;
-  if (diag[i] == T(0)) return;
-  int cx, cy, cz;
-  cell_xyz<D>(Lf, i, cx, cy, cz);
-  z[i] += scale * zc[cell_id<D>(Lc, cx >> 1, cy >> 1, cz >> 1)];
-}
-
 // Galerkin coarse operator of piecewise-constant aggregation: diag_I = sum of the
 // children's diagonals minus twice the faces inside I; cp_I(a) = sum of the fine faces
 // from I to I + e_a.
@@ -1059,7 +765,7 @@ template <int D, class T>
 __global__ __launch_bounds__(kBlock) void k_coarsen(Level Lf, const T* __restrict__ cpf,
                                                      const T* __restrict__ diagf, Level Lc,
                                                      T* __restrict__ cpc, T* __restrict__ diagc) {
-  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t I = gidx();
   if (I >= Lc.N) return;
   int X, Y, Z;
   cell_xyz<D>(Lc, I, X, Y, Z);
@@ -1091,13 +797,22 @@ __global__ __launch_bounds__(kBlock) void k_coarsen(Level Lf, const T* __restric
   for (int ax = 0; ax < D; ++ax) cpc[(int64_t)ax * Lc.N + I] = c[ax];
 }
 
+// dinv = 1/diag on active cells, 0 on inactive ones
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dinv(int64_t N, const T* __restrict__ diag, T* __restrict__ dinv) {
+  const int64_t i = gidx();
+  if (i >= N) return;
+  const T d = diag[i];
+  dinv[i] = d != T(0) ? T(1) / d : T(0);
+}
+
 // CG scalars live on the device: s[0] = rz, s[1] = alpha, s[2] = beta.
 // x += alpha p, r -= alpha q
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t N, const double* __restrict__ s,
                                                        const T* __restrict__ p, const T* __restrict__ q,
                                                        T* __restrict__ x, T* __restrict__ r) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gidx();
   if (i >= N) return;
   const T al = (T)s[1];
   x[i] += al * p[i];
@@ -1108,7 +823,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t N, const double* _
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_cg_dir(int64_t N, const double* __restrict__ s,
                                                     const T* __restrict__ z, T* __restrict__ p, int first) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gidx();
   if (i >= N) return;
   p[i] = first ? z[i] : z[i] + (T)s[2] * p[i];
 }
@@ -1118,7 +833,7 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_dot(int64_t N, const T* __restrict__ a, const T* __restrict__ b,
                                                  double* __restrict__ part) {
   double v[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t i = gidx(); i < N; i += (int64_t)gridDim.x * blockDim.x)
     v[0] += (double)a[i] * (double)b[i];
   block_reduce<1, false>(v, part + blockIdx.x);
 }
@@ -1130,7 +845,7 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Level L, const T* __restr
                                                         const T* __restrict__ b, const T* __restrict__ x,
                                                         T* __restrict__ r, double* __restrict__ part) {
   double m[3] = {0.0, 0.0, 0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = gidx(); i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
     const double dg = diag[i];
     double res = 0.0;
     if (dg != 0.0) {
@@ -1189,14 +904,14 @@ __global__ __launch_bounds__(kBlock) void k_final_beta(const double* __restrict_
 
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_zero(int64_t N, T* __restrict__ x) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gidx();
   if (i < N) x[i] = T(0);
 }
 
 // T -> double copy (read-out)
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_to_double(int64_t N, const T* __restrict__ a, double* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gidx();
   if (i < N) out[i] = (double)a[i];
 }
 
