@@ -214,10 +214,13 @@ ehdlb_status ehdlb_adjoint(ehdlb_ctx* ctx, const double dL_dcentroid[3], const d
 
 /* Options of the potential solver: conjugate gradients preconditioned by one
  * symmetric multigrid V-cycle (aggregation of 2 cells per axis, Galerkin coarse
- * operators, dense solve on the coarsest level).  omega in (0, 2): damped-
- * Jacobi weight; sweeps in [1, 8]: pre- and post-smoothing sweeps; overcorrect
- * in (0, 4]: scale of the coarse-grid correction.  EINVAL outside the ranges. */
-ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* ctx, double omega, int32_t sweeps, double overcorrect);
+ * operators, dense solve on the coarsest level).  Smoothing: the degree-2
+ * Chebyshev polynomial of the Jacobi-preconditioned operator D^-1 A on
+ * [lo, hi] (0 < lo < hi <= 2; D^-1 A has its spectrum in (0, 2]), applied once
+ * before and once after the coarse correction; overcorrect in (0, 4]: scale of
+ * the coarse-grid correction.  Defaults lo = 0.5, hi = 2, overcorrect = 2.
+ * EINVAL outside the ranges. */
+ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* ctx, double lo, double hi, double overcorrect);
 
 /* Optional timing of the step's three phases with HIP events recorded on the
  * bound stream: [0] moments and wetting ghosts, [1] potential solve (setup,

@@ -93,10 +93,18 @@ struct ehdlb_ctx {
     size_t lphi = 0, lpot = 0, lb = 0, lb2 = 0, vpart = 0, vred = 0, vacc = 0, obs = 0, total = 0, rec_stride = 0;
     int nvseg = 0;
   } adj;
-  // potential-solver options (ehdlb_set_solver_options)
-  double mg_omega = 0.8;       // damped-Jacobi weight
-  int mg_nu = 2;               // pre- and post-smoothing sweeps
-  double mg_overcorrect = 2.0; // scale of the coarse-grid correction
+  // potential-solver options (ehdlb_set_solver_options): degree-2 Chebyshev smoothing of the
+  // Jacobi-preconditioned operator on [lo, hi], coarse-correction scale
+  double mg_lo = 0.5, mg_hi = 2.0;
+  double mg_overcorrect = 2.0;
+  // smoothing polynomial z += c1 y - c2 D^-1 A y: p(mu) = 1 - c1 mu + c2 mu^2 = T2(s(mu))/T2(s(0)),
+  // s(mu) = (hi + lo - 2 mu)/(hi - lo)
+  void poly(double& c1, double& c2) const {
+    const double sg = (mg_hi + mg_lo) / (mg_hi - mg_lo), dl = 2.0 / (mg_hi - mg_lo);
+    const double t2 = 2.0 * sg * sg - 1.0;
+    c1 = 4.0 * sg * dl / t2;
+    c2 = 2.0 * dl * dl / t2;
+  }
   // optional timing: one event per phase boundary per step (moments | potential | step)
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -306,9 +314,11 @@ static TailArgs<T> tail_args(ehdlb_ctx* c) {
     t.t[l] = c->ptr<T>(m.t);
   }
   t.inv = c->ptr<double>(c->off_inv);
-  t.w = (T)c->mg_omega;
+  double c1, c2;
+  c->poly(c1, c2);
+  t.c1 = (T)c1;
+  t.c2 = (T)c2;
   t.a = (T)c->mg_overcorrect;
-  t.nu = c->mg_nu;
   return t;
 }
 
@@ -334,20 +344,13 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot
   T* cp = c->ptr<T>(m.cp);
   T* dg = c->ptr<T>(m.diag);
   T* di = c->ptr<T>(m.dinv);
-  const T omega = (T)c->mg_omega;
-  const int nu = c->mg_nu;
+  double c1d, c2d;
+  c->poly(c1d, c2d);
+  const T c1 = (T)c1d, c2 = (T)c2d, a = (T)c->mg_overcorrect;
   T* z = c->ptr<T>(m.z);
   T* t = c->ptr<T>(m.t);
   const int nb = nblocks(L.N);
-  if (nu >= 2) {
-    hipLaunchKernelGGL((k_smooth2<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, di, r, z, omega);
-  } else {
-    hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, di, r, (const T*)nullptr, z, omega);
-  }
-  for (int k = 2; k < nu; ++k) {
-    hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, di, r, z, t, omega);
-    std::swap(z, t);
-  }
+  hipLaunchKernelGGL((k_smooth2<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, di, r, z, c1, c2);
   MGLevel& mc = c->mg[lvl + 1];
   T* rc = c->ptr<T>(mc.r);
   hipLaunchKernelGGL((k_restrict_resid<D, T>), dim3(nblocks(mc.L.N)), dim3(kBlock), 0, s, L, cp, dg, r, z, mc.L, rc);
@@ -355,18 +358,15 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot
   T* zc = nullptr;
   ehdlb_status st = vcycle<D, T>(c, lvl + 1, rc, &zc, nullptr, nullptr);
   if (st) return st;
-  hipLaunchKernelGGL((k_prolong_smooth<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, di, r, z, mc.L, (const T*)zc,
-                     (T)c->mg_overcorrect, omega, t);
-  std::swap(z, t);
-  for (int k = 1; k < nu; ++k) {
-    if (k == nu - 1 && dot_part) {
-      hipLaunchKernelGGL((k_smooth_dot<D, T>), dim3(rblocks(L.N)), dim3(kBlock), 0, s, L, cp, dg, di, r, z, omega, t,
-                         dot_part);
-      if (dotted) *dotted = true;
-    } else {
-      hipLaunchKernelGGL((k_jacobi<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, di, r, z, t, omega);
-    }
-    std::swap(z, t);
+  hipLaunchKernelGGL((k_prolong_resid<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, di, r, z, mc.L, (const T*)zc,
+                     a, t);
+  if (dot_part) {
+    hipLaunchKernelGGL((k_poly_post<D, T, true>), dim3(rblocks(L.N)), dim3(kBlock), 0, s, L, cp, di, r, z, mc.L,
+                       (const T*)zc, a, (const T*)t, c1, c2, z, dot_part);
+    if (dotted) *dotted = true;
+  } else {
+    hipLaunchKernelGGL((k_poly_post<D, T, false>), dim3(nb), dim3(kBlock), 0, s, L, cp, di, r, z, mc.L, (const T*)zc,
+                       a, (const T*)t, c1, c2, z, (double*)nullptr);
   }
   LAUNCHCHK();
   *zout = z;
@@ -547,8 +547,8 @@ static ehdlb_status step_impl(ehdlb_ctx* c, int64_t n) {
       c->ev_used += 4;
       HIPCHK(hipEventRecord(ev[0], s));
     }
-    hipLaunchKernelGGL((k_moments<LT, T, EHD>), dim3(nblocks(N)), dim3(kBlock), 0, s, dm, flags, pin, phi, rho,
-                       (T*)nullptr);
+    hipLaunchKernelGGL((k_moments<LT, T>), dim3(nblocks(N), EHD ? 4 : 3), dim3(kBlock), 0, s, dm, flags, pin, phi, rho,
+                       (T*)nullptr, 1);
     if (G > 0)
       hipLaunchKernelGGL(k_ghosts<T>, dim3(nblocks(G)), dim3(kBlock), 0, s, N, G, c->ptr<int32_t>(c->off_gnode),
                          c->ptr<int32_t>(c->off_gsrc), c->ptr<T>(c->off_glen), phi, ph);
@@ -593,9 +593,10 @@ static ehdlb_status moments_now(ehdlb_ctx* c, T* drho) {
   const int64_t N = c->N;
   const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
   const int pi = (int)(c->t & 1);
-  hipLaunchKernelGGL((k_moments<LT, T, EHD>), dim3(nblocks(N)), dim3(kBlock), 0, c->stream, dm,
-                     c->ptr<uint8_t>(c->off_flags), c->ptr<T>(c->off_pop[c->cur]), c->ptr<T>(c->off_phi[pi]),
-                     c->ptr<T>(c->off_rho[pi]), drho);
+  // with drho also the flow family (read-out of the pressure)
+  hipLaunchKernelGGL((k_moments<LT, T>), dim3(nblocks(N), (EHD ? 4 : 3) + (drho ? 1 : 0)), dim3(kBlock), 0, c->stream,
+                     dm, c->ptr<uint8_t>(c->off_flags), c->ptr<T>(c->off_pop[c->cur]), c->ptr<T>(c->off_phi[pi]),
+                     c->ptr<T>(c->off_rho[pi]), drho, drho ? 0 : 1);
   LAUNCHCHK();
   return EHDLB_OK;
 }
@@ -812,8 +813,8 @@ static ehdlb_status step_record(ehdlb_ctx* c, T* rec) {
   T* rho = c->ptr<T>(c->off_rho[pi]);
   const T* pin = c->ptr<T>(c->off_pop[c->cur]);
   T* pout = c->ptr<T>(c->off_pop[1 - c->cur]);
-  hipLaunchKernelGGL((k_moments<LT, T, EHD>), dim3(nblocks(N)), dim3(kBlock), 0, s, dm, flags, pin, phi, rho,
-                     (T*)nullptr);
+  hipLaunchKernelGGL((k_moments<LT, T>), dim3(nblocks(N), EHD ? 4 : 3), dim3(kBlock), 0, s, dm, flags, pin, phi, rho,
+                     (T*)nullptr, 1);
   if (G > 0)
     hipLaunchKernelGGL(k_ghosts<T>, dim3(nblocks(G)), dim3(kBlock), 0, s, N, G, c->ptr<int32_t>(c->off_gnode),
                        c->ptr<int32_t>(c->off_gsrc), c->ptr<T>(c->off_glen), phi, ph);
@@ -1404,13 +1405,12 @@ ehdlb_status ehdlb_adjoint(ehdlb_ctx* c, const double* dL_dcentroid, const doubl
   return dispatch<AdjFn>(c, dL_dcentroid, dL_dvelocity, (int)electrode, dL_dvolts);
 }
 
-ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* c, double omega, int32_t sweeps, double overcorrect) {
+ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* c, double lo, double hi, double overcorrect) {
   if (!c) return EHDLB_EINVAL;
-  if (!(omega > 0.0 && omega < 2.0)) return fail(c, EHDLB_EINVAL, "Jacobi weight must lie in (0, 2)");
-  if (sweeps < 1 || sweeps > 8) return fail(c, EHDLB_EINVAL, "smoothing sweeps must lie in [1, 8]");
+  if (!(lo > 0.0 && hi > lo && hi <= 2.0)) return fail(c, EHDLB_EINVAL, "need 0 < lo < hi <= 2");
   if (!(overcorrect > 0.0 && overcorrect <= 4.0)) return fail(c, EHDLB_EINVAL, "over-correction must lie in (0, 4]");
-  c->mg_omega = omega;
-  c->mg_nu = sweeps;
+  c->mg_lo = lo;
+  c->mg_hi = hi;
   c->mg_overcorrect = overcorrect;
   return EHDLB_OK;
 }

@@ -121,38 +121,29 @@ struct MomLayout {
 };
 
 // ----------------------------------------------------------------------------- moments (Eq. 19)
-// Phi_i = sum_q f_i,q and rho_e = sum_q h_q at fluid nodes; zero at solid nodes
-// (the wetting kernel then overwrites the solid nodes next to fluid).  With
-// drho != nullptr also the flow density deviation (read-out only).
-template <class L, class T, bool EHD>
+// Zeroth moment of one population family per thread: blockIdx.y selects the family
+// fam0 + blockIdx.y (0: flow deviation -> drho, 1..3: phase fields -> phi, 4: charge -> rho).
+// Zero at solid nodes (the wetting kernel then overwrites the solid nodes next to fluid).
+template <class L, class T>
 __global__ __launch_bounds__(kBlock) void k_moments(Dims d, const uint8_t* __restrict__ flags,
                                                      const T* __restrict__ pop, T* __restrict__ phi,
-                                                     T* __restrict__ rho, T* __restrict__ drho) {
+                                                     T* __restrict__ rho, T* __restrict__ drho, int fam0) {
   const int64_t node = gidx();
   if (node >= d.N) return;
   const int64_t N = d.N;
-  const bool fluid = flags[node] == 0;
-  T s[3] = {0, 0, 0};
-  T r = 0, g = 0;
-  if (fluid) {
+  const int fam = fam0 + (int)blockIdx.y;
+  T s = 0;
+  if (flags[node] == 0) {
+    const T* p = pop + (int64_t)fam * L::Q * N + node;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-#pragma unroll
-      for (int q = 0; q < L::Q; ++q) s[i] += pop[((int64_t)(1 + i) * L::Q + q) * N + node];
-    }
-    if (EHD) {
-#pragma unroll
-      for (int q = 0; q < L::Q; ++q) r += pop[((int64_t)4 * L::Q + q) * N + node];
-    }
-    if (drho) {
-#pragma unroll
-      for (int q = 0; q < L::Q; ++q) g += pop[(int64_t)q * N + node];
-    }
+    for (int q = 0; q < L::Q; ++q) s += p[(int64_t)q * N];
   }
-#pragma unroll
-  for (int i = 0; i < 3; ++i) phi[(int64_t)i * N + node] = s[i];
-  if (EHD) rho[node] = r;
-  if (drho) drho[node] = g;
+  if (fam == 0)
+    drho[node] = s;
+  else if (fam <= 3)
+    phi[(int64_t)(fam - 1) * N + node] = s;
+  else
+    rho[node] = s;
 }
 
 // ----------------------------------------------------------------------------- wetting ghosts (Eq. 20)
@@ -440,44 +431,43 @@ __device__ __forceinline__ void axis_nbrs(const Level& L, int64_t i, int ax, int
   jm = m;
 }
 
-// Two sweeps from zero in one pass: z1 = w r/d, z2 = z1 + w (r - A z1)/d, with z1 at the
-// neighbours recomputed from r and d there.
+// Smoothing polynomial of the V-cycle: z <- z + c1 y - c2 D^-1 A y with y = D^-1 (r - A z)
+// (degree-2 polynomial in D^-1 A; c1 = 2w, c2 = w^2 is two damped-Jacobi sweeps).
+// Pre-smoothing from z = 0 in one pass: z = (c1 - c2) y + c2 dinv sum_faces c y(nb), y = dinv r.
 template <int D, class T>
 __global__ __launch_bounds__(kBlock) void k_smooth2(Level L, const T* __restrict__ cp, const T* __restrict__ dinv,
-                                                     const T* __restrict__ r, T* __restrict__ z, T w) {
+                                                     const T* __restrict__ r, T* __restrict__ z, T c1, T c2) {
   const int i = (int)gidx();
   if (i >= (int)L.N) return;
   const T di = dinv[i];
   const int N = (int)L.N;
   int cx, cy, cz;
   cell_xyz<D>(L, i, cx, cy, cz);
-  const T z1 = w * r[i] * di;
-  T off = 0;  // sum over faces c * z1(nb); absent faces have c = 0 and inactive cells dinv = 0
+  T off = 0;  // absent faces have c = 0 and inactive cells dinv = 0
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) {
     int jp, jm;
     axis_pm<D>(L, i, cx, cy, cz, ax, jp, jm);
     off += cp[ax * N + i] * r[jp] * dinv[jp] + cp[ax * N + jm] * r[jm] * dinv[jm];
   }
-  z[i] = z1 + w * (r[i] * di - z1 + w * off * di);
+  z[i] = (c1 - c2) * r[i] * di + c2 * di * off;
 }
 
-// Prolongation fused with one sweep: z' = z + a zc(parent) (on the fly at the neighbours too),
-// z_out = z' + w (r - A z')/d.
+// Post-smoothing, pass 1: prolongation z' = z + a zc(parent) (on the fly, also at the
+// neighbours) and y = dinv (r - A z').
 template <int D, class T>
-__global__ __launch_bounds__(kBlock) void k_prolong_smooth(Level L, const T* __restrict__ cp, const T* __restrict__ dg,
-                                                            const T* __restrict__ dinv, const T* __restrict__ r,
-                                                            const T* __restrict__ z, Level Lc, const T* __restrict__ zc,
-                                                            T a, T w, T* __restrict__ zo) {
+__global__ __launch_bounds__(kBlock) void k_prolong_resid(Level L, const T* __restrict__ cp, const T* __restrict__ dg,
+                                                           const T* __restrict__ dinv, const T* __restrict__ r,
+                                                           const T* __restrict__ z, Level Lc, const T* __restrict__ zc,
+                                                           T a, T* __restrict__ y) {
   const int i = (int)gidx();
   if (i >= (int)L.N) return;
   const T di = dinv[i];
   const int N = (int)L.N;
   int cx, cy, cz;
   cell_xyz<D>(L, i, cx, cy, cz);
-  // parent of a cell at (x, y, z); inactive cells hold z = 0, inactive parents zc = 0 and
-  // absent faces c = 0, so every term can be formed unconditionally
-  auto par = [&](int x, int y, int zz) -> int { return (x >> 1) + Lc.n[0] * ((y >> 1) + Lc.n[1] * (zz >> 1)); };
+  // inactive cells hold z = 0, inactive parents zc = 0 and absent faces c = 0
+  auto par = [&](int x, int yy, int zz) -> int { return (x >> 1) + Lc.n[0] * ((yy >> 1) + Lc.n[1] * (zz >> 1)); };
   const T zi = di != T(0) ? z[i] + a * zc[par(cx, cy, cz)] : T(0);
   T az = dg[i] * zi;
 #pragma unroll
@@ -490,23 +480,45 @@ __global__ __launch_bounds__(kBlock) void k_prolong_smooth(Level L, const T* __r
     if (ax == 2) { zp = wrap(cz + 1, L.n[2]); zm = wrap(cz - 1, L.n[2]); }
     az -= cp[ax * N + i] * (z[jp] + a * zc[par(xp, yp, zp)]) + cp[ax * N + jm] * (z[jm] + a * zc[par(xm, ym, zm)]);
   }
-  zo[i] = zi + w * (r[i] - az) * di;
+  y[i] = (r[i] - az) * di;
 }
 
-// One sweep with per-block FP64 partials of r.z_out (grid-stride, capped grid)
-template <int D, class T>
-__global__ __launch_bounds__(kBlock) void k_smooth_dot(Level L, const T* __restrict__ cp, const T* __restrict__ dg,
-                                                        const T* __restrict__ dinv, const T* __restrict__ r,
-                                                        const T* __restrict__ z, T w, T* __restrict__ zo,
-                                                        double* __restrict__ part) {
+// Post-smoothing, pass 2: z_out = z' + (c1 - c2) y + c2 dinv sum_faces c y(nb), z' = z + a zc
+// (zc == nullptr: z' = z), optionally with per-block FP64 partials of r.z_out (grid-stride).
+template <int D, class T, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_poly_post(Level L, const T* __restrict__ cp, const T* __restrict__ dinv,
+                                                       const T* __restrict__ r, const T* __restrict__ z,
+                                                       Level Lc, const T* __restrict__ zc, T a,
+                                                       const T* __restrict__ y, T c1, T c2, T* __restrict__ zo,
+                                                       double* __restrict__ part) {
   double acc[1] = {0.0};
-  for (int64_t i = gidx(); i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
-    const T di = dinv[i];
-    const T v = di != T(0) ? z[i] + w * (r[i] - apply_row<D, T>(L, cp, dg[i], z, i)) * di : T(0);
-    zo[i] = v;
-    acc[0] += (double)r[i] * (double)v;
+  int64_t lo_, hi_;
+  if (DOT) {
+    chunk_range(L.N, lo_, hi_);
+  } else {
+    lo_ = gidx();
+    hi_ = lo_ < L.N ? lo_ + 1 : lo_;
   }
-  block_reduce<1, false>(acc, part + blockIdx.x);
+  const int N = (int)L.N;
+  for (int64_t i64 = DOT ? lo_ + threadIdx.x : lo_; i64 < hi_; i64 += DOT ? blockDim.x : 1) {
+    const int i = (int)i64;
+    const T di = dinv[i];
+    int cx, cy, cz;
+    cell_xyz<D>(L, i, cx, cy, cz);
+    T off = 0;
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      int jp, jm;
+      axis_pm<D>(L, i, cx, cy, cz, ax, jp, jm);
+      off += cp[ax * N + i] * y[jp] + cp[ax * N + jm] * y[jm];
+    }
+    T zi = z[i];
+    if (zc) zi += a * zc[(cx >> 1) + Lc.n[0] * ((cy >> 1) + Lc.n[1] * (cz >> 1))];
+    const T v = di != T(0) ? zi + (c1 - c2) * y[i] + c2 * di * off : T(0);
+    zo[i] = v;
+    if (DOT) acc[0] += (double)r[i] * (double)v;
+  }
+  if (DOT) block_reduce<1, false>(acc, part + blockIdx.x);
 }
 
 // x += alpha p, r -= alpha q, with per-block FP64 partials of max|r| (grid-stride)
@@ -540,39 +552,45 @@ struct TailArgs {
   T* z[kMaxLevels];
   T* t[kMaxLevels];
   const double* inv;  // dense inverse of the coarsest operator
-  T w, a;
-  int nu;
+  T c1, c2, a;        // smoothing polynomial and coarse-correction scale
 };
 
+// y = dinv (r - A z) over one level (z == nullptr: y = dinv r)
 template <int D, class T>
-__device__ void tail_sweep(const Level& L, const T* cp, const T* dg, const T* dinv, const T* r, const T* zin,
-                           T* zout, T w) {
+__device__ void tail_resid(const Level& L, const T* cp, const T* dg, const T* dinv, const T* r, const T* z, T* y) {
   for (int64_t i = threadIdx.x; i < L.N; i += blockDim.x) {
     const T di = dinv[i];
-    zout[i] = zin ? (di != T(0) ? zin[i] + w * (r[i] - apply_row<D, T>(L, cp, dg[i], zin, i)) * di : T(0))
-                  : w * r[i] * di;
+    y[i] = z ? (di != T(0) ? (r[i] - apply_row<D, T>(L, cp, dg[i], z, i)) * di : T(0)) : r[i] * di;
+  }
+}
+// z = (z or 0) + (c1 - c2) y + c2 dinv sum_faces c y(nb)
+template <int D, class T>
+__device__ void tail_poly(const Level& L, const T* cp, const T* dinv, const T* y, T* z, bool add, T c1, T c2) {
+  const int N = (int)L.N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    int cx, cy, cz;
+    cell_xyz<D>(L, i, cx, cy, cz);
+    T off = 0;
+    for (int ax = 0; ax < D; ++ax) {
+      int jp, jm;
+      axis_pm<D>(L, i, cx, cy, cz, ax, jp, jm);
+      off += cp[ax * N + i] * y[jp] + cp[ax * N + jm] * y[jm];
+    }
+    const T di = dinv[i];
+    const T v = di != T(0) ? (c1 - c2) * y[i] + c2 * di * off : T(0);
+    z[i] = add ? z[i] + v : v;
   }
 }
 
 template <int D, class T>
 __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> a) {
-  // descend
+  // descend: pre-smooth from zero, restrict the residual
   for (int l = a.first; l < a.last; ++l) {
     const Level& L = a.L[l];
-    T* z = a.z[l];
-    T* t = a.t[l];
-    tail_sweep<D, T>(L, a.cp[l], a.dg[l], a.di[l], a.r[l], nullptr, z, a.w);
+    tail_resid<D, T>(L, a.cp[l], a.dg[l], a.di[l], a.r[l], nullptr, a.t[l]);
     __syncthreads();
-    for (int k = 1; k < a.nu; ++k) {
-      tail_sweep<D, T>(L, a.cp[l], a.dg[l], a.di[l], a.r[l], z, t, a.w);
-      __syncthreads();
-      T* tmp = z; z = t; t = tmp;
-    }
-    // keep the result in a.z[l]
-    if (z != a.z[l]) {
-      for (int64_t i = threadIdx.x; i < L.N; i += blockDim.x) a.z[l][i] = z[i];
-      __syncthreads();
-    }
+    tail_poly<D, T>(L, a.cp[l], a.di[l], a.t[l], a.z[l], false, a.c1, a.c2);
+    __syncthreads();
     const Level& Lc = a.L[l + 1];
     for (int64_t I = threadIdx.x; I < Lc.N; I += blockDim.x) {
       int X, Y, Z;
@@ -603,12 +621,11 @@ __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> a) {
     }
     __syncthreads();
   }
-  // ascend
+  // ascend: prolongate, post-smooth
   for (int l = a.last - 1; l >= a.first; --l) {
     const Level& L = a.L[l];
     const Level& Lc = a.L[l + 1];
     T* z = a.z[l];
-    T* t = a.t[l];
     for (int64_t i = threadIdx.x; i < L.N; i += blockDim.x) {
       if (a.dg[l][i] == T(0)) continue;
       int cx, cy, cz;
@@ -616,15 +633,10 @@ __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> a) {
       z[i] += a.a * a.z[l + 1][cell_id<D>(Lc, cx >> 1, cy >> 1, cz >> 1)];
     }
     __syncthreads();
-    for (int k = 0; k < a.nu; ++k) {
-      tail_sweep<D, T>(L, a.cp[l], a.dg[l], a.di[l], a.r[l], z, t, a.w);
-      __syncthreads();
-      T* tmp = z; z = t; t = tmp;
-    }
-    if (z != a.z[l]) {
-      for (int64_t i = threadIdx.x; i < L.N; i += blockDim.x) a.z[l][i] = z[i];
-      __syncthreads();
-    }
+    tail_resid<D, T>(L, a.cp[l], a.dg[l], a.di[l], a.r[l], z, a.t[l]);
+    __syncthreads();
+    tail_poly<D, T>(L, a.cp[l], a.di[l], a.t[l], z, true, a.c1, a.c2);
+    __syncthreads();
   }
 }
 

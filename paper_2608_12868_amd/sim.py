@@ -157,8 +157,9 @@ class Simulation(Context):
         self._chk(L.lib().ehdlb_adjoint(self.h, gx.ctypes.data, gv.ctypes.data, int(electrode), out.ctypes.data))
         return out
 
-    def set_solver_options(self, omega=0.8, sweeps=2, overcorrect=2.0):
-        self._chk(L.lib().ehdlb_set_solver_options(self.h, float(omega), int(sweeps), float(overcorrect)))
+    def set_solver_options(self, lo=0.5, hi=2.0, overcorrect=2.0):
+        """Chebyshev smoothing interval [lo, hi] of D^-1 A and coarse-correction scale."""
+        self._chk(L.lib().ehdlb_set_solver_options(self.h, float(lo), float(hi), float(overcorrect)))
 
     def set_timing(self, on=True):
         self._chk(L.lib().ehdlb_set_timing(self.h, int(bool(on))))
