@@ -28,6 +28,7 @@ int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 constexpr int kRedBlocks = 1024;
 // levels with at most this many cells run inside the single-workgroup V-cycle tail
 constexpr int64_t kTailMaxCells = 2048;
+constexpr int kSolverParts = 7;
 int rblocks(int64_t n) { return std::min(nblocks(n), kRedBlocks); }
 
 struct MGLevel {
@@ -66,10 +67,16 @@ struct ehdlb_ctx {
   int sticky = 0;
   double last_resid = 0.0, last_resid0 = 0.0;
   int last_iters = 0;
+  // iteration counts of the last potential solves of each kind (0: forward, 1: adjoint): they
+  // decide how much work is queued before the host looks at the control block (speed only)
+  struct CgHistory {
+    int last = 0, prev = 0, last_nonzero = 1;
+  } cg_hist[2];
+  ehd::CgCtl hctl{};  // host copy of the solve's control block
   // layout (byte offsets into ws)
   size_t off_pop[2]{}, off_phi[2]{}, off_rho[2]{}, off_u[2]{}, off_q[2]{}, off_pot = 0;
   size_t off_flags = 0, off_gnode = 0, off_gsrc = 0, off_glen = 0, off_scratch = 0;
-  size_t off_b = 0, off_r = 0, off_z = 0, off_p = 0, off_qv = 0;
+  size_t off_b = 0, off_r = 0, off_z = 0, off_p = 0, off_qv = 0, off_spart = 0;
   size_t off_part = 0, off_red = 0, off_cg = 0, off_inv = 0, off_dbl = 0;
   size_t state_bytes = 0, total = 0;
   std::vector<MGLevel> mg;
@@ -111,7 +118,6 @@ struct ehdlb_ctx {
   size_t ev_used = 0;
   int64_t timed_steps = 0;
   double acc_ms[3]{};
-  double hres[3]{};  // host copy of the residual check
   double last_mp = 0.0;  // sum of the previous-step Phi_1 at the last observables call
 
   template <class T>
@@ -262,7 +268,9 @@ static void plan_layout(ehdlb_ctx* c) {
   c->nparts = nblocks(N);
   c->off_part = take((size_t)c->nparts * kObs * 8 + 64);
   c->off_red = take(64 * 8);
-  c->off_cg = take(8 * 8);
+  c->off_cg = take(sizeof(CgCtl));
+  // solver partials: true residual (3 per block), max|r|, p.q, two r.z
+  c->off_spart = take((size_t)kSolverParts * kRedBlocks * 8);
   c->state_bytes = 256 + align_up((size_t)c->F * c->Q * N * ts) + (c->off_pot + N * ts - c->off_phi[0]);
   c->total = o;
 }
@@ -314,6 +322,7 @@ static TailArgs<T> tail_args(ehdlb_ctx* c) {
     t.t[l] = c->ptr<T>(m.t);
   }
   t.inv = c->ptr<double>(c->off_inv);
+  t.stop = &c->ptr<CgCtl>(c->off_cg)->stop;
   double c1, c2;
   c->poly(c1, c2);
   t.c1 = (T)c1;
@@ -330,6 +339,7 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot
   hipStream_t s = c->stream;
   MGLevel& m = c->mg[lvl];
   const Level L = m.L;
+  const int* stop = &c->ptr<CgCtl>(c->off_cg)->stop;
   if (dotted) *dotted = false;
   if (lvl == c->tail_first) {
     TailArgs<T> ta = tail_args<T>(c);
@@ -350,23 +360,24 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot
   T* z = c->ptr<T>(m.z);
   T* t = c->ptr<T>(m.t);
   const int nb = nblocks(L.N);
-  hipLaunchKernelGGL((k_smooth2<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, di, r, z, c1, c2);
+  hipLaunchKernelGGL((k_smooth2<D, T>), dim3(nb), dim3(kBlock), 0, s, stop, L, cp, di, r, z, c1, c2);
   MGLevel& mc = c->mg[lvl + 1];
   T* rc = c->ptr<T>(mc.r);
-  hipLaunchKernelGGL((k_restrict_resid<D, T>), dim3(nblocks(mc.L.N)), dim3(kBlock), 0, s, L, cp, dg, r, z, mc.L, rc);
+  hipLaunchKernelGGL((k_restrict_resid<D, T>), dim3(nblocks(mc.L.N)), dim3(kBlock), 0, s, stop, L, cp, dg, r, z, mc.L,
+                     rc);
   LAUNCHCHK();
   T* zc = nullptr;
   ehdlb_status st = vcycle<D, T>(c, lvl + 1, rc, &zc, nullptr, nullptr);
   if (st) return st;
-  hipLaunchKernelGGL((k_prolong_resid<D, T>), dim3(nb), dim3(kBlock), 0, s, L, cp, dg, di, r, z, mc.L, (const T*)zc,
-                     a, t);
+  hipLaunchKernelGGL((k_prolong_resid<D, T>), dim3(nb), dim3(kBlock), 0, s, stop, L, cp, dg, di, r, z, mc.L,
+                     (const T*)zc, a, t);
   if (dot_part) {
-    hipLaunchKernelGGL((k_poly_post<D, T, true>), dim3(rblocks(L.N)), dim3(kBlock), 0, s, L, cp, di, r, z, mc.L,
-                       (const T*)zc, a, (const T*)t, c1, c2, z, dot_part);
+    hipLaunchKernelGGL((k_poly_post<D, T, true>), dim3(rblocks(L.N)), dim3(kBlock), 0, s, stop, L, cp, di, r, z,
+                       mc.L, (const T*)zc, a, (const T*)t, c1, c2, z, dot_part);
     if (dotted) *dotted = true;
   } else {
-    hipLaunchKernelGGL((k_poly_post<D, T, false>), dim3(nb), dim3(kBlock), 0, s, L, cp, di, r, z, mc.L, (const T*)zc,
-                       a, (const T*)t, c1, c2, z, (double*)nullptr);
+    hipLaunchKernelGGL((k_poly_post<D, T, false>), dim3(nb), dim3(kBlock), 0, s, stop, L, cp, di, r, z, mc.L,
+                       (const T*)zc, a, (const T*)t, c1, c2, z, (double*)nullptr);
   }
   LAUNCHCHK();
   *zout = z;
@@ -375,9 +386,18 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot
 
 // Conjugate gradients on the fine-level operator (already set up in level 0) for A x = b, warm
 // started from x, preconditioned by one multigrid V-cycle; converged when the FP64 residual
-// max|b - A x| <= tol max|b|.
+// max|b - A x| <= tol max|b| or is at the rounding floor of x stored in T.
+//
+// Every decision is taken on the device (CgCtl): alpha and beta are evaluated by the kernels
+// that use them from the fixed-order partials of the previous reductions, the convergence test
+// by k_true_resid/k_cg_judge, and once the solve has stopped every queued solver kernel returns
+// at once.  How much is queued before the host reads the control block follows the recent
+// iteration counts `hist`: after solves that needed no iteration the host looks right after the
+// initial check; in a run of iterating solves it queues the hierarchy and as many iterations as
+// the last solve took.  Afterwards it continues one iteration at a time.  The iterates do not
+// depend on this.
 template <class LT, class T>
-static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b) {
+static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hist) {
   constexpr int D = LT::D;
   hipStream_t s = c->stream;
   const int64_t N = c->N;
@@ -387,98 +407,109 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b) {
   T* r = c->ptr<T>(c->off_r);
   T* p = c->ptr<T>(c->off_p);
   T* qv = c->ptr<T>(c->off_qv);
-  double* part = c->ptr<double>(c->off_part);
-  double* red = c->ptr<double>(c->off_red);
-  double* cg = c->ptr<double>(c->off_cg);
+  CgCtl* ctl = c->ptr<CgCtl>(c->off_cg);
+  const int* stop = &ctl->stop;
+  double* sp = c->ptr<double>(c->off_spart);
+  double* ptrue = sp;  // 3 per block
+  double* pmax = sp + 3 * kRedBlocks;
+  double* ppq = sp + 4 * kRedBlocks;
+  double* prz[2] = {sp + 5 * kRedBlocks, sp + 6 * kRedBlocks};  // r.z of preconditioning k in prz[k & 1]
   const int nb0 = nblocks(N), rb0 = rblocks(N);
   const double tol = c->prm.poisson_tol;
+  const double eps_t = sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
 
-  // FP64 residual check.  rel = max|r| / max|b|; the solve has converged when rel <= tol or
-  // when max|r| is at the rounding floor of x stored in T: 8 eps_T max_i sum_j |A_ij x_j|.
-  double floor_rel = 0.0;
-  auto check = [&](double& rel, double& bmax) -> ehdlb_status {
-    hipLaunchKernelGGL((k_true_resid<D, T>), dim3(rb0), dim3(kBlock), 0, s, m0.L, cp0, dg0, b, x, r, part);
-    hipLaunchKernelGGL((k_final<3, true>), dim3(1), dim3(kBlock), 0, s, part, rb0, red);
-    LAUNCHCHK();
-    HIPCHK(hipMemcpyAsync(c->hres, red, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  // initial check; x = 0 when b == 0
+  hipLaunchKernelGGL((k_true_resid<D, T>), dim3(rb0), dim3(kBlock), 0, s, (const CgCtl*)nullptr,
+                     (const double*)nullptr, 0, tol, 0, m0.L, (const T*)cp0, (const T*)dg0, b, (const T*)x, r,
+                     ptrue);
+  hipLaunchKernelGGL(k_cg_judge, dim3(1), dim3(kBlock), 0, s, ctl, (const double*)ptrue, (const double*)pmax, rb0,
+                     tol, eps_t, 0, 0, 1);
+  LAUNCHCHK();
+  auto read_ctl = [&]() -> ehdlb_status {
+    HIPCHK(hipMemcpyAsync(&c->hctl, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    bmax = c->hres[1];
-    rel = bmax > 0.0 ? c->hres[0] / bmax : 0.0;
-    const double eps = sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
-    floor_rel = bmax > 0.0 ? 8.0 * eps * c->hres[2] / bmax : 0.0;
     return EHDLB_OK;
   };
-  auto done = [&](double rel) { return rel <= tol || rel <= floor_rel; };
-
-  double rel = 0.0, bmax = 0.0;
-  ehdlb_status st = check(rel, bmax);
-  if (st) return st;
-  c->last_iters = 0;
-  c->last_resid0 = rel;
-  if (bmax == 0.0) {
-    hipLaunchKernelGGL(k_zero<T>, dim3(nb0), dim3(kBlock), 0, s, N, x);
-    c->last_resid = 0.0;
-    return EHDLB_OK;
+  bool stopped = false;
+  int batch = std::max(hist.last, 1);
+  if (hist.last == 0 || hist.prev == 0) {
+    // solves without iterations are common here: look before queueing the hierarchy
+    ehdlb_status e = read_ctl();
+    if (e) return e;
+    stopped = c->hctl.stop != 0;
+    if (c->hctl.zero) hipLaunchKernelGGL(k_zero<T>, dim3(nb0), dim3(kBlock), 0, s, N, x);
+    batch = std::max(hist.last_nonzero - 1, 1);
+  } else {
+    hipLaunchKernelGGL(k_cg_zero<T>, dim3(nb0), dim3(kBlock), 0, s, (const CgCtl*)ctl, N, x);
   }
-  if (!done(rel) && std::isfinite(rel)) {
-    // coarse hierarchy (Galerkin aggregation) and the dense coarsest inverse, only when iterating
-    hipLaunchKernelGGL(k_dinv<T>, dim3(nb0), dim3(kBlock), 0, s, N, (const T*)dg0, c->ptr<T>(m0.dinv));
+  // coarse hierarchy (Galerkin aggregation) and the dense coarsest inverse, only when iterating
+  if (!stopped) {
+    hipLaunchKernelGGL(k_dinv<T>, dim3(nb0), dim3(kBlock), 0, s, stop, N, (const T*)dg0, c->ptr<T>(m0.dinv));
     for (size_t l = 0; l < c->tail_first; ++l) {
       MGLevel& f = c->mg[l];
       MGLevel& g = c->mg[l + 1];
-      hipLaunchKernelGGL((k_coarsen<D, T>), dim3(nblocks(g.L.N)), dim3(kBlock), 0, s, f.L, c->ptr<T>(f.cp),
-                         c->ptr<T>(f.diag), g.L, c->ptr<T>(g.cp), c->ptr<T>(g.diag));
-      hipLaunchKernelGGL(k_dinv<T>, dim3(nblocks(g.L.N)), dim3(kBlock), 0, s, g.L.N, (const T*)c->ptr<T>(g.diag),
-                         c->ptr<T>(g.dinv));
+      hipLaunchKernelGGL((k_coarsen<D, T>), dim3(nblocks(g.L.N)), dim3(kBlock), 0, s, stop, f.L,
+                         (const T*)c->ptr<T>(f.cp), (const T*)c->ptr<T>(f.diag), g.L, c->ptr<T>(g.cp),
+                         c->ptr<T>(g.diag));
+      hipLaunchKernelGGL(k_dinv<T>, dim3(nblocks(g.L.N)), dim3(kBlock), 0, s, stop, g.L.N,
+                         (const T*)c->ptr<T>(g.diag), c->ptr<T>(g.dinv));
     }
     hipLaunchKernelGGL((k_tail_setup<D, T>), dim3(1), dim3(kTailThreads), 0, s, tail_args<T>(c),
                        c->ptr<double>(c->off_inv));
     LAUNCHCHK();
-    auto precondition = [&](bool first) -> ehdlb_status {
-      T* z = nullptr;
-      bool dotted = false;
-      ehdlb_status e = vcycle<D, T>(c, 0, r, &z, part, &dotted);
-      if (e) return e;
-      int nbp = rb0;
-      if (!dotted) {
-        hipLaunchKernelGGL(k_dot<T>, dim3(rb0), dim3(kBlock), 0, s, N, r, z, part);
-      }
-      hipLaunchKernelGGL(k_final_beta, dim3(1), dim3(kBlock), 0, s, part, nbp, cg, first ? 1 : 0);
-      hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb0), dim3(kBlock), 0, s, N, cg, z, p, first ? 1 : 0);
-      LAUNCHCHK();
-      return EHDLB_OK;
-    };
-    if ((st = precondition(true))) return st;
-    int it = 0;
-    const int maxit = c->prm.poisson_max_iter, every = c->prm.poisson_check_every;
-    bool conv = false;
-    while (it < maxit) {
-      ++it;
-      hipLaunchKernelGGL((k_spmv<D, T, true>), dim3(rb0), dim3(kBlock), 0, s, m0.L, cp0, dg0, p, qv, part);
-      hipLaunchKernelGGL(k_final_alpha, dim3(1), dim3(kBlock), 0, s, part, rb0, cg);
-      hipLaunchKernelGGL(k_cg_update_max<T>, dim3(rb0), dim3(kBlock), 0, s, N, cg, p, qv, x, r, part);
-      LAUNCHCHK();
-      if (it % every == 0 || it == maxit) {
-        // cheap trigger: the recursively updated residual; the FP64 true residual decides
-        hipLaunchKernelGGL((k_final<1, true>), dim3(1), dim3(kBlock), 0, s, part, rb0, red);
-        HIPCHK(hipMemcpyAsync(c->hres, red, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        const double est = c->hres[0] / bmax;
-        if (est <= tol || est <= floor_rel || !std::isfinite(est) || it == maxit) {
-          if ((st = check(rel, bmax))) return st;
-          if (done(rel) || !std::isfinite(rel)) {
-            conv = done(rel);
-            break;
-          }
-        }
-      }
-      if ((st = precondition(false))) return st;
-    }
-    c->last_iters = it;
-    if (!conv) c->sticky |= 2;
   }
-  if (!std::isfinite(rel)) c->sticky |= 1;
-  c->last_resid = rel;
+  // z = M r, with the partials of r.z
+  T* z = nullptr;
+  auto precondition = [&](double* rz) -> ehdlb_status {
+    bool dotted = false;
+    ehdlb_status e = vcycle<D, T>(c, 0, r, &z, rz, &dotted);
+    if (e) return e;
+    if (!dotted) hipLaunchKernelGGL(k_dot<T>, dim3(rb0), dim3(kBlock), 0, s, stop, N, (const T*)r, (const T*)z, rz);
+    LAUNCHCHK();
+    return EHDLB_OK;
+  };
+  ehdlb_status st = EHDLB_OK;
+  if (!stopped && (st = precondition(prz[0]))) return st;
+  const int maxit = c->prm.poisson_max_iter, every = c->prm.poisson_check_every;
+  int queued = 0;
+  for (; !stopped;) {
+    for (int k = 0; k < batch && queued < maxit; ++k) {
+      const int it = ++queued;
+      // p = z + beta p with beta = rz_{it-1} / rz_{it-2}; q = A p
+      hipLaunchKernelGGL(k_cg_dir<T>, dim3(rb0), dim3(kBlock), 0, s, (const CgCtl*)ctl, N,
+                         (const double*)prz[(it - 1) & 1], (const double*)prz[it & 1], rb0, it == 1 ? 1 : 0,
+                         (const T*)z, p);
+      hipLaunchKernelGGL((k_spmv<D, T>), dim3(rb0), dim3(kBlock), 0, s, (const CgCtl*)ctl, m0.L, (const T*)cp0,
+                         (const T*)dg0, (const T*)p, qv, ppq);
+      hipLaunchKernelGGL(k_cg_update_max<T>, dim3(rb0), dim3(kBlock), 0, s, (const CgCtl*)ctl, N,
+                         (const double*)prz[(it - 1) & 1], (const double*)ppq, rb0, (const T*)p, (const T*)qv, x, r,
+                         pmax);
+      if (it % every == 0 || it == maxit) {
+        const int force = it == maxit ? 1 : 0;
+        hipLaunchKernelGGL((k_true_resid<D, T>), dim3(rb0), dim3(kBlock), 0, s, (const CgCtl*)ctl,
+                           (const double*)pmax, rb0, tol, force, m0.L, (const T*)cp0, (const T*)dg0, b, (const T*)x,
+                           r, ptrue);
+        hipLaunchKernelGGL(k_cg_judge, dim3(1), dim3(kBlock), 0, s, ctl, (const double*)ptrue, (const double*)pmax,
+                           rb0, tol, eps_t, it, force, 0);
+      }
+      LAUNCHCHK();
+      if ((st = precondition(prz[it & 1]))) return st;
+    }
+    if ((st = read_ctl())) return st;
+    if (c->hctl.stop || queued >= maxit) break;
+    batch = 1;
+  }
+  const CgCtl& h = c->hctl;
+  c->last_resid0 = h.rel0;
+  c->last_iters = h.iterated && !h.zero ? h.iters : 0;
+  c->last_resid = h.zero ? 0.0 : h.rel;
+  if (!h.zero) {
+    if (h.iterated && !h.conv) c->sticky |= 2;
+    if (!std::isfinite(h.rel)) c->sticky |= 1;
+  }
+  hist.prev = hist.last;
+  hist.last = c->last_iters;
+  if (c->last_iters > 0) hist.last_nonzero = c->last_iters;
   return EHDLB_OK;
 }
 
@@ -500,7 +531,7 @@ template <class LT, class T>
 static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, const Volts<T>& volts) {
   ehdlb_status st = pois_setup<LT, T>(c, phi, rho, volts);
   if (st) return st;
-  return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b));
+  return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b), c->cg_hist[0]);
 }
 
 // ============================================================================ timing
@@ -923,7 +954,7 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
     HIPCHK(hipMemcpyAsync(c->ptr<T>(c->off_b), A(J.lpot), N * sizeof(T), hipMemcpyDeviceToDevice, s));
     // warm start from the adjoint potential of step t+2 (same parity: the adjoint of the
     // over-relaxed first moments alternates in sign from step to step); zero at the start
-    if ((st = pcg<LT, T>(c, A(lbx), c->ptr<T>(c->off_b)))) return st;
+    if ((st = pcg<LT, T>(c, A(lbx), c->ptr<T>(c->off_b), c->cg_hist[1]))) return st;
   }
   hipLaunchKernelGGL((k_adj_cd<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, v, rec, (const T*)A(J.lphi),
                      (const T*)A(J.lrho_loc), (const T*)A(lbx), (const T*)A(J.lmom), A(J.lP[cu]), vpart);

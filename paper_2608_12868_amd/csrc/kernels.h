@@ -44,6 +44,12 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // global thread index over nodes (plain block order: the XCD-aware order did not help the
 // one-thread-per-node kernels on MI355X and slowed the fused step by a few percent)
 __device__ __forceinline__ int64_t gidx() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+// global thread index of the one-thread-per-cell stencil kernels of the potential solver:
+// XCD-aware block order, so that the rows above and below a block's cells are read through
+// the same XCD's L2 (measured faster for these kernels, unlike the fused step)
+__device__ __forceinline__ int64_t sidx() {
+  return (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
 // contiguous chunk [lo, hi) of a grid-stride kernel's index space for this block (fixed, so
 // reductions keep a fixed order); chunks are multiples of the block size
 __device__ __forceinline__ void chunk_range(int64_t n, int64_t& lo, int64_t& hi) {
@@ -241,6 +247,43 @@ __global__ __launch_bounds__(kBlock) void k_final(const double* __restrict__ par
   block_reduce<K, MAX>(v, out);
 }
 
+// Sum (or max) of n per-block partials, evaluated by every block in the same fixed order as
+// k_final and returned to every thread (blockDim.x == kBlock).  Lets a kernel consume the
+// result of the previous kernel's reduction without a separate one-block launch.
+template <bool MAX>
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int n) {
+  __shared__ double sm[kBlock / 64];
+  double x = MAX ? -INFINITY : 0.0;
+  for (int b = threadIdx.x; b < n; b += kBlock) x = MAX ? fmax(x, part[b]) : x + part[b];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double y = __shfl_down(x, off, 64);
+    x = MAX ? fmax(x, y) : x + y;
+  }
+  __syncthreads();  // sm may still be read by a previous call
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = x;
+  __syncthreads();
+  double r = sm[0];
+#pragma unroll
+  for (int w = 1; w < kBlock / 64; ++w) r = MAX ? fmax(r, sm[w]) : r + sm[w];
+  return r;
+}
+
+// Device-side state of one conjugate-gradient solve.  Every solver kernel returns at once
+// when stop != 0, so the host can queue iterations ahead of the convergence decision.
+struct CgCtl {
+  double bmax;   // max|b|
+  double floor;  // rounding floor of the relative residual (8 eps_T max_i sum_j |A_ij x_j| / max|b|)
+  double rel;    // last FP64 relative residual max|b - A x| / max|b|
+  double rel0;   // the same before the first iteration
+  int stop;      // no further iteration
+  int conv;      // stopped converged
+  int zero;      // b == 0: x set to zero
+  int iterated;  // the initial check did not already satisfy the tolerance
+  int iters;     // iteration at which the solve stopped
+  int pad[3];
+};
+
 // ----------------------------------------------------------------------------- observables (a10)
 // Per-block FP64 partials: 0-2 masses, 3-5 sum x Phi1, 6-8 sum Phi1_prev u_prev,
 // 9 sum Phi1_prev, 10 total charge, 11 count of non-finite values; block 2 of the
@@ -390,54 +433,15 @@ __device__ __forceinline__ T apply_row(const Level& L, const T* __restrict__ cp,
   return r;
 }
 
-template <int D, class T, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_spmv(Level L, const T* __restrict__ cp, const T* __restrict__ diag,
-                                                  const T* __restrict__ x, T* __restrict__ y,
-                                                  double* __restrict__ part) {
-  double acc[1] = {0.0};
-  for (int64_t i = gidx(); i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
-    const T dg = diag[i];
-    const T r = dg != T(0) ? apply_row<D, T>(L, cp, dg, x, i) : T(0);
-    y[i] = r;
-    if (DOT) acc[0] += (double)x[i] * (double)r;
-  }
-  if (DOT) block_reduce<1, false>(acc, part + blockIdx.x);
-}
-
-// Damped Jacobi sweep: z_out = z_in + w (r - A z_in)/diag  (z_in == nullptr: z_out = w r/diag);
-// dinv = 1/diag on active cells and 0 on inactive ones
-template <int D, class T>
-__global__ __launch_bounds__(kBlock) void k_jacobi(Level L, const T* __restrict__ cp, const T* __restrict__ diag,
-                                                    const T* __restrict__ dinv, const T* __restrict__ r,
-                                                    const T* __restrict__ z_in, T* __restrict__ z_out, T omega) {
-  const int64_t i = gidx();
-  if (i >= L.N) return;
-  const T di = dinv[i];
-  if (!z_in) {
-    z_out[i] = omega * r[i] * di;
-    return;
-  }
-  z_out[i] = di != T(0) ? z_in[i] + omega * (r[i] - apply_row<D, T>(L, cp, diag[i], z_in, i)) * di : T(0);
-}
-
-// ---- fused smoothing kernels of the V-cycle (damped Jacobi, weight w) ----------------------
-template <int D>
-__device__ __forceinline__ void axis_nbrs(const Level& L, int64_t i, int ax, int64_t& jp, int64_t& jm) {
-  int cx, cy, cz;
-  cell_xyz<D>(L, i, cx, cy, cz);
-  int p, m;
-  axis_pm<D>(L, (int)i, cx, cy, cz, ax, p, m);
-  jp = p;
-  jm = m;
-}
-
 // Smoothing polynomial of the V-cycle: z <- z + c1 y - c2 D^-1 A y with y = D^-1 (r - A z)
 // (degree-2 polynomial in D^-1 A; c1 = 2w, c2 = w^2 is two damped-Jacobi sweeps).
 // Pre-smoothing from z = 0 in one pass: z = (c1 - c2) y + c2 dinv sum_faces c y(nb), y = dinv r.
 template <int D, class T>
-__global__ __launch_bounds__(kBlock) void k_smooth2(Level L, const T* __restrict__ cp, const T* __restrict__ dinv,
-                                                     const T* __restrict__ r, T* __restrict__ z, T c1, T c2) {
-  const int i = (int)gidx();
+__global__ __launch_bounds__(kBlock) void k_smooth2(const int* __restrict__ stop, Level L, const T* __restrict__ cp,
+                                                     const T* __restrict__ dinv, const T* __restrict__ r,
+                                                     T* __restrict__ z, T c1, T c2) {
+  if (*stop) return;
+  const int i = (int)sidx();
   if (i >= (int)L.N) return;
   const T di = dinv[i];
   const int N = (int)L.N;
@@ -456,11 +460,13 @@ __global__ __launch_bounds__(kBlock) void k_smooth2(Level L, const T* __restrict
 // Post-smoothing, pass 1: prolongation z' = z + a zc(parent) (on the fly, also at the
 // neighbours) and y = dinv (r - A z').
 template <int D, class T>
-__global__ __launch_bounds__(kBlock) void k_prolong_resid(Level L, const T* __restrict__ cp, const T* __restrict__ dg,
+__global__ __launch_bounds__(kBlock) void k_prolong_resid(const int* __restrict__ stop, Level L,
+                                                           const T* __restrict__ cp, const T* __restrict__ dg,
                                                            const T* __restrict__ dinv, const T* __restrict__ r,
                                                            const T* __restrict__ z, Level Lc, const T* __restrict__ zc,
                                                            T a, T* __restrict__ y) {
-  const int i = (int)gidx();
+  if (*stop) return;
+  const int i = (int)sidx();
   if (i >= (int)L.N) return;
   const T di = dinv[i];
   const int N = (int)L.N;
@@ -486,17 +492,19 @@ __global__ __launch_bounds__(kBlock) void k_prolong_resid(Level L, const T* __re
 // Post-smoothing, pass 2: z_out = z' + (c1 - c2) y + c2 dinv sum_faces c y(nb), z' = z + a zc
 // (zc == nullptr: z' = z), optionally with per-block FP64 partials of r.z_out (grid-stride).
 template <int D, class T, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_poly_post(Level L, const T* __restrict__ cp, const T* __restrict__ dinv,
+__global__ __launch_bounds__(kBlock) void k_poly_post(const int* __restrict__ stop, Level L,
+                                                       const T* __restrict__ cp, const T* __restrict__ dinv,
                                                        const T* __restrict__ r, const T* __restrict__ z,
                                                        Level Lc, const T* __restrict__ zc, T a,
                                                        const T* __restrict__ y, T c1, T c2, T* __restrict__ zo,
                                                        double* __restrict__ part) {
+  if (*stop) return;
   double acc[1] = {0.0};
   int64_t lo_, hi_;
   if (DOT) {
     chunk_range(L.N, lo_, hi_);
   } else {
-    lo_ = gidx();
+    lo_ = sidx();
     hi_ = lo_ < L.N ? lo_ + 1 : lo_;
   }
   const int N = (int)L.N;
@@ -521,13 +529,20 @@ __global__ __launch_bounds__(kBlock) void k_poly_post(Level L, const T* __restri
   if (DOT) block_reduce<1, false>(acc, part + blockIdx.x);
 }
 
-// x += alpha p, r -= alpha q, with per-block FP64 partials of max|r| (grid-stride)
+// alpha = rz / pq from the partials of r.z (previous preconditioning) and p.q (this
+// iteration's product); x += alpha p, r -= alpha q, with per-block FP64 partials of max|r|
+// (grid-stride)
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_cg_update_max(int64_t N, const double* __restrict__ s,
+__global__ __launch_bounds__(kBlock) void k_cg_update_max(const CgCtl* __restrict__ ctl, int64_t N,
+                                                           const double* __restrict__ prz,
+                                                           const double* __restrict__ ppq, int nblk,
                                                            const T* __restrict__ p, const T* __restrict__ q,
                                                            T* __restrict__ x, T* __restrict__ r,
                                                            double* __restrict__ part) {
-  const T al = (T)s[1];
+  if (ctl->stop) return;
+  const double rz = reduce_partials<false>(prz, nblk);
+  const double pq = reduce_partials<false>(ppq, nblk);
+  const T al = (T)(pq != 0.0 ? rz / pq : 0.0);
   double m[1] = {0.0};
   for (int64_t i = gidx(); i < N; i += (int64_t)gridDim.x * blockDim.x) {
     x[i] += al * p[i];
@@ -536,6 +551,44 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_max(int64_t N, const doubl
     m[0] = fmax(m[0], fabs((double)rn));
   }
   block_reduce<1, true>(m, part + blockIdx.x);
+}
+
+// p = z + beta p with beta = rz_new / rz_old from the partials of the last two
+// preconditionings (first: p = z) (grid-stride)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_cg_dir(const CgCtl* __restrict__ ctl, int64_t N,
+                                                    const double* __restrict__ prz_new,
+                                                    const double* __restrict__ prz_old, int nblk, int first,
+                                                    const T* __restrict__ z, T* __restrict__ p) {
+  if (ctl->stop) return;
+  int64_t lo, hi;
+  chunk_range(N, lo, hi);
+  if (first) {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) p[i] = z[i];
+    return;
+  }
+  const double rn = reduce_partials<false>(prz_new, nblk);
+  const double ro = reduce_partials<false>(prz_old, nblk);
+  const T beta = (T)(ro != 0.0 ? rn / ro : 0.0);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) p[i] = z[i] + beta * p[i];
+}
+
+// q = A p with per-block FP64 partials of p.q (grid-stride)
+template <int D, class T>
+__global__ __launch_bounds__(kBlock) void k_spmv(const CgCtl* __restrict__ ctl, Level L, const T* __restrict__ cp,
+                                                  const T* __restrict__ diag, const T* __restrict__ p,
+                                                  T* __restrict__ q, double* __restrict__ part) {
+  if (ctl->stop) return;
+  double acc[1] = {0.0};
+  int64_t lo, hi;
+  chunk_range(L.N, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+    const T dg = diag[i];
+    const T r = dg != T(0) ? apply_row<D, T>(L, cp, dg, p, i) : T(0);
+    q[i] = r;
+    acc[0] += (double)p[i] * (double)r;
+  }
+  block_reduce<1, false>(acc, part + blockIdx.x);
 }
 
 // ---- V-cycle tail: every level from `first` to the coarsest in one workgroup ---------------
@@ -553,6 +606,7 @@ struct TailArgs {
   T* t[kMaxLevels];
   const double* inv;  // dense inverse of the coarsest operator
   T c1, c2, a;        // smoothing polynomial and coarse-correction scale
+  const int* stop;    // the solve's stop flag (nothing to do when set)
 };
 
 // y = dinv (r - A z) over one level (z == nullptr: y = dinv r)
@@ -584,6 +638,7 @@ __device__ void tail_poly(const Level& L, const T* cp, const T* dinv, const T* y
 
 template <int D, class T>
 __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> a) {
+  if (*a.stop) return;
   // descend: pre-smooth from zero, restrict the residual
   for (int l = a.first; l < a.last; ++l) {
     const Level& L = a.L[l];
@@ -677,6 +732,7 @@ __device__ void coarsen_level(const Level& Lf, const T* cpf, const T* diagf, con
 
 template <int D, class T>
 __global__ __launch_bounds__(kTailThreads) void k_tail_setup(TailArgs<T> a, double* __restrict__ inv) {
+  if (*a.stop) return;
   for (int l = a.first; l < a.last; ++l) {
     coarsen_level<D, T>(a.L[l], a.cp[l], a.dg[l], a.L[l + 1], a.cp[l + 1], a.dg[l + 1], a.di[l + 1]);
     __syncthreads();
@@ -738,11 +794,12 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_setup(TailArgs<T> a, doub
 // Restriction of the residual r - A z to the coarse level (sum over the children), fused:
 // each coarse cell recomputes the residual of its children.
 template <int D, class T>
-__global__ __launch_bounds__(kBlock) void k_restrict_resid(Level Lf, const T* __restrict__ cp,
-                                                            const T* __restrict__ diag, const T* __restrict__ r,
-                                                            const T* __restrict__ z, Level Lc,
-                                                            T* __restrict__ rc) {
-  const int64_t I = gidx();
+__global__ __launch_bounds__(kBlock) void k_restrict_resid(const int* __restrict__ stop, Level Lf,
+                                                            const T* __restrict__ cp, const T* __restrict__ diag,
+                                                            const T* __restrict__ r, const T* __restrict__ z,
+                                                            Level Lc, T* __restrict__ rc) {
+  if (*stop) return;
+  const int64_t I = sidx();
   if (I >= Lc.N) return;
   int X, Y, Z;
   cell_xyz<D>(Lc, I, X, Y, Z);
@@ -774,9 +831,10 @@ __global__ __launch_bounds__(kBlock) void k_restrict_resid(Level Lf, const T* __
 // children's diagonals minus twice the faces inside I; cp_I(a) = sum of the fine faces
 // from I to I + e_a.
 template <int D, class T>
-__global__ __launch_bounds__(kBlock) void k_coarsen(Level Lf, const T* __restrict__ cpf,
-                                                     const T* __restrict__ diagf, Level Lc,
-                                                     T* __restrict__ cpc, T* __restrict__ diagc) {
+__global__ __launch_bounds__(kBlock) void k_coarsen(const int* __restrict__ stop, Level Lf,
+                                                     const T* __restrict__ cpf, const T* __restrict__ diagf,
+                                                     Level Lc, T* __restrict__ cpc, T* __restrict__ diagc) {
+  if (*stop) return;
   const int64_t I = gidx();
   if (I >= Lc.N) return;
   int X, Y, Z;
@@ -811,51 +869,49 @@ __global__ __launch_bounds__(kBlock) void k_coarsen(Level Lf, const T* __restric
 
 // dinv = 1/diag on active cells, 0 on inactive ones
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_dinv(int64_t N, const T* __restrict__ diag, T* __restrict__ dinv) {
+__global__ __launch_bounds__(kBlock) void k_dinv(const int* __restrict__ stop, int64_t N, const T* __restrict__ diag,
+                                                  T* __restrict__ dinv) {
+  if (*stop) return;
   const int64_t i = gidx();
   if (i >= N) return;
   const T d = diag[i];
   dinv[i] = d != T(0) ? T(1) / d : T(0);
 }
 
-// CG scalars live on the device: s[0] = rz, s[1] = alpha, s[2] = beta.
-// x += alpha p, r -= alpha q
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t N, const double* __restrict__ s,
-                                                       const T* __restrict__ p, const T* __restrict__ q,
-                                                       T* __restrict__ x, T* __restrict__ r) {
-  const int64_t i = gidx();
-  if (i >= N) return;
-  const T al = (T)s[1];
-  x[i] += al * p[i];
-  r[i] -= al * q[i];
-}
-
-// p = z + beta p  (beta from s[2]; first == true: p = z)
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_cg_dir(int64_t N, const double* __restrict__ s,
-                                                    const T* __restrict__ z, T* __restrict__ p, int first) {
-  const int64_t i = gidx();
-  if (i >= N) return;
-  p[i] = first ? z[i] : z[i] + (T)s[2] * p[i];
-}
-
 // per-block FP64 partial of a.b (grid-stride)
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_dot(int64_t N, const T* __restrict__ a, const T* __restrict__ b,
-                                                 double* __restrict__ part) {
+__global__ __launch_bounds__(kBlock) void k_dot(const int* __restrict__ stop, int64_t N, const T* __restrict__ a,
+                                                 const T* __restrict__ b, double* __restrict__ part) {
+  if (*stop) return;
   double v[1] = {0.0};
   for (int64_t i = gidx(); i < N; i += (int64_t)gridDim.x * blockDim.x)
     v[0] += (double)a[i] * (double)b[i];
   block_reduce<1, false>(v, part + blockIdx.x);
 }
 
+// Convergence trigger after an iteration, evaluated alike by every block that needs it: the
+// recursively updated residual max|r| (partials of k_cg_update_max) against the tolerance and
+// the rounding floor, or non-finite, or the iteration cap (force).
+__device__ __forceinline__ bool cg_trigger(const CgCtl* __restrict__ ctl, const double* __restrict__ pmax,
+                                           int nblk, double tol, int force) {
+  const double est = reduce_partials<true>(pmax, nblk) / ctl->bmax;
+  return force || est <= tol || est <= ctl->floor || !isfinite(est);
+}
+
 // FP64 true residual: r = b - A x (stored in T), per-block partials of max|r|, max|b| and
-// max_i sum_j |A_ij x_j| (the rounding floor of the residual of an x stored in T) (grid-stride)
+// max_i sum_j |A_ij x_j| (the rounding floor of the residual of an x stored in T) (grid-stride).
+// ctl == nullptr: unconditional (initial check); otherwise only when the solve is running and
+// cg_trigger fires.
 template <int D, class T>
-__global__ __launch_bounds__(kBlock) void k_true_resid(Level L, const T* __restrict__ cp, const T* __restrict__ diag,
+__global__ __launch_bounds__(kBlock) void k_true_resid(const CgCtl* __restrict__ ctl, const double* __restrict__ pmax,
+                                                        int nmax, double tol, int force, Level L,
+                                                        const T* __restrict__ cp, const T* __restrict__ diag,
                                                         const T* __restrict__ b, const T* __restrict__ x,
                                                         T* __restrict__ r, double* __restrict__ part) {
+  if (ctl) {
+    if (ctl->stop) return;
+    if (!cg_trigger(ctl, pmax, nmax, tol, force)) return;
+  }
   double m[3] = {0.0, 0.0, 0.0};
   for (int64_t i = gidx(); i < L.N; i += (int64_t)gridDim.x * blockDim.x) {
     const double dg = diag[i];
@@ -887,31 +943,53 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Level L, const T* __restr
   block_reduce<3, true>(m, part + (int64_t)blockIdx.x * 3);
 }
 
-// Final reduction of p.q partials fused with alpha = rz / pq  (s[0] = rz, s[1] = alpha)
-__global__ __launch_bounds__(kBlock) void k_final_alpha(const double* __restrict__ part, int nblk,
-                                                         double* __restrict__ s) {
-  double v[1] = {0.0};
-  for (int b = threadIdx.x; b < nblk; b += kBlock) v[0] += part[b];
-  __shared__ double out[1];
-  block_reduce<1, false>(v, out);
+// Convergence decision from the true-residual partials (one block).  init != 0: the check
+// before the first iteration (sets every field).  Otherwise runs only when k_true_resid ran,
+// i.e. the solve is running and cg_trigger fires; stops on convergence, a non-finite residual
+// or the iteration cap (force).
+__global__ __launch_bounds__(kBlock) void k_cg_judge(CgCtl* __restrict__ ctl, const double* __restrict__ ptrue,
+                                                      const double* __restrict__ pmax, int nblk, double tol,
+                                                      double eps_t, int it, int force, int init) {
+  if (!init) {
+    if (ctl->stop) return;
+    if (!cg_trigger(ctl, pmax, nblk, tol, force)) return;
+  }
+  double v[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = threadIdx.x; b < nblk; b += kBlock)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = fmax(v[k], ptrue[(int64_t)b * 3 + k]);
+  __shared__ double out[3];
+  block_reduce<3, true>(v, out);
   __syncthreads();
-  if (threadIdx.x == 0) s[1] = out[0] != 0.0 ? s[0] / out[0] : 0.0;
+  if (threadIdx.x != 0) return;
+  const double bmax = out[1];
+  const double rel = bmax > 0.0 ? out[0] / bmax : 0.0;
+  const double floor = bmax > 0.0 ? 8.0 * eps_t * out[2] / bmax : 0.0;
+  const bool done = rel <= tol || rel <= floor;
+  ctl->rel = rel;
+  ctl->floor = floor;
+  if (init) {
+    ctl->bmax = bmax;
+    ctl->rel0 = rel;
+    ctl->zero = bmax == 0.0;
+    ctl->iters = 0;
+    const bool run = bmax != 0.0 && !done && isfinite(rel);
+    ctl->iterated = run;
+    ctl->stop = !run;
+    ctl->conv = bmax == 0.0 || done;
+  } else if (done || !isfinite(rel) || force) {
+    ctl->stop = 1;
+    ctl->conv = done;
+    ctl->iters = it;
+  }
 }
 
-// Final reduction of r.z partials fused with beta = rz_new / rz and rz <- rz_new (s[2] = beta).
-// init != 0: only rz <- rz_new.
-__global__ __launch_bounds__(kBlock) void k_final_beta(const double* __restrict__ part, int nblk,
-                                                        double* __restrict__ s, int init) {
-  double v[1] = {0.0};
-  for (int b = threadIdx.x; b < nblk; b += kBlock) v[0] += part[b];
-  __shared__ double out[1];
-  block_reduce<1, false>(v, out);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double n = out[0];
-    if (!init) s[2] = s[0] != 0.0 ? n / s[0] : 0.0;
-    s[0] = n;
-  }
+// x = 0 when the right-hand side vanishes
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_cg_zero(const CgCtl* __restrict__ ctl, int64_t N, T* __restrict__ x) {
+  if (!ctl->zero) return;
+  const int64_t i = gidx();
+  if (i < N) x[i] = T(0);
 }
 
 template <class T>
