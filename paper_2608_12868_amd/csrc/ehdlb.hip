@@ -26,7 +26,8 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 // grid of the grid-stride reduction kernels (fixed, so the reduction order is fixed)
 constexpr int kRedBlocks = 1024;
-// levels with at most this many cells run inside the single-workgroup V-cycle tail
+// levels with at most this many cells whose working vectors, with those of every coarser
+// level, fit the tail's LDS run inside the single-workgroup V-cycle tail
 constexpr int64_t kTailMaxCells = 2048;
 constexpr int kSolverParts = 7;
 int rblocks(int64_t n) { return std::min(nblocks(n), kRedBlocks); }
@@ -263,7 +264,13 @@ static void plan_layout(ehdlb_ctx* c) {
     const int64_t nc = c->mg.back().L.N;
     c->off_inv = take((size_t)nc * nc * 8);
     c->tail_first = c->mg.size() - 1;
-    while (c->tail_first > 0 && c->mg[c->tail_first - 1].L.N <= kTailMaxCells) --c->tail_first;
+    int64_t tail_cells = c->mg.back().L.N;
+    while (c->tail_first > 0) {
+      const int64_t n = c->mg[c->tail_first - 1].L.N;
+      if (n > kTailMaxCells || 3 * (size_t)(tail_cells + n) * ts > (size_t)kTailLdsBytes) break;
+      tail_cells += n;
+      --c->tail_first;
+    }
   }
   c->nparts = nblocks(N);
   c->off_part = take((size_t)c->nparts * kObs * 8 + 64);
@@ -311,6 +318,11 @@ static TailArgs<T> tail_args(ehdlb_ctx* c) {
   TailArgs<T> t{};
   t.first = (int)c->tail_first;
   t.last = (int)c->mg.size() - 1;
+  int off = 0;
+  for (int l = t.first; l <= t.last; ++l) {
+    t.lds[l] = off;
+    off += 3 * (int)c->mg[l].L.N;
+  }
   for (int l = t.first; l <= t.last; ++l) {
     MGLevel& m = c->mg[l];
     t.L[l] = m.L;

@@ -592,11 +592,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const CgCtl* __restrict__ ctl, 
 }
 
 // ---- V-cycle tail: every level from `first` to the coarsest in one workgroup ---------------
+// The working vectors r, z, y of the tail levels live in LDS (gfx950: 160 KiB per CU); the
+// coefficients stay in global memory, where they are L2-resident.  Only r of level `first` is
+// read from and z of level `first` written to global memory.
 constexpr int kMaxLevels = 16;
 constexpr int kTailThreads = 1024;
+constexpr int kTailLdsBytes = 144 * 1024;
 template <class T>
 struct TailArgs {
   int first, last;  // level indices handled here; last = coarsest
+  int lds[kMaxLevels];  // element offset of level l's [r | z | y] in the tail's LDS
   Level L[kMaxLevels];
   T* cp[kMaxLevels];
   T* dg[kMaxLevels];
@@ -609,90 +614,134 @@ struct TailArgs {
   const int* stop;    // the solve's stop flag (nothing to do when set)
 };
 
-// y = dinv (r - A z) over one level (z == nullptr: y = dinv r)
+// One level of the tail, every pass over the level's cells with independent loads only.
+// Pre-smoothing from zero: z = (c1 - c2) dinv r + c2 dinv sum_faces c dinv(nb) r(nb).
 template <int D, class T>
-__device__ void tail_resid(const Level& L, const T* cp, const T* dg, const T* dinv, const T* r, const T* z, T* y) {
-  for (int64_t i = threadIdx.x; i < L.N; i += blockDim.x) {
-    const T di = dinv[i];
-    y[i] = z ? (di != T(0) ? (r[i] - apply_row<D, T>(L, cp, dg[i], z, i)) * di : T(0)) : r[i] * di;
-  }
-}
-// z = (z or 0) + (c1 - c2) y + c2 dinv sum_faces c y(nb)
-template <int D, class T>
-__device__ void tail_poly(const Level& L, const T* cp, const T* dinv, const T* y, T* z, bool add, T c1, T c2) {
+__device__ __forceinline__ void tail_pre(const Level& L, const T* cp, const T* di, const T* r, T* z, T c1, T c2) {
   const int N = (int)L.N;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     int cx, cy, cz;
     cell_xyz<D>(L, i, cx, cy, cz);
     T off = 0;
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      int jp, jm;
+      axis_pm<D>(L, i, cx, cy, cz, ax, jp, jm);
+      off += cp[ax * N + i] * r[jp] * di[jp] + cp[ax * N + jm] * r[jm] * di[jm];
+    }
+    const T d = di[i];
+    z[i] = (c1 - c2) * r[i] * d + c2 * d * off;
+  }
+}
+// Residual of every cell of the level, y = r - A z' (inactive cells 0), with z' = z + a zc(parent)
+// when zc != nullptr (prolongation evaluated on the fly), optionally scaled by dinv.
+template <int D, class T>
+__device__ __forceinline__ void tail_resid(const Level& L, const T* cp, const T* dg, const T* di, const T* r,
+                                           const T* z, const Level& Lc, const T* zc, T a, bool scale, T* y) {
+  const int N = (int)L.N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    int cx, cy, cz;
+    cell_xyz<D>(L, i, cx, cy, cz);
+    auto zp = [&](int j, int x, int yy, int zz) -> T {
+      return zc ? z[j] + a * zc[cell_id<D>(Lc, x >> 1, yy >> 1, zz >> 1)] : z[j];
+    };
+    const T d = dg[i];
+    T az = d * zp(i, cx, cy, cz);
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      int jp, jm;
+      axis_pm<D>(L, i, cx, cy, cz, ax, jp, jm);
+      int xp = cx, yp = cy, zp_ = cz, xm = cx, ym = cy, zm = cz;
+      if (ax == 0) { xp = wrap(cx + 1, L.n[0]); xm = wrap(cx - 1, L.n[0]); }
+      if (ax == 1) { yp = wrap(cy + 1, L.n[1]); ym = wrap(cy - 1, L.n[1]); }
+      if (ax == 2) { zp_ = wrap(cz + 1, L.n[2]); zm = wrap(cz - 1, L.n[2]); }
+      az -= cp[ax * N + i] * zp(jp, xp, yp, zp_) + cp[ax * N + jm] * zp(jm, xm, ym, zm);
+    }
+    const T res = d != T(0) ? r[i] - az : T(0);
+    y[i] = scale ? res * di[i] : res;
+  }
+}
+// Restriction: coarse residual = sum of the children's residuals y
+template <int D, class T>
+__device__ __forceinline__ void tail_restrict(const Level& L, const T* y, const Level& Lc, T* rc) {
+  for (int I = threadIdx.x; I < (int)Lc.N; I += blockDim.x) {
+    int X, Yc, Zc;
+    cell_xyz<D>(Lc, I, X, Yc, Zc);
+    T acc = 0;
+    for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const int cx = 2 * X + dx, cy = 2 * Yc + dy, cz = 2 * Zc + dz;
+          if (cx >= L.n[0] || cy >= L.n[1] || (D == 3 && cz >= L.n[2])) continue;
+          acc += y[cell_id<D>(L, cx, cy, cz)];
+        }
+    rc[I] = acc;
+  }
+}
+// Post-smoothing: z = z' + (c1 - c2) y + c2 dinv sum_faces c y(nb), z' = z + a zc(parent)
+template <int D, class T>
+__device__ __forceinline__ void tail_post(const Level& L, const T* cp, const T* di, const T* y, T* z,
+                                          const Level& Lc, const T* zc, T a, T c1, T c2) {
+  const int N = (int)L.N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    int cx, cy, cz;
+    cell_xyz<D>(L, i, cx, cy, cz);
+    T off = 0;
+#pragma unroll
     for (int ax = 0; ax < D; ++ax) {
       int jp, jm;
       axis_pm<D>(L, i, cx, cy, cz, ax, jp, jm);
       off += cp[ax * N + i] * y[jp] + cp[ax * N + jm] * y[jm];
     }
-    const T di = dinv[i];
-    const T v = di != T(0) ? (c1 - c2) * y[i] + c2 * di * off : T(0);
-    z[i] = add ? z[i] + v : v;
+    const T d = di[i];
+    const T zi = z[i] + a * zc[cell_id<D>(Lc, cx >> 1, cy >> 1, cz >> 1)];
+    z[i] = d != T(0) ? zi + (c1 - c2) * y[i] + c2 * d * off : T(0);
   }
 }
 
 template <int D, class T>
 __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> a) {
   if (*a.stop) return;
-  // descend: pre-smooth from zero, restrict the residual
+  __shared__ __align__(16) unsigned char lds_raw[kTailLdsBytes];
+  T* const lds = reinterpret_cast<T*>(lds_raw);
+  auto R = [&](int l) { return lds + a.lds[l]; };
+  auto Z = [&](int l) { return lds + a.lds[l] + a.L[l].N; };
+  auto Y = [&](int l) { return lds + a.lds[l] + 2 * a.L[l].N; };
+  for (int64_t i = threadIdx.x; i < a.L[a.first].N; i += blockDim.x) R(a.first)[i] = a.r[a.first][i];
+  __syncthreads();
+  // descend: pre-smooth from zero, residual, restriction
   for (int l = a.first; l < a.last; ++l) {
     const Level& L = a.L[l];
-    tail_resid<D, T>(L, a.cp[l], a.dg[l], a.di[l], a.r[l], nullptr, a.t[l]);
+    tail_pre<D, T>(L, a.cp[l], a.di[l], R(l), Z(l), a.c1, a.c2);
     __syncthreads();
-    tail_poly<D, T>(L, a.cp[l], a.di[l], a.t[l], a.z[l], false, a.c1, a.c2);
+    tail_resid<D, T>(L, a.cp[l], a.dg[l], a.di[l], R(l), Z(l), L, (const T*)nullptr, T(0), false, Y(l));
     __syncthreads();
-    const Level& Lc = a.L[l + 1];
-    for (int64_t I = threadIdx.x; I < Lc.N; I += blockDim.x) {
-      int X, Y, Z;
-      cell_xyz<D>(Lc, I, X, Y, Z);
-      T acc = 0;
-      for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-          for (int dx = 0; dx < 2; ++dx) {
-            const int cx = 2 * X + dx, cy = 2 * Y + dy, cz = 2 * Z + dz;
-            if (cx >= L.n[0] || cy >= L.n[1] || (D == 3 && cz >= L.n[2])) continue;
-            const int64_t i = cell_id<D>(L, cx, cy, cz);
-            const T d = a.dg[l][i];
-            if (d == T(0)) continue;
-            acc += a.r[l][i] - apply_row<D, T>(L, a.cp[l], d, a.z[l], i);
-          }
-      a.r[l + 1][I] = acc;
-    }
+    tail_restrict<D, T>(L, Y(l), a.L[l + 1], R(l + 1));
     __syncthreads();
   }
   // coarsest: dense inverse
   {
     const Level& L = a.L[a.last];
     const int n = (int)L.N;
+    const T* rc = R(a.last);
+    T* zc = Z(a.last);
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       double acc = 0.0;
-      for (int j = 0; j < n; ++j) acc += a.inv[i * n + j] * (double)a.r[a.last][j];
-      a.z[a.last][i] = a.dg[a.last][i] == T(0) ? T(0) : (T)acc;
+      for (int j = 0; j < n; ++j) acc += a.inv[i * n + j] * (double)rc[j];
+      zc[i] = a.dg[a.last][i] == T(0) ? T(0) : (T)acc;
     }
     __syncthreads();
   }
-  // ascend: prolongate, post-smooth
+  // ascend: y = dinv (r - A z') and z = z' + smoothing, the prolongation z' = z + a zc on the fly
   for (int l = a.last - 1; l >= a.first; --l) {
     const Level& L = a.L[l];
     const Level& Lc = a.L[l + 1];
-    T* z = a.z[l];
-    for (int64_t i = threadIdx.x; i < L.N; i += blockDim.x) {
-      if (a.dg[l][i] == T(0)) continue;
-      int cx, cy, cz;
-      cell_xyz<D>(L, i, cx, cy, cz);
-      z[i] += a.a * a.z[l + 1][cell_id<D>(Lc, cx >> 1, cy >> 1, cz >> 1)];
-    }
+    tail_resid<D, T>(L, a.cp[l], a.dg[l], a.di[l], R(l), Z(l), Lc, Z(l + 1), a.a, true, Y(l));
     __syncthreads();
-    tail_resid<D, T>(L, a.cp[l], a.dg[l], a.di[l], a.r[l], z, a.t[l]);
-    __syncthreads();
-    tail_poly<D, T>(L, a.cp[l], a.di[l], a.t[l], z, true, a.c1, a.c2);
+    tail_post<D, T>(L, a.cp[l], a.di[l], Y(l), Z(l), Lc, Z(l + 1), a.a, a.c1, a.c2);
     __syncthreads();
   }
+  for (int64_t i = threadIdx.x; i < a.L[a.first].N; i += blockDim.x) a.z[a.first][i] = Z(a.first)[i];
 }
 
 // Tail setup: Galerkin coarsening of levels first+1..last and the dense coarsest inverse
