@@ -231,6 +231,13 @@ ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* ctx, double lo, double hi, doub
 ehdlb_status ehdlb_set_timing(ehdlb_ctx* ctx, int32_t on);
 ehdlb_status ehdlb_timing(ehdlb_ctx* ctx, double* ms3, int64_t* steps);
 
+/* Potential-solve statistics accumulated since the context was created or the last call
+ * with reset != 0 (which clears them after reading).  Per kind k (0: solves of the forward
+ * steps, 1: adjoint solves of ehdlb_adjoint): counts[2k] solves, counts[2k+1] conjugate-
+ * gradient iterations, max_rel0[k] the largest initial relative residual max|b - A x0|/max|b|
+ * of the warm start.  counts: int64[4], max_rel0: double[2] (host, either may be NULL). */
+ehdlb_status ehdlb_solver_stats(ehdlb_ctx* ctx, int32_t reset, int64_t* counts, double* max_rel0);
+
 const char* ehdlb_last_error(const ehdlb_ctx* ctx);
 void ehdlb_destroy(ehdlb_ctx* ctx);
 

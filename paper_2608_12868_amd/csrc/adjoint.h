@@ -62,7 +62,7 @@ struct AdjArgs {
 
 // ----------------------------------------------------------------------------- pass A
 template <class L, class T, bool EHD>
-__global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
+__device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
   using ML = MomLayout<L>;
   using RL = RecLayout<L>;
   constexpr int Q = L::Q;
@@ -78,8 +78,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
     const T dt = a.dt_on;
     const T* rec = a.rec;
     auto R = [&](int f, int64_t i) -> T { return rec[(int64_t)f * N + i]; };
-    int nb[Q];
-    neighbours<L>(a.d, node, nb);
+    // neighbour indices on demand (keeping all Q of them live costs occupancy)
+    const int nx_ = (int)node % a.d.nx, ny_ = ((int)node / a.d.nx) % a.d.ny, nz_ = ((int)node / a.d.nx) / a.d.ny;
+    auto NB = [&](int q) -> int { return neighbour<L>(a.d, nx_, ny_, nz_, q); };
     uint32_t solid = 0;
 
     // ---------------------------------------------------------- forward recompute
@@ -88,11 +89,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
     for (int i = 0; i < 3; ++i) pc[i] = R(RL::PHI + i, node);
     T gr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     T lap[3] = {0, 0, 0};
-    T sig_ax[2 * D];
-    uint8_t fl_ax[2 * D];
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
-      const int m = nb[q];
+      const int m = NB(q);
       const uint8_t fm = a.flags[m];
       if (fm) solid |= 1u << q;
       const T w = T(L::w36[q]) / T(36);
@@ -104,14 +103,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
         gr[i][1] += w * T(L::ey[q]) * v[i];
         if (D == 3) gr[i][2] += w * T(L::ez[q]) * v[i];
         lap[i] += w * (v[i] - pc[i]);
-      }
-#pragma unroll
-      for (int ax = 0; ax < D; ++ax) {
-        if (q == L::axp[ax] || q == L::axm[ax]) {
-          const int k = 2 * ax + (q == L::axp[ax] ? 0 : 1);
-          sig_ax[k] = p.cond[0] * v[0] + p.cond[1] * v[1] + p.cond[2] * v[2];
-          fl_ax[k] = fm;
-        }
       }
     }
 #pragma unroll
@@ -130,7 +121,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) F[c] += mu[i] * gr[i][c];
     }
-    T E[3] = {0, 0, 0}, ge[3] = {0, 0, 0}, side[2 * D], pnb[2 * D], pd_ax[2 * D];
+    // face kk = 2 ax + k (k = 0: +axis, 1: -axis): neighbour flag, conductivity, potential and
+    // Dirichlet value, recomputed wherever needed instead of being kept live
+    struct Face {
+      uint8_t fm;
+      T sig, pn, pd;
+    };
+    auto face = [&](int kk) -> Face {
+      const int ax = kk >> 1;
+      const int q = (kk & 1) == 0 ? L::axp[ax] : L::axm[ax];
+      const int m = NB(q);
+      Face f;
+      f.fm = a.flags[m];
+      f.sig = p.cond[0] * R(RL::PHI, m) + p.cond[1] * R(RL::PHI + 1, m) + p.cond[2] * R(RL::PHI + 2, m);
+      f.pn = f.fm == 0 ? R(RL::POT, m) : T(0);
+      f.pd = (f.fm == 1 || f.fm >= 3) ? (f.fm == 1 ? T(0) : a.volts.v[f.fm - 3]) : T(0);
+      return f;
+    };
+    T E[3] = {0, 0, 0}, ge[3] = {0, 0, 0};
     T phx = 0, sigx = 0, rq = 0, Qs = 0, e2 = 0;
     if (EHD) {
       phx = R(RL::POT, node);
@@ -138,26 +146,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
       rq = R(RL::RHO, node);
 #pragma unroll
       for (int ax = 0; ax < D; ++ax) {
+        T side[2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-          const int q = k == 0 ? L::axp[ax] : L::axm[ax];
-          const int kk = 2 * ax + k;
-          const uint8_t fm = fl_ax[kk];
-          pnb[kk] = T(0);
-          pd_ax[kk] = T(0);
-          if (fm == 0) {
-            pnb[kk] = R(RL::POT, nb[q]);
-            side[kk] = pnb[kk];
-            Qs += T(0.5) * (sigx + sig_ax[kk]) * (pnb[kk] - phx);
-          } else if (fm == 1 || fm >= 3) {
-            pd_ax[kk] = fm == 1 ? T(0) : a.volts.v[fm - 3];
-            side[kk] = T(2) * pd_ax[kk] - phx;
-            Qs += T(2) * sigx * (pd_ax[kk] - phx);
+          const Face f = face(2 * ax + k);
+          if (f.fm == 0) {
+            side[k] = f.pn;
+            Qs += T(0.5) * (sigx + f.sig) * (f.pn - phx);
+          } else if (f.fm == 1 || f.fm >= 3) {
+            side[k] = T(2) * f.pd - phx;
+            Qs += T(2) * sigx * (f.pd - phx);
           } else {
-            side[kk] = phx;
+            side[k] = phx;
           }
         }
-        E[ax] = -T(0.5) * (side[2 * ax] - side[2 * ax + 1]);
+        E[ax] = -T(0.5) * (side[0] - side[1]);
       }
       e2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
 #pragma unroll
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
     // node's opposite slot when bounced back)
     auto lout = [&](int fam, int q) -> T {
       if ((solid >> q) & 1u) return a.lP_next[((int64_t)fam * Q + L::opp[q]) * N + node];
-      return a.lP_next[((int64_t)fam * Q + q) * N + nb[q]];
+      return a.lP_next[((int64_t)fam * Q + q) * N + NB(q)];
     };
     T lu[3] = {0, 0, 0}, lF[3] = {0, 0, 0}, lphi[3] = {0, 0, 0};
 #pragma unroll
@@ -343,12 +346,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
     // ---------------------------------------------------------- flow (reverse)
     {
       T C[6] = {0, 0, 0, 0, 0, 0};  // C_k = sum_q lambda_g*_q P_k[q]  (xx yy zz xy xz yz)
-      T lg[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
         const T lo = lout(0, q);
-        lg[q] = lo;
         const int l2 = ix * ix + iy * iy + iz * iz;
         if (l2 == 0) {
           C[0] -= lo;
@@ -397,8 +398,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
                       exq * ezq * Ck[4] + eyq * ezq * Ck[5]);
         }
         const T w = T(L::w36[q]) / T(36);
-        const T lgeq = lg[q] - ld;
-        const T lFq = T(0.5) * (lg[q] + ld);
+        const T lq = lout(0, q);  // re-read (cache hit) rather than kept live
+        const T lgeq = lq - ld;
+        const T lFq = T(0.5) * (lq + ld);
         const T eu = exq * u[0] + eyq * u[1] + ezq * u[2];
         const T eF = exq * F[0] + eyq * F[1] + ezq * F[2];
         ldrho += lgeq * w;
@@ -461,17 +463,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
         for (int k = 0; k < 2; ++k) {
           const int kk = 2 * ax + k;
           const T lside = (k == 0 ? -T(0.5) : T(0.5)) * lE[ax];
-          const uint8_t fm = fl_ax[kk];
+          const Face f = face(kk);
+          const uint8_t fm = f.fm;
           T lsn = 0, lpn = 0;
           if (fm == 0) {
-            const T hs = T(0.5) * (sigx + sig_ax[kk]);
-            const T dphi = pnb[kk] - phx;
+            const T hs = T(0.5) * (sigx + f.sig);
+            const T dphi = f.pn - phx;
             lsigx += T(0.5) * dphi * lQs;
             lsn = T(0.5) * dphi * lQs;
             lpn = hs * lQs + lside;
             lpot -= hs * lQs;
           } else if (fm == 1 || fm >= 3) {
-            lsigx += T(2) * (pd_ax[kk] - phx) * lQs;
+            lsigx += T(2) * (f.pd - phx) * lQs;
             lpot -= T(2) * sigx * lQs + lside;
             if (fm >= 3) vloc[fm - 3] += (double)(T(2) * sigx * lQs + T(2) * lside);
           } else {
@@ -529,6 +532,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
   if (EHD) block_reduce<kMaxE, false>(vloc, a.vpart + (int64_t)blockIdx.x * kMaxE);
 }
 
+template <class L, class T, bool EHD>
+__global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
+  adj_a_body<L, T, EHD>(a);
+}
+// FP32: capped at 256 registers so that two waves fit per SIMD (one 8-byte spill in 3D);
+// uncapped, the kernel needs just over 256 and runs one wave per SIMD.  The FP64 variants
+// would spill heavily under the same cap.
+template <class L, bool EHD>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_a32(AdjArgs<float> a) {
+  adj_a_body<L, float, EHD>(a);
+}
+
 // ----------------------------------------------------------------------------- pass B
 // Transposed stencils as gathers.  lphi_out at every node (ghost solids included),
 // lpot_out at fluid nodes.
@@ -557,7 +572,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(Dims d, const uint8_t* __restr
 #pragma unroll
   for (int q = 1; q < Q; ++q) {
     const int x = nb[L::opp[q]];  // y = x + e_q
-    if (flags[x] != 0) continue;
+    // no test of flags[x]: pass A wrote zero stencil cotangents at solid nodes, so the
+    // gathers are unconditional and their loads independent
     const T w = T(L::w36[q]) / T(36);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {

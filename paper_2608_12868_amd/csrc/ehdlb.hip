@@ -8,6 +8,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <type_traits>
 
 #include "../../include/ehdlb.h"
 #include "kernels.h"
@@ -72,6 +73,8 @@ struct ehdlb_ctx {
   // decide how much work is queued before the host looks at the control block (speed only)
   struct CgHistory {
     int last = 0, prev = 0, last_nonzero = 1;
+    int64_t solves = 0, iters = 0;  // statistics (ehdlb_solver_stats)
+    double max_rel0 = 0.0;
   } cg_hist[2];
   ehd::CgCtl hctl{};  // host copy of the solve's control block
   // layout (byte offsets into ws)
@@ -522,6 +525,9 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
   hist.prev = hist.last;
   hist.last = c->last_iters;
   if (c->last_iters > 0) hist.last_nonzero = c->last_iters;
+  ++hist.solves;
+  hist.iters += c->last_iters;
+  if (!h.zero) hist.max_rel0 = std::max(hist.max_rel0, h.rel0);
   return EHDLB_OK;
 }
 
@@ -660,8 +666,8 @@ static ehdlb_status observables_impl(ehdlb_ctx* c, ehdlb_obs* o) {
                      c->ptr<T>(c->off_phi[pi]), c->ptr<T>(c->off_phi[pp]), c->ptr<T>(c->off_u[pp]),
                      c->ptr<T>(c->off_rho[pi]), psum, pmax);
   double* red = c->ptr<double>(c->off_red);
-  hipLaunchKernelGGL((k_final<kObs, false>), dim3(1), dim3(kBlock), 0, c->stream, psum, nb, red);
-  hipLaunchKernelGGL((k_final<1, true>), dim3(1), dim3(kBlock), 0, c->stream, pmax, nb, red + kObs);
+  hipLaunchKernelGGL((k_final_wide<kObs, false>), dim3(1), dim3(kFinalWide), 0, c->stream, psum, nb, red);
+  hipLaunchKernelGGL((k_final_wide<1, true>), dim3(1), dim3(kFinalWide), 0, c->stream, pmax, nb, red + kObs);
   LAUNCHCHK();
   double h[kObs + 1];
   HIPCHK(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, c->stream));
@@ -944,9 +950,12 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
   double* vpart = reinterpret_cast<double*>(J.ws + J.vpart);
   double* vred = reinterpret_cast<double*>(J.ws + J.vred);
   double* vacc = reinterpret_cast<double*>(J.ws + J.vacc);
-  hipLaunchKernelGGL((k_adj_a<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, a);
+  if constexpr (std::is_same<T, float>::value)
+    hipLaunchKernelGGL((k_adj_a32<LT, EHD>), dim3(nb), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_adj_a<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, a);
   if (EHD) {
-    hipLaunchKernelGGL((k_final<kMaxE, false>), dim3(1), dim3(kBlock), 0, s, vpart, nb, vred);
+    hipLaunchKernelGGL((k_final_wide<kMaxE, false>), dim3(1), dim3(kFinalWide), 0, s, vpart, nb, vred);
     hipLaunchKernelGGL(k_vacc_add, dim3(1), dim3(64), 0, s, vred, vacc, seg, J.nvseg);
   }
   hipLaunchKernelGGL((k_adj_b<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, (const T*)A(J.lgr),
@@ -971,7 +980,7 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
   hipLaunchKernelGGL((k_adj_cd<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, v, rec, (const T*)A(J.lphi),
                      (const T*)A(J.lrho_loc), (const T*)A(lbx), (const T*)A(J.lmom), A(J.lP[cu]), vpart);
   if (EHD) {
-    hipLaunchKernelGGL((k_final<kMaxE, false>), dim3(1), dim3(kBlock), 0, s, vpart, nb, vred);
+    hipLaunchKernelGGL((k_final_wide<kMaxE, false>), dim3(1), dim3(kFinalWide), 0, s, vpart, nb, vred);
     hipLaunchKernelGGL(k_vacc_add, dim3(1), dim3(64), 0, s, vred, vacc, seg, J.nvseg);
   }
   LAUNCHCHK();
@@ -1477,6 +1486,22 @@ ehdlb_status ehdlb_timing(ehdlb_ctx* c, double* ms3, int64_t* steps) {
   if (st) return st;
   for (int j = 0; j < 3; ++j) ms3[j] = c->acc_ms[j];
   if (steps) *steps = c->timed_steps;
+  return EHDLB_OK;
+}
+
+ehdlb_status ehdlb_solver_stats(ehdlb_ctx* c, int32_t reset, int64_t* counts, double* max_rel0) {
+  if (!c) return EHDLB_EINVAL;
+  for (int k = 0; k < 2; ++k) {
+    if (counts) {
+      counts[2 * k] = c->cg_hist[k].solves;
+      counts[2 * k + 1] = c->cg_hist[k].iters;
+    }
+    if (max_rel0) max_rel0[k] = c->cg_hist[k].max_rel0;
+    if (reset) {
+      c->cg_hist[k].solves = c->cg_hist[k].iters = 0;
+      c->cg_hist[k].max_rel0 = 0.0;
+    }
+  }
   return EHDLB_OK;
 }
 

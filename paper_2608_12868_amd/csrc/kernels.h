@@ -59,6 +59,15 @@ __device__ __forceinline__ void chunk_range(int64_t n, int64_t& lo, int64_t& hi)
   hi = lo + per < n ? lo + per : n;
 }
 
+// neighbour of (x, y, z) along link q (periodic wrap), computed on demand
+template <class L>
+__device__ __forceinline__ int neighbour(const Dims& d, int x, int y, int z, int q) {
+  const int xx = wrap(x + L::ex[q], d.nx);
+  const int yy = wrap(y + L::ey[q], d.ny);
+  const int zz = wrap(z + L::ez[q], d.nz);
+  return xx + d.nx * (yy + d.ny * zz);
+}
+
 template <class L>
 __device__ __forceinline__ void neighbours(const Dims& d, int64_t node64, int (&nb)[L::Q]) {
   // node counts are validated below 2^31: 32-bit index arithmetic
@@ -245,6 +254,39 @@ __global__ __launch_bounds__(kBlock) void k_final(const double* __restrict__ par
     for (int k = 0; k < K; ++k) v[k] = MAX ? fmax(v[k], part[(int64_t)b * K + k]) : v[k] + part[(int64_t)b * K + k];
   }
   block_reduce<K, MAX>(v, out);
+}
+
+// k_final for many partial rows: 1024 threads, fixed order (thread t sums rows t, t + 1024, ...,
+// then a fixed tree over the 16 waves).
+constexpr int kFinalWide = 1024;
+template <int K, bool MAX>
+__global__ __launch_bounds__(kFinalWide) void k_final_wide(const double* __restrict__ part, int nblk,
+                                                            double* __restrict__ out) {
+  __shared__ double sm[kFinalWide / 64][K];
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = MAX ? -INFINITY : 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kFinalWide) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = MAX ? fmax(v[k], part[(int64_t)b * K + k]) : v[k] + part[(int64_t)b * K + k];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double y = __shfl_down(x, off, 64);
+      x = MAX ? fmax(x, y) : x + y;
+    }
+    if (lane == 0) sm[wv][k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double x = sm[0][threadIdx.x];
+    for (int w = 1; w < kFinalWide / 64; ++w) x = MAX ? fmax(x, sm[w][threadIdx.x]) : x + sm[w][threadIdx.x];
+    out[threadIdx.x] = x;
+  }
 }
 
 // Sum (or max) of n per-block partials, evaluated by every block in the same fixed order as

@@ -157,6 +157,15 @@ class Simulation(Context):
         self._chk(L.lib().ehdlb_adjoint(self.h, gx.ctypes.data, gv.ctypes.data, int(electrode), out.ctypes.data))
         return out
 
+    def solver_stats(self, reset=False):
+        """Potential-solve statistics per kind (forward steps, adjoint): solves, CG iterations,
+        largest initial relative residual."""
+        counts = np.zeros(4, dtype=np.int64)
+        rel0 = np.zeros(2)
+        self._chk(L.lib().ehdlb_solver_stats(self.h, 1 if reset else 0, counts.ctypes.data, rel0.ctypes.data))
+        return {k: dict(solves=int(counts[2 * j]), iters=int(counts[2 * j + 1]), max_rel0=float(rel0[j]))
+                for j, k in enumerate(("forward", "adjoint"))}
+
     def set_solver_options(self, lo=0.5, hi=2.0, overcorrect=2.0):
         """Chebyshev smoothing interval [lo, hi] of D^-1 A and coarse-correction scale."""
         self._chk(L.lib().ehdlb_set_solver_options(self.h, float(lo), float(hi), float(overcorrect)))
