@@ -1,13 +1,17 @@
 """Benchmark of the ternary EHD lattice-Boltzmann step on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c2-fp64|c1]
+    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c2-fp64|c1] [--adjoint c4|c5|none]
 
 Prints one JSON line: throughput in MLUPS (million lattice-node updates per
-second, all nodes counted) of whole steps (moments and wetting ghosts,
-potential solve to tolerance, fused collide-stream of all population
-families), with inputs resident in HBM; the roofline of the dominant kernel
-(the fused collide-stream) from its algorithmic bytes and its HIP-event time;
-and the FP64 CPU oracle timed on a bounded sample of the same physics.
+second, all nodes counted; fluid-only MLUPS beside it) of whole steps (moments
+and wetting ghosts, potential solve to tolerance, fused collide-stream of all
+population families), with inputs resident in HBM; the roofline of the dominant
+kernel (the fused collide-stream) from its algorithmic bytes and its HIP-event
+time; a plain device-copy ceiling; the FP64 CPU oracle timed on a bounded
+sample of the same physics; and the adjoint leg: the cost of the gradient of
+the droplet centroid with respect to a piecewise-constant electrode schedule
+relative to the forward run, with its error stated against the FP64 adjoint
+and against central finite differences of the FP64 forward.
 """
 import argparse
 import hashlib
@@ -84,6 +88,123 @@ def copy_ceiling(nbytes=1 << 30, reps=10):
     return dict(bytes_per_copy=2 * nbytes, gbs=2 * nbytes / (ms * 1e-3) / 1e9)
 
 
+ADJOINT = {
+    "c4": ("c4", 4000, 100, 3, "2D D2Q9 ternary EHD LB, 512x256 (pillars, droplet R=40, electrode), FP32-deviation "
+                               "storage, 64-segment voltage schedule, T=4000, checkpoint every 100 steps"),
+    "c5": ("c5", 2000, 50, 1, "3D D3Q19 ternary EHD LB, 384x192x128 (pillars pitch 12, droplet R=48, electrode "
+                              "strip), FP32-deviation storage, 32-segment schedule, T=2000, checkpoint every 50"),
+}
+
+
+def adjoint_leg(key, fd_h=1e-4, seed=1):
+    """Cost of dL/dV for L = (x_c(T) - x*)^2 (x* = initial centroid + 5 lu): plain forward,
+    checkpointed forward and reverse sweep (recompute included), timed with device syncs; the
+    FP32 gradient's error against the FP64 adjoint (where it fits in memory) and the directional
+    derivatives of both against central differences of the FP64 forward."""
+    import numpy as np
+    import torch
+    from inputs import make_case
+    from paper_2608_12868_amd import Simulation
+    name, T, K, ndir, desc = ADJOINT[key]
+    torch.cuda.reset_peak_memory_stats()
+    case = make_case(name)
+    sim = Simulation.from_case(case, precision="fp32", poisson_tol=1e-5)
+    sim.set_schedule(0, case.schedule, case.t_total)
+    sim.step(10)
+    sim.set_phase(case.phi)
+    x0 = sim.observables()["centroid"].copy()
+    target = x0[0] + 5.0
+    sim.solver_stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(T)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    st_f = sim.solver_stats(reset=True)
+    sim.set_phase(case.phi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.forward_checkpointed(T, K)
+    torch.cuda.synchronize()
+    t_ck = time.perf_counter() - t0
+    xT = sim.observables()["centroid"]
+    gx = np.array([2.0 * (xT[0] - target), 0.0, 0.0])
+    sim.solver_stats(reset=True)
+    t0 = time.perf_counter()
+    g32 = sim.adjoint(gx, np.zeros(3), 0, len(case.schedule))
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    st_a = sim.solver_stats()["adjoint"]
+    peak32 = torch.cuda.max_memory_allocated() / 1e9
+    ws = sim.adjoint_workspace_bytes(T, K) / 1e9
+    del sim
+    torch.cuda.empty_cache()
+
+    # FP64: adjoint (when the checkpoints fit) and central differences of the forward
+    case64 = make_case(name, precision="fp64")
+    s64 = Simulation.from_case(case64, precision="fp64")
+    g64 = None
+    t64 = {}
+
+    def loss(v):
+        s64.set_phase(case64.phi)
+        s64.set_schedule(0, v, case64.t_total)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s64.step(T)
+        torch.cuda.synchronize()
+        t64["forward_s"] = time.perf_counter() - t0
+        return float((s64.observables()["centroid"][0] - target) ** 2)
+
+    if key == "c4":
+        loss(case64.schedule)
+        s64.set_phase(case64.phi)
+        s64.set_schedule(0, case64.schedule, case64.t_total)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s64.forward_checkpointed(T, K)
+        torch.cuda.synchronize()
+        t64["checkpointed_forward_s"] = time.perf_counter() - t0
+        x64 = s64.observables()["centroid"]
+        t0 = time.perf_counter()
+        g64 = s64.adjoint(np.array([2.0 * (x64[0] - target), 0.0, 0.0]), np.zeros(3), 0, len(case64.schedule))
+        torch.cuda.synchronize()
+        t64["adjoint_s"] = time.perf_counter() - t0
+        t64["ratio_adjoint_to_forward"] = t64["adjoint_s"] / t64["forward_s"]
+        s64.adj_ws = None
+        torch.cuda.empty_cache()
+
+    rng = np.random.default_rng(seed)
+    fd = []
+    for _ in range(ndir):
+        d = rng.standard_normal(len(case.schedule))
+        d /= np.linalg.norm(d)
+        f = (loss(case64.schedule + fd_h * d) - loss(case64.schedule - fd_h * d)) / (2 * fd_h)
+        row = {"fd": f, "fp32_adjoint": float(g32 @ d), "fp32_rel_err": abs(float(g32 @ d) - f) / abs(f)}
+        if g64 is not None:
+            row.update(fp64_adjoint=float(g64 @ d), fp64_rel_err=abs(float(g64 @ d) - f) / abs(f))
+        fd.append(row)
+    out = {
+        "workload": desc,
+        "forward_s": t_fwd,
+        "checkpointed_forward_s": t_ck,
+        "adjoint_s": t_adj,
+        "ratio_adjoint_to_forward": t_adj / t_fwd,
+        "ratio_gradient_to_forward": (t_ck + t_adj) / t_fwd,
+        "forward_mlups": case.N * T / t_fwd / 1e6,
+        "potential_iters_per_step": {"forward": st_f["forward"]["iters"] / T, "adjoint": st_a["iters"] / T},
+        "adjoint_workspace_gb": ws,
+        "peak_hbm_gb": peak32,
+        "fd_h": fd_h,
+        "fd_directions": fd,
+        "fd_rel_err_max": {k: max(r[k] for r in fd) for k in ("fp32_rel_err", "fp64_rel_err") if k in fd[0]},
+    }
+    if g64 is not None:
+        out["grad_rel_err_fp32_vs_fp64"] = float(np.abs(g32 - g64).max() / np.abs(g64).max())
+        out["fp64"] = t64
+    return out
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle, as it stands, on a bounded sample: the 48x32x24 3D lattice with the same
     structure (D3Q19, pillars, lubricant, droplet, electrode, field on)."""
@@ -111,9 +232,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also time a plain 1 GiB device copy (practical bandwidth ceiling; the "
+    ap.add_argument("--no-copy-probe", action="store_true",
+                    help="skip the plain 1 GiB device copy (practical bandwidth ceiling; the "
                          "calibration kernel of the rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--adjoint", default="c4", choices=sorted(ADJOINT) + ["none"],
+                    help="adjoint leg: c4 (2D, default, about half a minute), c5 (3D at scale: "
+                         "about 250 GB of HBM and two minutes), none")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the step is built for a single MI355X (multi-GPU slab "
@@ -133,6 +257,7 @@ def main():
     sim = Simulation.from_case(case, precision=prec, **over)
     sim.step(args.warmup)
     torch.cuda.synchronize()
+    sim.solver_stats(reset=True)
     sim.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -141,6 +266,7 @@ def main():
     t1 = time.perf_counter()
     ms3, nt = sim.timing()
     sim.set_timing(False)
+    stats = sim.solver_stats(reset=True)["forward"]
     obs = sim.observables()
     wall = t1 - t0
     N = case.N
@@ -155,6 +281,7 @@ def main():
         "metric": METRIC,
         "value": N * args.steps / wall / 1e6,
         "unit": "MLUPS",
+        "fluid_mlups": nfluid * args.steps / wall / 1e6,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -170,11 +297,17 @@ def main():
         "phase_ms_per_step": {"moments_ghosts": ms3[0] / max(nt, 1), "potential_solve": ms3[1] / max(nt, 1),
                               "fused_step": step_ms},
         "fused_step_bytes_per_fluid_node": bpn,
+        "potential_iters_per_step": stats["iters"] / max(stats["solves"], 1),
         "potential_iters_last_step": obs["poisson_iters"],
         "potential_residual_last_step": obs["poisson_residual"],
     }
-    if args.copy_probe:
+    if not args.no_copy_probe:
         out["copy_ceiling"] = copy_ceiling()
+        out["copy_ceiling"]["fused_step_frac_of_copy"] = achieved / out["copy_ceiling"]["gbs"]
+    del sim
+    torch.cuda.empty_cache()
+    if args.adjoint != "none":
+        out["adjoint"] = adjoint_leg(args.adjoint)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
