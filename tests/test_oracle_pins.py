@@ -10,6 +10,7 @@ V8  charge relaxation at rate sigma/eps in a uniform medium (Eq. 14)
 V9  Maxwell-stress jump across a flat dielectric interface, and the Coulomb force (Eq. 12)
 V10 per-component mass conservation and the charge balance
 V11 the potential solve's adjoint against finite differences
+V12 advection-diffusion of charge in a uniform flow (the convective part of Eq. 14)
 """
 import math
 
@@ -318,3 +319,51 @@ def test_v11_oracle_schedule_gradient_vs_finite_differences():
             vals.append(float((torch.tensor(gx) * xc).sum() + (torch.tensor(gv) * vc).sum()))
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - float(g[k])) <= 1e-5 * max(abs(fd), 1e-300) + 1e-16
+
+
+# ---------------------------------------------------------------- V12
+def test_v12_charge_advection_diffusion():
+    """Convected charge (Eq. 14 with sigma = 0): a small charge mode A cos(kx) in a uniform flow
+    u0 along x evolves as advection-diffusion with the charge diffusivity alpha = cs^2 (tau_e - 1/2):
+    between t1 and t2 its amplitude falls by exp(-alpha k^2 (t2 - t1)) and its phase advances by
+    k u0 (t2 - t1).  Populations start at equilibrium, so the nearly non-dissipative first-order
+    charge moment (tau_e = 0.53) carries a start-up transient decaying by |1 - 1/tau_e| = 0.89 per
+    step (worth ~8 extra steps of diffusion); the comparison window starts after it.  Rows far
+    from the channel's no-slip walls (boundary layer ~ sqrt(nu t) = 8 lu at t = 400) are fitted;
+    the mode moves by ~1 rad over the window, so a dropped or sign-flipped convective term, or a
+    wrong diffusivity, fails."""
+    from oracle import model
+    nx, ny, t1, t2 = 64, 96, 200, 400
+    u0, alpha, A = 0.05, 0.01, 1e-8
+    case = pc.capacitor(nx=nx, ny=ny, top=GROUND, ehd=1, cond=(0.0, 0.0, 0.0), charge_diffusion=alpha,
+                        electrode_volts=(0, 0, 0, 0))
+    n, per, p, fl, phi = case
+    o = Oracle(2, n, per, p, fl)
+    x, y, _ = pc.grid(n)
+    k = 2 * math.pi / nx
+    rho0 = np.where(fl == FLUID, A * np.cos(k * x), 0.0)
+    s = o.init_state(phi, rho0)
+    lat = o.lat
+    u = torch.zeros(3, o.N, dtype=F64)
+    u[0] = u0 * o.fl
+    phi_t = torch.as_tensor(phi, dtype=F64)
+    s.g = model.flow_equilibrium(torch.zeros(o.N, dtype=F64), u, lat) * o.fl
+    s.f = torch.stack([model.phase_equilibrium(phi_t[i], u, lat) for i in range(3)]) * o.fl
+    s.h = model.phase_equilibrium(torch.as_tensor(rho0, dtype=F64), u, lat) * o.fl
+    s.u_prev = u.clone()
+    fits = {}
+    for t in range(1, t2 + 1):
+        s, aux = o.step(s)
+        if t in (t1, t2):
+            rows = o.fields(s)["rho_e"].numpy().reshape(ny, nx)[ny // 2 - 8: ny // 2 + 8]
+            c = (rows * np.cos(k * np.arange(nx))).sum(1) * 2 / nx
+            sn = (rows * np.sin(k * np.arange(nx))).sum(1) * 2 / nx
+            fits[t] = (np.hypot(c, sn), np.arctan2(sn, c))
+    ratio = fits[t2][0] / fits[t1][0]
+    advance = fits[t2][1] - fits[t1][1]
+    ratio_ref = math.exp(-alpha * k * k * (t2 - t1))
+    advance_ref = k * u0 * (t2 - t1)
+    print("amplitude ratio", ratio.min(), ratio.max(), ratio_ref, "phase advance", advance.min(), advance.max(),
+          advance_ref)
+    assert np.abs(ratio / ratio_ref - 1).max() < 1e-4
+    assert np.abs(advance - advance_ref).max() < 1e-3
