@@ -378,8 +378,12 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot
   hipLaunchKernelGGL((k_smooth2<D, T>), dim3(nb), dim3(kBlock), 0, s, stop, L, cp, di, r, z, c1, c2);
   MGLevel& mc = c->mg[lvl + 1];
   T* rc = c->ptr<T>(mc.r);
-  hipLaunchKernelGGL((k_restrict_resid<D, T>), dim3(nblocks(mc.L.N)), dim3(kBlock), 0, s, stop, L, cp, dg, r, z, mc.L,
-                     rc);
+  {
+    constexpr int TX = restrict_tile_x<D>();
+    const int ntx = (L.n[0] + TX - 1) / TX, nty = (L.n[1] + 1) / 2, ntz = D == 3 ? (L.n[2] + 1) / 2 : 1;
+    hipLaunchKernelGGL((k_restrict_tile<D, T>), dim3(ntx * nty * ntz), dim3(kBlock), 0, s, stop, L, (const T*)cp,
+                       (const T*)dg, (const T*)r, (const T*)z, mc.L, rc);
+  }
   LAUNCHCHK();
   T* zc = nullptr;
   ehdlb_status st = vcycle<D, T>(c, lvl + 1, rc, &zc, nullptr, nullptr);

@@ -419,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_pois_setup(Dims d, const uint8_t* __
                                                         Phys<T> p, Volts<T> volts,
                                                         T* __restrict__ cp, T* __restrict__ diag,
                                                         T* __restrict__ b) {
-  const int64_t node = gidx();
+  const int64_t node = sidx();
   if (node >= d.N) return;
   const int64_t N = d.N;
   if (flags[node] != 0) {
@@ -428,27 +428,23 @@ __global__ __launch_bounds__(kBlock) void k_pois_setup(Dims d, const uint8_t* __
     b[node] = T(0);
     return;
   }
-  int nb[L::Q];
-  neighbours<L>(d, node, nb);
+  const int x = (int)node % d.nx, yz = (int)node / d.nx, y = yz % d.ny, z = yz / d.ny;
   const T ex = p.eps[0] * phi[node] + p.eps[1] * phi[N + node] + p.eps[2] * phi[2 * N + node];
   T dg = 0, rhs = rho ? rho[node] : T(0);
+  // axis neighbours only; their loads do not wait for the flag test
 #pragma unroll
   for (int ax = 0; ax < L::D; ++ax) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int q = k == 0 ? L::axp[ax] : L::axm[ax];
-      const int m = nb[q];
+      const int m = neighbour<L>(d, x, y, z, q);
       const uint8_t fm = flags[m];
-      T c = 0;
-      if (fm == 0) {
-        const T em = p.eps[0] * phi[m] + p.eps[1] * phi[N + m] + p.eps[2] * phi[2 * N + m];
-        c = T(0.5) * (ex + em);
-        dg += c;
-      } else if (fm == 1 || fm >= 3) {
-        const T cd = T(2) * ex;
-        dg += cd;
-        rhs += cd * (fm == 1 ? T(0) : volts.v[fm - 3]);
-      }
+      const T em = p.eps[0] * phi[m] + p.eps[1] * phi[N + m] + p.eps[2] * phi[2 * N + m];
+      const bool fluid = fm == 0, dirichlet = fm == 1 || fm >= 3;
+      const T c = fluid ? T(0.5) * (ex + em) : T(0);
+      const T cd = T(2) * ex;
+      dg += fluid ? c : (dirichlet ? cd : T(0));
+      if (fm >= 3) rhs += cd * volts.v[fm - 3];
       if (k == 0) cp[(int64_t)ax * N + node] = c;
     }
   }
@@ -882,40 +878,47 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_setup(TailArgs<T> a, doub
   for (int k = threadIdx.x; k < n * n; k += blockDim.x) inv[k] = A[k / n][n + k % n];
 }
 
-// Restriction of the residual r - A z to the coarse level (sum over the children), fused:
-// each coarse cell recomputes the residual of its children.
+// Restriction of the residual r - A z by fine-cell threads.  A block is a tile of whole
+// 2-per-axis aggregates, 64 x 2 x 2 fine cells in 3D (128 x 2 in 2D); each thread forms the
+// residual of its own cell (independent loads, like the smoother), x pairs are summed across
+// adjacent lanes and the y/z pairs through LDS.  Grid: ceil(nx/TX) x ceil(ny/2) x ceil(nz/2).
+template <int D>
+constexpr int restrict_tile_x() { return D == 3 ? 64 : 128; }
 template <int D, class T>
-__global__ __launch_bounds__(kBlock) void k_restrict_resid(const int* __restrict__ stop, Level Lf,
-                                                            const T* __restrict__ cp, const T* __restrict__ diag,
-                                                            const T* __restrict__ r, const T* __restrict__ z,
-                                                            Level Lc, T* __restrict__ rc) {
+__global__ __launch_bounds__(kBlock) void k_restrict_tile(const int* __restrict__ stop, Level Lf,
+                                                           const T* __restrict__ cp, const T* __restrict__ diag,
+                                                           const T* __restrict__ r, const T* __restrict__ z,
+                                                           Level Lc, T* __restrict__ rc) {
   if (*stop) return;
-  const int64_t I = sidx();
-  if (I >= Lc.N) return;
-  int X, Y, Z;
-  cell_xyz<D>(Lc, I, X, Y, Z);
-  T acc = 0;
-  for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
-    for (int dy = 0; dy < 2; ++dy)
-      for (int dx = 0; dx < 2; ++dx) {
-        const int cx = 2 * X + dx, cy = 2 * Y + dy, cz = 2 * Z + dz;
-        if (cx >= Lf.n[0] || cy >= Lf.n[1] || (D == 3 && cz >= Lf.n[2])) continue;
-        const int64_t i = cell_id<D>(Lf, cx, cy, cz);
-        const T dg = diag[i];
-        if (dg == T(0)) continue;
-        T az = dg * z[i];
+  constexpr int TX = restrict_tile_x<D>();
+  constexpr int NS = D == 3 ? 4 : 2;  // fine rows per tile: (dy, dz)
+  constexpr int NP = TX / 2;          // coarse cells per tile
+  const int ntx = (Lf.n[0] + TX - 1) / TX;
+  const int nty = (Lf.n[1] + 1) / 2;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int bx = b % ntx;
+  const int by = (b / ntx) % nty;
+  const int bz = D == 3 ? b / (ntx * nty) : 0;
+  const int t = threadIdx.x;
+  const int tx = t % TX, sub = t / TX;
+  const int cx = bx * TX + tx, cy = 2 * by + (sub & 1), cz = 2 * bz + (sub >> 1);
+  T res = 0;
+  if (cx < Lf.n[0] && cy < Lf.n[1] && (D == 2 || cz < Lf.n[2])) {
+    const int i = (int)cell_id<D>(Lf, cx, cy, cz);
+    const T dg = diag[i];
+    if (dg != T(0)) res = r[i] - apply_row<D, T>(Lf, cp, dg, z, i);
+  }
+  res += __shfl_xor(res, 1, 64);
+  __shared__ T sm[NS][NP];
+  if ((tx & 1) == 0) sm[sub][tx >> 1] = res;
+  __syncthreads();
+  if (t < NP) {
+    T acc = 0;
 #pragma unroll
-        for (int ax = 0; ax < D; ++ax) {
-          int xp = cx, yp = cy, zp = cz, xm = cx, ym = cy, zm = cz;
-          if (ax == 0) { xp = wrap(cx + 1, Lf.n[0]); xm = wrap(cx - 1, Lf.n[0]); }
-          if (ax == 1) { yp = wrap(cy + 1, Lf.n[1]); ym = wrap(cy - 1, Lf.n[1]); }
-          if (ax == 2) { zp = wrap(cz + 1, Lf.n[2]); zm = wrap(cz - 1, Lf.n[2]); }
-          const int64_t jp = cell_id<D>(Lf, xp, yp, zp), jm = cell_id<D>(Lf, xm, ym, zm);
-          az -= cp[(int64_t)ax * Lf.N + i] * z[jp] + cp[(int64_t)ax * Lf.N + jm] * z[jm];
-        }
-        acc += r[i] - az;
-      }
-  rc[I] = acc;
+    for (int k = 0; k < NS; ++k) acc += sm[k][t];
+    const int X = bx * NP + t;
+    if (X < Lc.n[0]) rc[cell_id<D>(Lc, X, by, bz)] = acc;
+  }
 }
 
 // Galerkin coarse operator of piecewise-constant aggregation: diag_I = sum of the
