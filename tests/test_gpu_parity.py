@@ -129,3 +129,67 @@ def test_mass_conservation_config2_full():
     ob = sim.observables()
     assert np.all(np.abs(ob["mass"] - m0) / m0 <= 1e-12)
     assert ob["poisson_residual"] <= case.params["poisson_tol"]
+
+
+# ---------------------------------------------------------------- edge cases
+def _droplet_case(n, periodic, radius, volts=0.05, electrode=True):
+    """Droplet of phase 1 in phase 3 on a grounded bottom wall, insulating top wall with an
+    electrode patch (odd sizes allowed); the field on."""
+    from inputs import default_params
+    from inputs.presets import ELECTRODE0, GROUND, NEUMANN, FLUID
+    import pin_cases as pc
+    dim = 3 if n[2] > 1 else 2
+    x, y, z = pc.grid(n)
+    h = z if dim == 3 else y
+    top = n[dim - 1] - 1
+    flags = np.zeros(x.size, np.uint8)
+    flags[h == 0] = GROUND
+    flags[h == top] = NEUMANN
+    if electrode:
+        patch = (h == top) & (x >= n[0] // 2) & (x < n[0] // 2 + max(4, n[0] // 4))
+        flags[patch] = ELECTRODE0
+    cx = n[0] / 3.0
+    r2 = (x - cx) ** 2 + (h - 0.5) ** 2
+    if dim == 3:
+        r2 = r2 + (y - n[1] / 2.0) ** 2
+    p1 = 0.5 * (1 + np.tanh(2 * (radius - np.sqrt(r2)) / 4.0))
+    phi = np.stack([p1, np.zeros_like(p1), 1 - p1])
+    phi[:, flags != FLUID] = 0
+    params = default_params(dim, ehd=1, electrode_volts=(volts, 0.0, 0.0, 0.0), charge_diffusion=1e-3)
+    return dim, n, periodic, params, flags, phi
+
+
+def _run_pair(dim, n, periodic, params, flags, phi, steps):
+    from paper_2608_12868_amd import Simulation
+    from oracle import Oracle
+    gu.require_gpu()
+    sim = Simulation(dim, n, periodic, "fp64", params, flags, phi)
+    sim.step(steps)
+    o = Oracle(dim, n, periodic, params, flags)
+    s = o.init_state(phi)
+    aux = None
+    for _ in range(steps):
+        s, aux = o.step(s)
+    return sim, o, s, aux
+
+
+@pytest.mark.parametrize("n,periodic", [((75, 41, 1), (1, 0, 0)), ((29, 23, 19), (1, 1, 0)),
+                                        ((40, 24, 1), (1, 0, 0))])
+def test_fp64_parity_ragged_sizes(n, periodic):
+    """Odd and non-tile-multiple lattice sizes (partial aggregates and tiles on every multigrid
+    level); 40x24 keeps the whole hierarchy in the single-workgroup tail."""
+    case = _droplet_case(n, periodic, radius=min(n[0], n[-1] if n[2] > 1 else n[1]) / 3.0)
+    print("ragged", n, flush=True)
+    sim, o, s, aux = _run_pair(*case, steps=40)
+    _compare(sim, o, s, aux, FP64_TOL)
+
+
+def test_fp64_zero_potential():
+    """Field on with every electrode at 0 V and no charge: the Gauss law's right-hand side
+    vanishes, the potential is exactly zero and no iteration runs."""
+    case = _droplet_case((64, 36, 1), (1, 0, 0), radius=10.0, volts=0.0)
+    sim, o, s, aux = _run_pair(*case, steps=20)
+    assert np.all(sim.field("pot") == 0.0)
+    ob = sim.observables()
+    assert ob["poisson_iters"] == 0 and ob["poisson_residual"] == 0.0
+    _compare(sim, o, s, aux, FP64_TOL)
