@@ -375,6 +375,24 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot
   T* z = c->ptr<T>(m.z);
   T* t = c->ptr<T>(m.t);
   const int nb = nblocks(L.N);
+  if (lvl > 0 && L.N <= small_level_max<D>()) {
+    // small level: two launches (down, up) instead of four; the result is in t
+    MGLevel& mc = c->mg[lvl + 1];
+    T* rc = c->ptr<T>(mc.r);
+    constexpr int TX = restrict_tile_x<D>();
+    const int ntx = (L.n[0] + TX - 1) / TX, nty = (L.n[1] + 1) / 2, ntz = D == 3 ? (L.n[2] + 1) / 2 : 1;
+    hipLaunchKernelGGL((k_down_small<D, T>), dim3(ntx * nty * ntz), dim3(kBlock), 0, s, stop, L, (const T*)cp,
+                       (const T*)dg, (const T*)di, r, z, mc.L, rc, c1, c2);
+    LAUNCHCHK();
+    T* zc = nullptr;
+    ehdlb_status st = vcycle<D, T>(c, lvl + 1, rc, &zc, nullptr, nullptr);
+    if (st) return st;
+    hipLaunchKernelGGL((k_up_small<D, T>), dim3(nb), dim3(kBlock), 0, s, stop, L, (const T*)cp, (const T*)dg,
+                       (const T*)di, (const T*)r, (const T*)z, mc.L, (const T*)zc, a, c1, c2, t);
+    LAUNCHCHK();
+    *zout = t;
+    return EHDLB_OK;
+  }
   hipLaunchKernelGGL((k_smooth2<D, T>), dim3(nb), dim3(kBlock), 0, s, stop, L, cp, di, r, z, c1, c2);
   MGLevel& mc = c->mg[lvl + 1];
   T* rc = c->ptr<T>(mc.r);
@@ -976,10 +994,10 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
     // potential adjoint: A lb = lambda_phi with the operator of step t
     ehdlb_status st = pois_setup<LT, T>(c, rec + (size_t)RL::PHI * N, (const T*)nullptr, v);
     if (st) return st;
-    HIPCHK(hipMemcpyAsync(c->ptr<T>(c->off_b), A(J.lpot), N * sizeof(T), hipMemcpyDeviceToDevice, s));
-    // warm start from the adjoint potential of step t+2 (same parity: the adjoint of the
-    // over-relaxed first moments alternates in sign from step to step); zero at the start
-    if ((st = pcg<LT, T>(c, A(lbx), c->ptr<T>(c->off_b), c->cg_hist[1]))) return st;
+    // right-hand side lambda_phi read in place; warm start from the adjoint potential of step
+    // t+2 (same parity: the adjoint of the over-relaxed first moments alternates in sign from
+    // step to step); zero at the start
+    if ((st = pcg<LT, T>(c, A(lbx), (const T*)A(J.lpot), c->cg_hist[1]))) return st;
   }
   hipLaunchKernelGGL((k_adj_cd<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, v, rec, (const T*)A(J.lphi),
                      (const T*)A(J.lrho_loc), (const T*)A(lbx), (const T*)A(J.lmom), A(J.lP[cu]), vpart);

@@ -921,6 +921,157 @@ __global__ __launch_bounds__(kBlock) void k_restrict_tile(const int* __restrict_
   }
 }
 
+// ---- small levels: the four passes of a level fused into two by recomputation -----------
+// On small levels the kernels are launch-latency bound, so each thread can recompute what it
+// needs at its neighbours (from L2-resident data) instead of waiting for a separate pass.  The
+// values a thread recomputes are bit-identical to those the owning thread stores: both call the
+// same device functions.  Measured on MI355X: faster for 2D levels of up to 128K cells (5-point
+// stencil), slower for 3D levels (the 7-point recomputation costs more than the launch saved),
+// so only 2D levels use it.
+template <int D>
+constexpr int64_t small_level_max() { return D == 2 ? 131072 : 0; }
+
+// coordinates of the +axis (sgn = 1) or -axis (sgn = -1) neighbour, periodic wrap
+template <int D>
+__device__ __forceinline__ void nbr_xyz(const Level& L, int x, int y, int z, int ax, int sgn, int& xo, int& yo,
+                                        int& zo) {
+  xo = x;
+  yo = y;
+  zo = z;
+  if (ax == 0) xo = wrap(x + sgn, L.n[0]);
+  if (ax == 1) yo = wrap(y + sgn, L.n[1]);
+  if (ax == 2) zo = wrap(z + sgn, L.n[2]);
+}
+
+// pre-smoothing from zero at cell p = (x, y, z) (the formula of k_smooth2)
+template <int D, class T>
+__device__ __forceinline__ T pre_smooth_at(const Level& L, const T* __restrict__ cp, const T* __restrict__ di,
+                                           const T* __restrict__ r, int p, int x, int y, int z, T c1, T c2) {
+  const int N = (int)L.N;
+  T off = 0;
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    int jp, jm;
+    axis_pm<D>(L, p, x, y, z, ax, jp, jm);
+    off += cp[ax * N + p] * r[jp] * di[jp] + cp[ax * N + jm] * r[jm] * di[jm];
+  }
+  const T d = di[p];
+  return (c1 - c2) * r[p] * d + c2 * d * off;
+}
+
+// Down pass of a small level: z = pre-smoothing of r (written), and the restriction of
+// r - A z (tiles of whole aggregates as in k_restrict_tile; the neighbours' z recomputed).
+template <int D, class T>
+__global__ __launch_bounds__(kBlock) void k_down_small(const int* __restrict__ stop, Level Lf,
+                                                        const T* __restrict__ cp, const T* __restrict__ diag,
+                                                        const T* __restrict__ di, const T* __restrict__ r,
+                                                        T* __restrict__ z, Level Lc, T* __restrict__ rc, T c1, T c2) {
+  if (*stop) return;
+  constexpr int TX = restrict_tile_x<D>();
+  constexpr int NS = D == 3 ? 4 : 2;
+  constexpr int NP = TX / 2;
+  const int ntx = (Lf.n[0] + TX - 1) / TX;
+  const int nty = (Lf.n[1] + 1) / 2;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int bx = b % ntx;
+  const int by = (b / ntx) % nty;
+  const int bz = D == 3 ? b / (ntx * nty) : 0;
+  const int t = threadIdx.x;
+  const int tx = t % TX, sub = t / TX;
+  const int cx = bx * TX + tx, cy = 2 * by + (sub & 1), cz = 2 * bz + (sub >> 1);
+  T res = 0;
+  if (cx < Lf.n[0] && cy < Lf.n[1] && (D == 2 || cz < Lf.n[2])) {
+    const int N = (int)Lf.N;
+    const int i = (int)cell_id<D>(Lf, cx, cy, cz);
+    const T zi = pre_smooth_at<D, T>(Lf, cp, di, r, i, cx, cy, cz, c1, c2);
+    z[i] = zi;
+    const T dg = diag[i];
+    if (dg != T(0)) {
+      T az = dg * zi;
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        int jp, jm, xp, yp, zp, xm, ym, zm;
+        axis_pm<D>(Lf, i, cx, cy, cz, ax, jp, jm);
+        nbr_xyz<D>(Lf, cx, cy, cz, ax, 1, xp, yp, zp);
+        nbr_xyz<D>(Lf, cx, cy, cz, ax, -1, xm, ym, zm);
+        az -= cp[ax * N + i] * pre_smooth_at<D, T>(Lf, cp, di, r, jp, xp, yp, zp, c1, c2) +
+              cp[ax * N + jm] * pre_smooth_at<D, T>(Lf, cp, di, r, jm, xm, ym, zm, c1, c2);
+      }
+      res = r[i] - az;
+    }
+  }
+  res += __shfl_xor(res, 1, 64);
+  __shared__ T sm[NS][NP];
+  if ((tx & 1) == 0) sm[sub][tx >> 1] = res;
+  __syncthreads();
+  if (t < NP) {
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) acc += sm[k][t];
+    const int X = bx * NP + t;
+    if (X < Lc.n[0]) rc[cell_id<D>(Lc, X, by, bz)] = acc;
+  }
+}
+
+// prolongated correction z' = z + a zc(parent) at cell p = (x, y, zz)
+template <int D, class T>
+__device__ __forceinline__ T zprime_at(const T* __restrict__ z, const Level& Lc, const T* __restrict__ zc, T a,
+                                       int p, int x, int y, int zz) {
+  return z[p] + a * zc[(x >> 1) + Lc.n[0] * ((y >> 1) + Lc.n[1] * (zz >> 1))];
+}
+// y = dinv (r - A z') at cell p = (x, y, zz) (0 on inactive cells)
+template <int D, class T>
+__device__ __forceinline__ T post_resid_at(const Level& L, const T* __restrict__ cp, const T* __restrict__ dg,
+                                           const T* __restrict__ di, const T* __restrict__ r,
+                                           const T* __restrict__ z, const Level& Lc, const T* __restrict__ zc, T a,
+                                           int p, int x, int y, int zz) {
+  const T d = di[p];
+  if (d == T(0)) return T(0);
+  const int N = (int)L.N;
+  T az = dg[p] * zprime_at<D, T>(z, Lc, zc, a, p, x, y, zz);
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    int jp, jm, xp, yp, zp, xm, ym, zm;
+    axis_pm<D>(L, p, x, y, zz, ax, jp, jm);
+    nbr_xyz<D>(L, x, y, zz, ax, 1, xp, yp, zp);
+    nbr_xyz<D>(L, x, y, zz, ax, -1, xm, ym, zm);
+    az -= cp[ax * N + p] * zprime_at<D, T>(z, Lc, zc, a, jp, xp, yp, zp) +
+          cp[ax * N + jm] * zprime_at<D, T>(z, Lc, zc, a, jm, xm, ym, zm);
+  }
+  return (r[p] - az) * d;
+}
+// Up pass of a small level: zo = z' + (c1 - c2) y + c2 dinv sum_faces c y(nb), with y and z'
+// recomputed at the neighbours; zo is a different buffer from z.
+template <int D, class T>
+__global__ __launch_bounds__(kBlock) void k_up_small(const int* __restrict__ stop, Level L, const T* __restrict__ cp,
+                                                      const T* __restrict__ dg, const T* __restrict__ di,
+                                                      const T* __restrict__ r, const T* __restrict__ z, Level Lc,
+                                                      const T* __restrict__ zc, T a, T c1, T c2, T* __restrict__ zo) {
+  if (*stop) return;
+  const int i = (int)sidx();
+  if (i >= (int)L.N) return;
+  const T d = di[i];
+  if (d == T(0)) {
+    zo[i] = T(0);
+    return;
+  }
+  const int N = (int)L.N;
+  int cx, cy, cz;
+  cell_xyz<D>(L, i, cx, cy, cz);
+  T off = 0;
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    int jp, jm, xp, yp, zp, xm, ym, zm;
+    axis_pm<D>(L, i, cx, cy, cz, ax, jp, jm);
+    nbr_xyz<D>(L, cx, cy, cz, ax, 1, xp, yp, zp);
+    nbr_xyz<D>(L, cx, cy, cz, ax, -1, xm, ym, zm);
+    off += cp[ax * N + i] * post_resid_at<D, T>(L, cp, dg, di, r, z, Lc, zc, a, jp, xp, yp, zp) +
+           cp[ax * N + jm] * post_resid_at<D, T>(L, cp, dg, di, r, z, Lc, zc, a, jm, xm, ym, zm);
+  }
+  const T yi = post_resid_at<D, T>(L, cp, dg, di, r, z, Lc, zc, a, i, cx, cy, cz);
+  zo[i] = zprime_at<D, T>(z, Lc, zc, a, i, cx, cy, cz) + (c1 - c2) * yi + c2 * d * off;
+}
+
 // Galerkin coarse operator of piecewise-constant aggregation: diag_I = sum of the
 // children's diagonals minus twice the faces inside I; cp_I(a) = sum of the fine faces
 // from I to I + e_a.
