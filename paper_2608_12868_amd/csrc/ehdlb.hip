@@ -101,7 +101,7 @@ struct ehdlb_ctx {
     bool ready = false;
     size_t ckpt = 0, fin = 0, rec = 0, lP[2]{}, lphip[2]{}, lup[2]{}, lrhop[2]{}, lqp[2]{};
     size_t lgr = 0, llap = 0, lsig = 0, lpnb = 0, lphi_loc = 0, lpot_loc = 0, lrho_loc = 0, lmom = 0;
-    size_t lphi = 0, lpot = 0, lb = 0, lb2 = 0, vpart = 0, vred = 0, vacc = 0, obs = 0, total = 0, rec_stride = 0;
+    size_t lphi = 0, lpot = 0, lb = 0, lb2 = 0, lbo = 0, lbo2 = 0, vpart = 0, vred = 0, vacc = 0, obs = 0, total = 0, rec_stride = 0;
     int nvseg = 0;
   } adj;
   // potential-solver options (ehdlb_set_solver_options): degree-2 Chebyshev smoothing of the
@@ -852,6 +852,8 @@ static void plan_adjoint(const ehdlb_ctx* c, int64_t T, int K, ehdlb_ctx::Adj& a
   a.lpot = take(N * ts);
   a.lb = take(N * ts);
   a.lb2 = take(N * ts);
+  a.lbo = take(N * ts);
+  a.lbo2 = take(N * ts);
   a.vpart = take((size_t)nblocks(N) * kMaxE * 8);
   a.vred = take(kMaxE * 8);
   a.nvseg = 1 << 16;
@@ -994,9 +996,13 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
     // potential adjoint: A lb = lambda_phi with the operator of step t
     ehdlb_status st = pois_setup<LT, T>(c, rec + (size_t)RL::PHI * N, (const T*)nullptr, v);
     if (st) return st;
-    // right-hand side lambda_phi read in place; warm start from the adjoint potential of step
-    // t+2 (same parity: the adjoint of the over-relaxed first moments alternates in sign from
-    // step to step); zero at the start
+    // right-hand side lambda_phi read in place; warm start extrapolated linearly from the
+    // adjoint potentials of steps t+2 and t+4 (same parity: the adjoint of the over-relaxed first
+    // moments alternates in sign from step to step); zero at the start
+    {
+      const size_t lbo = (t & 1) ? J.lbo2 : J.lbo;
+      hipLaunchKernelGGL(k_extrapolate<T>, dim3(nb), dim3(kBlock), 0, s, N, A(lbx), A(lbo));
+    }
     if ((st = pcg<LT, T>(c, A(lbx), (const T*)A(J.lpot), c->cg_hist[1]))) return st;
   }
   hipLaunchKernelGGL((k_adj_cd<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, v, rec, (const T*)A(J.lphi),
@@ -1052,6 +1058,8 @@ struct AdjFn {
     HIPCHK(hipMemsetAsync(J.ws + J.vacc, 0, (size_t)kMaxE * J.nvseg * 8, s));
     hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, N, A(J.lb));
     hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, N, A(J.lb2));
+    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, N, A(J.lbo));
+    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, N, A(J.lbo2));
     LAUNCHCHK();
     const auto& sch = c->sched[electrode];
     const int nseg = sch.v.empty() ? 1 : (int)sch.v.size();

@@ -1237,6 +1237,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_zero(const CgCtl* __restrict__ ct
   if (i < N) x[i] = T(0);
 }
 
+// Linear extrapolation of a warm start from two earlier solutions: x <- 2 x - older, older <- x
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t N, T* __restrict__ x, T* __restrict__ older) {
+  const int64_t i = gidx();
+  if (i >= N) return;
+  const T v = x[i];
+  x[i] = T(2) * v - older[i];
+  older[i] = v;
+}
+
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_zero(int64_t N, T* __restrict__ x) {
   const int64_t i = gidx();
