@@ -97,10 +97,11 @@ ADJOINT = {
 
 
 def adjoint_leg(key, fd_h=1e-4, seed=1):
-    """Cost of dL/dV for L = (x_c(T) - x*)^2 (x* = initial centroid + 5 lu): plain forward,
-    checkpointed forward and reverse sweep (recompute included), timed with device syncs; the
-    FP32 gradient's error against the FP64 adjoint (where it fits in memory) and the directional
-    derivatives of both against central differences of the FP64 forward."""
+    """Cost of dL/dV for L = (x_c(T) - x*)^2 (x* = initial centroid + 5 lu), FP32 path, with
+    each forward warm start (previous potential; extrapolated from the last two): plain forward,
+    checkpointed forward and reverse sweep (recompute included), timed with device syncs; each
+    gradient's error against the FP64 adjoint (where it fits in memory) and the directional
+    derivatives against central differences of the FP64 forward."""
     import numpy as np
     import torch
     from inputs import make_case
@@ -108,37 +109,47 @@ def adjoint_leg(key, fd_h=1e-4, seed=1):
     name, T, K, ndir, desc = ADJOINT[key]
     torch.cuda.reset_peak_memory_stats()
     case = make_case(name)
-    sim = Simulation.from_case(case, precision="fp32", poisson_tol=1e-5)
-    sim.set_schedule(0, case.schedule, case.t_total)
-    sim.step(10)
-    sim.set_phase(case.phi)
-    x0 = sim.observables()["centroid"].copy()
-    target = x0[0] + 5.0
-    sim.solver_stats(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(T)
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    st_f = sim.solver_stats(reset=True)
-    sim.set_phase(case.phi)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.forward_checkpointed(T, K)
-    torch.cuda.synchronize()
-    t_ck = time.perf_counter() - t0
-    xT = sim.observables()["centroid"]
-    gx = np.array([2.0 * (xT[0] - target), 0.0, 0.0])
-    sim.solver_stats(reset=True)
-    t0 = time.perf_counter()
-    g32 = sim.adjoint(gx, np.zeros(3), 0, len(case.schedule))
-    torch.cuda.synchronize()
-    t_adj = time.perf_counter() - t0
-    st_a = sim.solver_stats()["adjoint"]
+    runs = {}
+    target = None
+    for mode, label in ((0, "warm_previous"), (1, "warm_extrapolated")):
+        sim = Simulation.from_case(case, precision="fp32", poisson_tol=1e-5)
+        sim.set_solver_options(warm_start=mode)
+        sim.set_schedule(0, case.schedule, case.t_total)
+        sim.step(10)
+        sim.set_phase(case.phi)
+        if target is None:
+            target = sim.observables()["centroid"][0] + 5.0
+        sim.solver_stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(T)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        st_f = sim.solver_stats(reset=True)
+        sim.set_phase(case.phi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.forward_checkpointed(T, K)
+        torch.cuda.synchronize()
+        t_ck = time.perf_counter() - t0
+        xT = sim.observables()["centroid"]
+        sim.solver_stats(reset=True)
+        t0 = time.perf_counter()
+        g = sim.adjoint(np.array([2.0 * (xT[0] - target), 0.0, 0.0]), np.zeros(3), 0, len(case.schedule))
+        torch.cuda.synchronize()
+        t_adj = time.perf_counter() - t0
+        st_a = sim.solver_stats()["adjoint"]
+        runs[label] = dict(forward_s=t_fwd, checkpointed_forward_s=t_ck, adjoint_s=t_adj,
+                           ratio_adjoint_to_forward=t_adj / t_fwd,
+                           ratio_gradient_to_forward=(t_ck + t_adj) / t_fwd,
+                           forward_mlups=case.N * T / t_fwd / 1e6,
+                           potential_iters_per_step={"forward": st_f["forward"]["iters"] / T,
+                                                     "adjoint": st_a["iters"] / T},
+                           grad=g)
+        ws = sim.adjoint_workspace_bytes(T, K) / 1e9
+        del sim
+        torch.cuda.empty_cache()
     peak32 = torch.cuda.max_memory_allocated() / 1e9
-    ws = sim.adjoint_workspace_bytes(T, K) / 1e9
-    del sim
-    torch.cuda.empty_cache()
 
     # FP64: adjoint (when the checkpoints fit) and central differences of the forward
     case64 = make_case(name, precision="fp64")
@@ -180,27 +191,29 @@ def adjoint_leg(key, fd_h=1e-4, seed=1):
         d = rng.standard_normal(len(case.schedule))
         d /= np.linalg.norm(d)
         f = (loss(case64.schedule + fd_h * d) - loss(case64.schedule - fd_h * d)) / (2 * fd_h)
-        row = {"fd": f, "fp32_adjoint": float(g32 @ d), "fp32_rel_err": abs(float(g32 @ d) - f) / abs(f)}
+        # relative to the directional derivative, and to the gradient's norm (the first is
+        # inflated on directions where the derivative is much smaller than the gradient)
+        row = {"fd": f}
+        for label, r in runs.items():
+            row[label] = float(r["grad"] @ d)
+            row[label + "_rel_err"] = abs(row[label] - f) / abs(f)
+            row[label + "_err_over_norm"] = abs(row[label] - f) / float(np.linalg.norm(r["grad"]))
         if g64 is not None:
-            row.update(fp64_adjoint=float(g64 @ d), fp64_rel_err=abs(float(g64 @ d) - f) / abs(f))
+            row.update(fp64_adjoint=float(g64 @ d), fp64_rel_err=abs(float(g64 @ d) - f) / abs(f),
+                       fp64_err_over_norm=abs(float(g64 @ d) - f) / float(np.linalg.norm(g64)))
         fd.append(row)
-    out = {
-        "workload": desc,
-        "forward_s": t_fwd,
-        "checkpointed_forward_s": t_ck,
-        "adjoint_s": t_adj,
-        "ratio_adjoint_to_forward": t_adj / t_fwd,
-        "ratio_gradient_to_forward": (t_ck + t_adj) / t_fwd,
-        "forward_mlups": case.N * T / t_fwd / 1e6,
-        "potential_iters_per_step": {"forward": st_f["forward"]["iters"] / T, "adjoint": st_a["iters"] / T},
-        "adjoint_workspace_gb": ws,
-        "peak_hbm_gb": peak32,
-        "fd_h": fd_h,
-        "fd_directions": fd,
-        "fd_rel_err_max": {k: max(r[k] for r in fd) for k in ("fp32_rel_err", "fp64_rel_err") if k in fd[0]},
-    }
+    out = {"workload": desc, "dtype": "f32", "adjoint_workspace_gb": ws, "peak_hbm_gb": peak32, "fd_h": fd_h,
+           "fd_directions": fd}
+    for label, r in runs.items():
+        g = r.pop("grad")
+        r["fd_rel_err_max"] = max(row[label + "_rel_err"] for row in fd)
+        r["fd_err_over_norm_max"] = max(row[label + "_err_over_norm"] for row in fd)
+        if g64 is not None:
+            r["grad_rel_err_vs_fp64_adjoint"] = float(np.abs(g - g64).max() / np.abs(g64).max())
+        out[label] = r
     if g64 is not None:
-        out["grad_rel_err_fp32_vs_fp64"] = float(np.abs(g32 - g64).max() / np.abs(g64).max())
+        t64["fd_rel_err_max"] = max(row["fp64_rel_err"] for row in fd)
+        t64["fd_err_over_norm_max"] = max(row["fp64_err_over_norm"] for row in fd)
         out["fp64"] = t64
     return out
 

@@ -74,7 +74,7 @@ SIGNATURES = {
     "ehdlb_adjoint_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int64, C.c_int32]),
     "ehdlb_forward_checkpointed": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_size_t]),
     "ehdlb_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
-    "ehdlb_set_solver_options": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double]),
+    "ehdlb_set_solver_options": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int32]),
     "ehdlb_solver_stats": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "ehdlb_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "ehdlb_timing": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

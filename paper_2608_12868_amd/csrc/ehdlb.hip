@@ -78,7 +78,9 @@ struct ehdlb_ctx {
   } cg_hist[2];
   ehd::CgCtl hctl{};  // host copy of the solve's control block
   // layout (byte offsets into ws)
-  size_t off_pop[2]{}, off_phi[2]{}, off_rho[2]{}, off_u[2]{}, off_q[2]{}, off_pot = 0;
+  size_t off_pop[2]{}, off_phi[2]{}, off_rho[2]{}, off_u[2]{}, off_q[2]{}, off_pot = 0, off_pot_old = 0;
+  // end of the state region that save_state copies after the populations
+  size_t state_end() const { return off_pot_old + (size_t)N * tsize; }
   size_t off_flags = 0, off_gnode = 0, off_gsrc = 0, off_glen = 0, off_scratch = 0;
   size_t off_b = 0, off_r = 0, off_z = 0, off_p = 0, off_qv = 0, off_spart = 0;
   size_t off_part = 0, off_red = 0, off_cg = 0, off_inv = 0, off_dbl = 0;
@@ -108,6 +110,7 @@ struct ehdlb_ctx {
   // Jacobi-preconditioned operator on [lo, hi], coarse-correction scale
   double mg_lo = 0.5, mg_hi = 2.0;
   double mg_overcorrect = 2.0;
+  bool warm_extrapolate = false;  // forward warm start: previous potential, or extrapolated
   // smoothing polynomial z += c1 y - c2 D^-1 A y: p(mu) = 1 - c1 mu + c2 mu^2 = T2(s(mu))/T2(s(0)),
   // s(mu) = (hi + lo - 2 mu)/(hi - lo)
   void poly(double& c1, double& c2) const {
@@ -218,6 +221,7 @@ static void plan_layout(ehdlb_ctx* c) {
   for (int k = 0; k < 2; ++k) c->off_u[k] = take((size_t)c->D * N * ts);
   for (int k = 0; k < 2; ++k) c->off_q[k] = take(N * ts);
   c->off_pot = take(N * ts);
+  c->off_pot_old = take(N * ts);  // potential of the previous step (warm-start extrapolation)
   // --- geometry
   c->off_flags = take(N);
   c->max_ghost = N;  // upper bound; actual count known at set_geometry
@@ -281,7 +285,7 @@ static void plan_layout(ehdlb_ctx* c) {
   c->off_cg = take(sizeof(CgCtl));
   // solver partials: true residual (3 per block), max|r|, p.q, two r.z
   c->off_spart = take((size_t)kSolverParts * kRedBlocks * 8);
-  c->state_bytes = 256 + align_up((size_t)c->F * c->Q * N * ts) + (c->off_pot + N * ts - c->off_phi[0]);
+  c->state_bytes = 256 + align_up((size_t)c->F * c->Q * N * ts) + (c->state_end() - c->off_phi[0]);
   c->total = o;
 }
 
@@ -571,6 +575,11 @@ template <class LT, class T>
 static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, const Volts<T>& volts) {
   ehdlb_status st = pois_setup<LT, T>(c, phi, rho, volts);
   if (st) return st;
+  // optional warm start extrapolated linearly from the potentials of the two previous steps
+  // (both kept in the saved state, so a replay from a checkpoint takes the same iterates)
+  if (c->warm_extrapolate)
+    hipLaunchKernelGGL(k_extrapolate<T>, dim3(nblocks(c->N)), dim3(kBlock), 0, c->stream, c->N,
+                       c->ptr<T>(c->off_pot), c->ptr<T>(c->off_pot_old));
   return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b), c->cg_hist[0]);
 }
 
@@ -744,6 +753,7 @@ struct InitFn {
     const int64_t npop = (int64_t)c->F * c->Q * N;
     hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(npop)), dim3(kBlock), 0, c->stream, npop, c->ptr<T>(c->off_pop[1]));
     hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, c->stream, N, c->ptr<T>(c->off_pot));
+    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, c->stream, N, c->ptr<T>(c->off_pot_old));
     LAUNCHCHK();
     return EHDLB_OK;
   }
@@ -1412,7 +1422,7 @@ ehdlb_status ehdlb_save_state(ehdlb_ctx* c, void* dst) {
   HIPCHK(hipMemcpyAsync(d, c->hdr, sizeof(c->hdr), hipMemcpyHostToDevice, c->stream));
   const size_t pop_bytes = (size_t)c->F * c->Q * c->N * c->tsize;
   HIPCHK(hipMemcpyAsync(d + 256, c->ws + c->off_pop[c->cur], pop_bytes, hipMemcpyDeviceToDevice, c->stream));
-  const size_t rest = c->off_pot + c->N * c->tsize - c->off_phi[0];
+  const size_t rest = c->state_end() - c->off_phi[0];
   HIPCHK(hipMemcpyAsync(d + 256 + align_up(pop_bytes), c->ws + c->off_phi[0], rest, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return EHDLB_OK;
@@ -1430,7 +1440,7 @@ ehdlb_status ehdlb_load_state(ehdlb_ctx* c, const void* src) {
     return fail(c, EHDLB_EINVAL, "state blob does not match this context");
   const size_t pop_bytes = (size_t)c->F * c->Q * c->N * c->tsize;
   HIPCHK(hipMemcpyAsync(c->ws + c->off_pop[0], s + 256, pop_bytes, hipMemcpyDeviceToDevice, c->stream));
-  const size_t rest = c->off_pot + c->N * c->tsize - c->off_phi[0];
+  const size_t rest = c->state_end() - c->off_phi[0];
   HIPCHK(hipMemcpyAsync(c->ws + c->off_phi[0], s + 256 + align_up(pop_bytes), rest, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->t = hdr[0];
@@ -1487,13 +1497,16 @@ ehdlb_status ehdlb_adjoint(ehdlb_ctx* c, const double* dL_dcentroid, const doubl
   return dispatch<AdjFn>(c, dL_dcentroid, dL_dvelocity, (int)electrode, dL_dvolts);
 }
 
-ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* c, double lo, double hi, double overcorrect) {
+ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* c, double lo, double hi, double overcorrect,
+                                      int32_t warm_start) {
   if (!c) return EHDLB_EINVAL;
   if (!(lo > 0.0 && hi > lo && hi <= 2.0)) return fail(c, EHDLB_EINVAL, "need 0 < lo < hi <= 2");
   if (!(overcorrect > 0.0 && overcorrect <= 4.0)) return fail(c, EHDLB_EINVAL, "over-correction must lie in (0, 4]");
+  if (warm_start != 0 && warm_start != 1) return fail(c, EHDLB_EINVAL, "warm_start must be 0 or 1");
   c->mg_lo = lo;
   c->mg_hi = hi;
   c->mg_overcorrect = overcorrect;
+  c->warm_extrapolate = warm_start != 0;
   return EHDLB_OK;
 }
 
