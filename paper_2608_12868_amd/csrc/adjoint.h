@@ -555,7 +555,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(Dims d, const uint8_t* __restr
                                                    T* __restrict__ lphi_out, T* __restrict__ lpot_out) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
-  const int64_t y = gidx();
+  const int64_t y = sidx();  // XCD-aware order: the gathered neighbours share an L2
   if (y >= d.N) return;
   const int64_t N = d.N;
   const bool fluid = flags[y] == 0;
