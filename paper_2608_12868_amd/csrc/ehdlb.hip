@@ -31,6 +31,8 @@ constexpr int kRedBlocks = 1024;
 // level, fit the tail's LDS run inside the single-workgroup V-cycle tail
 constexpr int64_t kTailMaxCells = 2048;
 constexpr int kSolverParts = 7;
+// MI355X's Infinity Cache (memory-side last-level cache)
+constexpr size_t kInfinityCacheBytes = (size_t)256 << 20;
 int rblocks(int64_t n) { return std::min(nblocks(n), kRedBlocks); }
 
 struct MGLevel {
@@ -110,6 +112,7 @@ struct ehdlb_ctx {
   // Jacobi-preconditioned operator on [lo, hi], coarse-correction scale
   double mg_lo = 0.5, mg_hi = 2.0;
   double mg_overcorrect = 2.0;
+  bool stream_pops = false;       // population loads with the non-temporal hint
   bool warm_extrapolate = false;  // forward warm start: previous potential, or extrapolated
   // smoothing polynomial z += c1 y - c2 D^-1 A y: p(mu) = 1 - c1 mu + c2 mu^2 = T2(s(mu))/T2(s(0)),
   // s(mu) = (hi + lo - 2 mu)/(hi - lo)
@@ -216,6 +219,9 @@ static void plan_layout(ehdlb_ctx* c) {
   };
   // --- state region (save/load copies [state_begin, state_end))
   for (int k = 0; k < 2; ++k) c->off_pop[k] = take((size_t)c->F * c->Q * N * ts);
+  // populations that cannot stay in the Infinity Cache between steps are loaded with the
+  // non-temporal hint (faster there; slightly slower where they stay resident)
+  c->stream_pops = 2 * (size_t)c->F * c->Q * N * ts > kInfinityCacheBytes;
   for (int k = 0; k < 2; ++k) c->off_phi[k] = take(3 * N * ts);
   for (int k = 0; k < 2; ++k) c->off_rho[k] = take(N * ts);
   for (int k = 0; k < 2; ++k) c->off_u[k] = take((size_t)c->D * N * ts);
@@ -599,6 +605,27 @@ static ehdlb_status flush_timing(ehdlb_ctx* c) {
   return EHDLB_OK;
 }
 
+// ============================================================================ launch helpers
+template <class LT, class T>
+static void launch_moments(const ehdlb_ctx* c, int families, const Dims& dm, const uint8_t* flags, const T* pop,
+                           T* phi, T* rho, T* drho, int fam0) {
+  const dim3 grid(nblocks(dm.N), families);
+  if (c->stream_pops)
+    hipLaunchKernelGGL((k_moments<LT, T, true>), grid, dim3(kBlock), 0, c->stream, dm, flags, pop, phi, rho, drho,
+                       fam0);
+  else
+    hipLaunchKernelGGL((k_moments<LT, T, false>), grid, dim3(kBlock), 0, c->stream, dm, flags, pop, phi, rho, drho,
+                       fam0);
+}
+
+template <class LT, class T, bool EHD, bool STORE>
+static void launch_step(const ehdlb_ctx* c, const StepArgs<T>& a) {
+  if (c->stream_pops)
+    hipLaunchKernelGGL((k_step<LT, T, EHD, STORE, true>), dim3(nblocks(a.d.N)), dim3(kBlock), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL((k_step<LT, T, EHD, STORE, false>), dim3(nblocks(a.d.N)), dim3(kBlock), 0, c->stream, a);
+}
+
 // ============================================================================ step
 template <class LT, class T, bool EHD>
 static ehdlb_status step_impl(ehdlb_ctx* c, int64_t n) {
@@ -627,8 +654,7 @@ static ehdlb_status step_impl(ehdlb_ctx* c, int64_t n) {
       c->ev_used += 4;
       HIPCHK(hipEventRecord(ev[0], s));
     }
-    hipLaunchKernelGGL((k_moments<LT, T>), dim3(nblocks(N), EHD ? 4 : 3), dim3(kBlock), 0, s, dm, flags, pin, phi, rho,
-                       (T*)nullptr, 1);
+    launch_moments<LT, T>(c, EHD ? 4 : 3, dm, flags, pin, phi, rho, (T*)nullptr, 1);
     if (G > 0)
       hipLaunchKernelGGL(k_ghosts<T>, dim3(nblocks(G)), dim3(kBlock), 0, s, N, G, c->ptr<int32_t>(c->off_gnode),
                          c->ptr<int32_t>(c->off_gsrc), c->ptr<T>(c->off_glen), phi, ph);
@@ -656,7 +682,7 @@ static ehdlb_status step_impl(ehdlb_ctx* c, int64_t n) {
     a.p = ph;
     a.volts = v;
     a.dt_on = t == 0 ? T(0) : T(1);
-    hipLaunchKernelGGL((k_step<LT, T, EHD>), dim3(nblocks(N)), dim3(kBlock), 0, s, a);
+    launch_step<LT, T, EHD, false>(c, a);
     LAUNCHCHK();
     if (ev) {
       HIPCHK(hipEventRecord(ev[3], s));
@@ -674,9 +700,9 @@ static ehdlb_status moments_now(ehdlb_ctx* c, T* drho) {
   const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
   const int pi = (int)(c->t & 1);
   // with drho also the flow family (read-out of the pressure)
-  hipLaunchKernelGGL((k_moments<LT, T>), dim3(nblocks(N), (EHD ? 4 : 3) + (drho ? 1 : 0)), dim3(kBlock), 0, c->stream,
-                     dm, c->ptr<uint8_t>(c->off_flags), c->ptr<T>(c->off_pop[c->cur]), c->ptr<T>(c->off_phi[pi]),
-                     c->ptr<T>(c->off_rho[pi]), drho, drho ? 0 : 1);
+  launch_moments<LT, T>(c, (EHD ? 4 : 3) + (drho ? 1 : 0), dm, c->ptr<uint8_t>(c->off_flags),
+                        c->ptr<T>(c->off_pop[c->cur]), c->ptr<T>(c->off_phi[pi]), c->ptr<T>(c->off_rho[pi]), drho,
+                        drho ? 0 : 1);
   LAUNCHCHK();
   return EHDLB_OK;
 }
@@ -896,8 +922,7 @@ static ehdlb_status step_record(ehdlb_ctx* c, T* rec) {
   T* rho = c->ptr<T>(c->off_rho[pi]);
   const T* pin = c->ptr<T>(c->off_pop[c->cur]);
   T* pout = c->ptr<T>(c->off_pop[1 - c->cur]);
-  hipLaunchKernelGGL((k_moments<LT, T>), dim3(nblocks(N), EHD ? 4 : 3), dim3(kBlock), 0, s, dm, flags, pin, phi, rho,
-                     (T*)nullptr, 1);
+  launch_moments<LT, T>(c, EHD ? 4 : 3, dm, flags, pin, phi, rho, (T*)nullptr, 1);
   if (G > 0)
     hipLaunchKernelGGL(k_ghosts<T>, dim3(nblocks(G)), dim3(kBlock), 0, s, N, G, c->ptr<int32_t>(c->off_gnode),
                        c->ptr<int32_t>(c->off_gsrc), c->ptr<T>(c->off_glen), phi, ph);
@@ -934,7 +959,7 @@ static ehdlb_status step_record(ehdlb_ctx* c, T* rec) {
   a.volts = v;
   a.dt_on = t == 0 ? T(0) : T(1);
   a.rec = rec + (size_t)RL::MOM * N;
-  hipLaunchKernelGGL((k_step<LT, T, EHD, true>), dim3(nblocks(N)), dim3(kBlock), 0, s, a);
+  launch_step<LT, T, EHD, true>(c, a);
   LAUNCHCHK();
   c->cur = 1 - c->cur;
   c->t = t + 1;

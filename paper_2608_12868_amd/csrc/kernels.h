@@ -135,11 +135,21 @@ struct MomLayout {
   static constexpr int COUNT = 1 + 5 * D + P;
 };
 
+// Population load, with the non-temporal hint if NT.  Each population is read once per step;
+// where the two population arrays exceed the 256 MB Infinity Cache, hinted loads keep them from
+// evicting the phase, potential and flag values that neighbouring blocks re-read through L2.
+template <bool NT, class T>
+__device__ __forceinline__ T ld_pop(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 // ----------------------------------------------------------------------------- moments (Eq. 19)
 // Zeroth moment of one population family per thread: blockIdx.y selects the family
 // fam0 + blockIdx.y (0: flow deviation -> drho, 1..3: phase fields -> phi, 4: charge -> rho).
 // Zero at solid nodes (the wetting kernel then overwrites the solid nodes next to fluid).
-template <class L, class T>
+// NT: population loads with the non-temporal hint (ld_pop).
+template <class L, class T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_moments(Dims d, const uint8_t* __restrict__ flags,
                                                      const T* __restrict__ pop, T* __restrict__ phi,
                                                      T* __restrict__ rho, T* __restrict__ drho, int fam0) {
@@ -151,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(Dims d, const uint8_t* __res
   if (flags[node] == 0) {
     const T* p = pop + (int64_t)fam * L::Q * N + node;
 #pragma unroll
-    for (int q = 0; q < L::Q; ++q) s += p[(int64_t)q * N];
+    for (int q = 0; q < L::Q; ++q) s += ld_pop<NT>(&p[(int64_t)q * N]);
   }
   if (fam == 0)
     drho[node] = s;

@@ -9,7 +9,8 @@
 namespace ehd {
 
 // ----------------------------------------------------------------------------- fused collide-stream
-template <class L, class T, bool EHD, bool STORE = false>
+// NT: population loads with the non-temporal hint (as in k_moments)
+template <class L, class T, bool EHD, bool STORE, bool NT>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
   using ML = MomLayout<L>;
   constexpr int Q = L::Q;
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
     T drho = 0, j[3] = {0, 0, 0};
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      gq[q] = a.pop_in[(int64_t)q * N + node];
+      gq[q] = ld_pop<NT>(&a.pop_in[(int64_t)q * N + node]);
       drho += gq[q];
       j[0] += T(L::ex[q]) * gq[q];
       j[1] += T(L::ey[q]) * gq[q];
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
       T fq[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        fq[q] = a.pop_in[((int64_t)(1 + i) * Q + q) * N + node];
+        fq[q] = ld_pop<NT>(&a.pop_in[((int64_t)(1 + i) * Q + q) * N + node]);
         jf[0] += T(L::ex[q]) * fq[q];
         jf[1] += T(L::ey[q]) * fq[q];
         jf[2] += T(L::ez[q]) * fq[q];
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
     T hq[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      hq[q] = a.pop_in[((int64_t)4 * Q + q) * N + node];
+      hq[q] = ld_pop<NT>(&a.pop_in[((int64_t)4 * Q + q) * N + node]);
       jh[0] += T(L::ex[q]) * hq[q];
       jh[1] += T(L::ey[q]) * hq[q];
       jh[2] += T(L::ez[q]) * hq[q];
