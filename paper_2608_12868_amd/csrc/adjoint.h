@@ -68,7 +68,7 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
   constexpr int P = ML::P;
-  const int64_t node = gidx();
+  const int64_t node = D == 3 ? band_idx(a.d) : gidx();
   double vloc[kMaxE] = {0.0, 0.0, 0.0, 0.0};
   const int64_t N = a.d.N;
   const bool active = node < N && a.flags[node] == 0;
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(Dims d, const uint8_t* __restr
                                                    T* __restrict__ lphi_out, T* __restrict__ lpot_out) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
-  const int64_t y = sidx();  // XCD-aware order: the gathered neighbours share an L2
+  const int64_t y = D == 3 ? band_idx(d) : sidx();  // XCD-aware orders: gathered neighbours share an L2
   if (y >= d.N) return;
   const int64_t N = d.N;
   const bool fluid = flags[y] == 0;
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_cd(Dims d, const uint8_t* __rest
   using RL = RecLayout<L>;
   constexpr int Q = L::Q;
   constexpr int D = L::D;
-  const int64_t x = gidx();
+  const int64_t x = D == 3 ? band_idx(d) : gidx();
   double vloc[kMaxE] = {0.0, 0.0, 0.0, 0.0};
   const int64_t N = d.N;
   if (x < N) {

@@ -41,8 +41,8 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   if (b >= per * kXcd) return b;
   return (b % kXcd) * per + b / kXcd;
 }
-// global thread index over nodes (plain block order: the XCD-aware order did not help the
-// one-thread-per-node kernels on MI355X and slowed the fused step by a few percent)
+// global thread index over nodes, plain block order (kernels without stencils, and the 2D
+// lattices, whose fields stay in the Infinity Cache)
 __device__ __forceinline__ int64_t gidx() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 // global thread index of the one-thread-per-cell stencil kernels of the potential solver:
 // XCD-aware block order, so that the rows above and below a block's cells are read through
@@ -50,6 +50,21 @@ __device__ __forceinline__ int64_t gidx() { return (int64_t)blockIdx.x * blockDi
 __device__ __forceinline__ int64_t sidx() {
   return (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
 }
+// global thread index of the fused step and the adjoint passes on 3D lattices (plane = nx ny
+// nodes, grid of whole blocks over the lattice): the blocks of each z plane form 8
+// contiguous bands of rows, one per XCD, each walked in order, so the rows above and below a
+// block are read through the same XCD's L2, and the same rows of the next plane follow an
+// eighth of a plane later (plain order when a plane is not a multiple of 8 blocks)
+__device__ __forceinline__ int64_t band_idx(int64_t plane) {
+  const int bpp = (int)(plane / blockDim.x);
+  int b = blockIdx.x;
+  if (plane % blockDim.x == 0 && bpp % kXcd == 0) {
+    const int pz = b / bpp, r = b - pz * bpp;
+    b = pz * bpp + (r % kXcd) * (bpp / kXcd) + r / kXcd;
+  }
+  return (int64_t)b * blockDim.x + threadIdx.x;
+}
+__device__ __forceinline__ int64_t band_idx(const Dims& d) { return band_idx((int64_t)d.nx * d.ny); }
 // contiguous chunk [lo, hi) of a grid-stride kernel's index space for this block (fixed, so
 // reductions keep a fixed order); chunks are multiples of the block size
 __device__ __forceinline__ void chunk_range(int64_t n, int64_t& lo, int64_t& hi) {
