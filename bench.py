@@ -98,7 +98,8 @@ ADJOINT = {
 
 def adjoint_leg(key, fd_h=1e-4, seed=1):
     """Cost of dL/dV for L = (x_c(T) - x*)^2 (x* = initial centroid + 5 lu), FP32 path, with
-    each forward warm start (previous potential; extrapolated from the last two): plain forward,
+    each forward warm start (projected onto the last three potentials, the default; previous
+    potential; extrapolated from the last two): plain forward,
     checkpointed forward and reverse sweep (recompute included), timed with device syncs; each
     gradient's error against the FP64 adjoint (where it fits in memory) and the directional
     derivatives against central differences of the FP64 forward."""
@@ -111,7 +112,7 @@ def adjoint_leg(key, fd_h=1e-4, seed=1):
     case = make_case(name)
     runs = {}
     target = None
-    for mode, label in ((0, "warm_previous"), (1, "warm_extrapolated")):
+    for mode, label in ((2, "warm_projected"), (0, "warm_previous"), (1, "warm_extrapolated")):
         sim = Simulation.from_case(case, precision="fp32", poisson_tol=1e-5)
         sim.set_solver_options(warm_start=mode)
         sim.set_schedule(0, case.schedule, case.t_total)

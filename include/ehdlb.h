@@ -218,14 +218,18 @@ ehdlb_status ehdlb_adjoint(ehdlb_ctx* ctx, const double dL_dcentroid[3], const d
  * Chebyshev polynomial of the Jacobi-preconditioned operator D^-1 A on
  * [lo, hi] (0 < lo < hi <= 2; D^-1 A has its spectrum in (0, 2]), applied once
  * before and once after the coarse correction; overcorrect in (0, 4]: scale of
- * the coarse-grid correction.  warm_start: 0 = each step's solve starts from the
- * previous step's potential (fewest iterations); 1 = from the linear
- * extrapolation 2 phi(t-1) - phi(t-2) (more iterations, but the potential then
- * does not lag the exactly solved Gauss law, which the adjoint differentiates:
- * use it for accurate FP32 gradients).  Both potentials are part of the saved
- * state; switching to 1 in mid-run extrapolates once from a stale phi(t-2).
- * Defaults lo = 0.5, hi = 2, overcorrect = 2, warm_start = 0.  EINVAL outside
- * the ranges. */
+ * the coarse-grid correction.  warm_start (forward solves): 0 = each step's
+ * solve starts from the previous step's potential; 1 = from the linear
+ * extrapolation 2 phi(t-1) - phi(t-2); 2 = from the Galerkin projection of the
+ * step's system onto the potentials of the last three steps (formed in the
+ * basis phi(t-1) and its first and second differences): the A-norm-optimal
+ * start in their span, so at least as good in that norm as 0 and 1 (fewest
+ * iterations).  The adjoint's solves always start from the projection onto
+ * the adjoint potentials of steps t+1..t+4.  The earlier potentials are part
+ * of the saved state, so replays from a checkpoint take the same iterates;
+ * switching modes in mid-run projects once onto stale potentials (still a
+ * valid start).  Defaults lo = 0.5, hi = 2, overcorrect = 2, warm_start = 2.
+ * EINVAL outside the ranges. */
 ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* ctx, double lo, double hi, double overcorrect,
                                       int32_t warm_start);
 

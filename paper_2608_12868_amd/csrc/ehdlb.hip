@@ -31,6 +31,11 @@ constexpr int kRedBlocks = 1024;
 // level, fit the tail's LDS run inside the single-workgroup V-cycle tail
 constexpr int64_t kTailMaxCells = 2048;
 constexpr int kSolverParts = 7;
+// earlier solutions spanning the projected warm starts: forward (potentials of steps t-1..t-3)
+// and adjoint (adjoint potentials of steps t+1..t+4, which alternate in sign)
+constexpr int kProjFwd = 3, kProjAdj = 4;
+// grid of the projection's Gram pass (more blocks than the solver's reductions: it is latency bound)
+constexpr int kProjBlocks = 4096;
 // MI355X's Infinity Cache (memory-side last-level cache)
 constexpr size_t kInfinityCacheBytes = (size_t)256 << 20;
 int rblocks(int64_t n) { return std::min(nblocks(n), kRedBlocks); }
@@ -81,11 +86,12 @@ struct ehdlb_ctx {
   ehd::CgCtl hctl{};  // host copy of the solve's control block
   // layout (byte offsets into ws)
   size_t off_pop[2]{}, off_phi[2]{}, off_rho[2]{}, off_u[2]{}, off_q[2]{}, off_pot = 0, off_pot_old = 0;
+  size_t off_pot_hist[kProjFwd]{};  // potentials of earlier steps for the projected warm start (ring by t)
   // end of the state region that save_state copies after the populations
-  size_t state_end() const { return off_pot_old + (size_t)N * tsize; }
+  size_t state_end() const { return off_pot_hist[kProjFwd - 1] + (size_t)N * tsize; }
   size_t off_flags = 0, off_gnode = 0, off_gsrc = 0, off_glen = 0, off_scratch = 0;
   size_t off_b = 0, off_r = 0, off_z = 0, off_p = 0, off_qv = 0, off_spart = 0;
-  size_t off_part = 0, off_red = 0, off_cg = 0, off_inv = 0, off_dbl = 0;
+  size_t off_part = 0, off_red = 0, off_cg = 0, off_inv = 0, off_dbl = 0, off_ppart = 0, off_pcoef = 0;
   size_t state_bytes = 0, total = 0;
   std::vector<MGLevel> mg;
   size_t tail_first = 0;  // first level handled by the single-workgroup tail kernel
@@ -105,7 +111,7 @@ struct ehdlb_ctx {
     bool ready = false;
     size_t ckpt = 0, fin = 0, rec = 0, lP[2]{}, lphip[2]{}, lup[2]{}, lrhop[2]{}, lqp[2]{};
     size_t lgr = 0, llap = 0, lsig = 0, lpnb = 0, lphi_loc = 0, lpot_loc = 0, lrho_loc = 0, lmom = 0;
-    size_t lphi = 0, lpot = 0, lb = 0, lb2 = 0, lbo = 0, lbo2 = 0, vpart = 0, vred = 0, vacc = 0, obs = 0, total = 0, rec_stride = 0;
+    size_t lphi = 0, lpot = 0, lb = 0, lbr[kProjAdj]{}, vpart = 0, vred = 0, vacc = 0, obs = 0, total = 0, rec_stride = 0;
     int nvseg = 0;
   } adj;
   // potential-solver options (ehdlb_set_solver_options): degree-2 Chebyshev smoothing of the
@@ -113,7 +119,7 @@ struct ehdlb_ctx {
   double mg_lo = 0.5, mg_hi = 2.0;
   double mg_overcorrect = 2.0;
   bool stream_pops = false;       // population loads with the non-temporal hint
-  bool warm_extrapolate = false;  // forward warm start: previous potential, or extrapolated
+  int warm_mode = 2;  // forward warm start: 0 previous potential, 1 extrapolated, 2 projected
   // smoothing polynomial z += c1 y - c2 D^-1 A y: p(mu) = 1 - c1 mu + c2 mu^2 = T2(s(mu))/T2(s(0)),
   // s(mu) = (hi + lo - 2 mu)/(hi - lo)
   void poly(double& c1, double& c2) const {
@@ -228,6 +234,7 @@ static void plan_layout(ehdlb_ctx* c) {
   for (int k = 0; k < 2; ++k) c->off_q[k] = take(N * ts);
   c->off_pot = take(N * ts);
   c->off_pot_old = take(N * ts);  // potential of the previous step (warm-start extrapolation)
+  for (int k = 0; k < kProjFwd; ++k) c->off_pot_hist[k] = take(N * ts);
   // --- geometry
   c->off_flags = take(N);
   c->max_ghost = N;  // upper bound; actual count known at set_geometry
@@ -291,6 +298,8 @@ static void plan_layout(ehdlb_ctx* c) {
   c->off_cg = take(sizeof(CgCtl));
   // solver partials: true residual (3 per block), max|r|, p.q, two r.z
   c->off_spart = take((size_t)kSolverParts * kRedBlocks * 8);
+  c->off_ppart = take((size_t)proj_sums<kProjAdj>() * kProjBlocks * 8);
+  c->off_pcoef = take(kProjAdj * 8);
   c->state_bytes = 256 + align_up((size_t)c->F * c->Q * N * ts) + (c->state_end() - c->off_phi[0]);
   c->total = o;
 }
@@ -577,15 +586,50 @@ static ehdlb_status pois_setup(ehdlb_ctx* c, const T* phi, const T* rho, const V
   return EHDLB_OK;
 }
 
+// Warm start of A x = b (the fine operator of the current pois_setup) by Galerkin projection onto
+// x's current content h_1 and up to M - 1 earlier solutions (m vectors in all); h_1 is kept in
+// `keep` for later solves.
+template <int D, class T, int M>
+static void project_warm_start(ehdlb_ctx* c, T* x, const T* b, const T* const* older, int m, T* keep,
+                               const double (&basis)[M][M]) {
+  hipStream_t s = c->stream;
+  const MGLevel& m0 = c->mg[0];
+  const int64_t N = m0.L.N;
+  ProjVecs<T, M> h{};
+  h.v[0] = x;
+  for (int j = 1; j < M; ++j) h.v[j] = j < m ? older[j - 1] : x;
+  for (int r = 0; r < M; ++r)
+    for (int k = 0; k < M; ++k) h.B[r][k] = m == M ? basis[r][k] : (r == k && r < m ? 1.0 : 0.0);
+  const int rb = std::min(nblocks(N), kProjBlocks);
+  double* part = c->ptr<double>(c->off_ppart);
+  double* coef = c->ptr<double>(c->off_pcoef);
+  hipLaunchKernelGGL((k_proj_gram<D, T, M>), dim3(rb), dim3(kBlock), 0, s, m0.L, (const T*)c->ptr<T>(m0.cp),
+                     (const T*)c->ptr<T>(m0.diag), b, h, m, keep, part);
+  hipLaunchKernelGGL((k_proj_solve<T, M>), dim3(1), dim3(kBlock), 0, s, (const double*)part, rb, m, h, coef);
+  hipLaunchKernelGGL((k_proj_combine<T, M>), dim3(nblocks(N)), dim3(kBlock), 0, s, N, (const double*)coef, h, m, x);
+}
+
 template <class LT, class T>
 static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, const Volts<T>& volts) {
   ehdlb_status st = pois_setup<LT, T>(c, phi, rho, volts);
   if (st) return st;
-  // optional warm start extrapolated linearly from the potentials of the two previous steps
-  // (both kept in the saved state, so a replay from a checkpoint takes the same iterates)
-  if (c->warm_extrapolate)
-    hipLaunchKernelGGL(k_extrapolate<T>, dim3(nblocks(c->N)), dim3(kBlock), 0, c->stream, c->N,
-                       c->ptr<T>(c->off_pot), c->ptr<T>(c->off_pot_old));
+  // optional warm starts: extrapolated linearly from the potentials of the two previous steps,
+  // or projected onto the potentials of the last three steps (kept in the saved state, so a
+  // replay from a checkpoint takes the same iterates)
+  T* pot = c->ptr<T>(c->off_pot);
+  if (c->warm_mode == 1) {
+    hipLaunchKernelGGL(k_extrapolate<T>, dim3(nblocks(c->N)), dim3(kBlock), 0, c->stream, c->N, pot,
+                       c->ptr<T>(c->off_pot_old));
+  } else if (c->warm_mode == 2 && c->t >= 1) {
+    const int64_t t = c->t;
+    const int m = (int)std::min<int64_t>(t, kProjFwd);
+    const T* older[kProjFwd - 1];
+    for (int j = 1; j < kProjFwd; ++j) older[j - 1] = j < m ? c->ptr<T>(c->off_pot_hist[(t - 1 - j) % kProjFwd]) : pot;
+    // basis: phi(t-1) and its first and second differences
+    static constexpr double kBasis[kProjFwd][kProjFwd] = {{1, 0, 0}, {1, -1, 0}, {1, -2, 1}};
+    project_warm_start<LT::D, T, kProjFwd>(c, pot, c->ptr<T>(c->off_b), older, m,
+                                          c->ptr<T>(c->off_pot_hist[(t - 1) % kProjFwd]), kBasis);
+  }
   return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b), c->cg_hist[0]);
 }
 
@@ -887,9 +931,7 @@ static void plan_adjoint(const ehdlb_ctx* c, int64_t T, int K, ehdlb_ctx::Adj& a
   a.lphi = take(3 * N * ts);
   a.lpot = take(N * ts);
   a.lb = take(N * ts);
-  a.lb2 = take(N * ts);
-  a.lbo = take(N * ts);
-  a.lbo2 = take(N * ts);
+  for (int k = 0; k < kProjAdj; ++k) a.lbr[k] = take(N * ts);
   a.vpart = take((size_t)nblocks(N) * kMaxE * 8);
   a.vred = take(kMaxE * 8);
   a.nvseg = 1 << 16;
@@ -980,7 +1022,7 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
   Volts<T> v{};
   for (int e = 0; e < kMaxE; ++e) v.v[e] = (T)volts_at(c, e, t);
   const int nb = nblocks(N);
-  const size_t lbx = (t & 1) ? J.lb2 : J.lb;
+  const size_t lbx = J.lb;
   AdjArgs<T> a{};
   a.d = dm;
   a.flags = flags;
@@ -1031,12 +1073,21 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
     // potential adjoint: A lb = lambda_phi with the operator of step t
     ehdlb_status st = pois_setup<LT, T>(c, rec + (size_t)RL::PHI * N, (const T*)nullptr, v);
     if (st) return st;
-    // right-hand side lambda_phi read in place; warm start extrapolated linearly from the
-    // adjoint potentials of steps t+2 and t+4 (same parity: the adjoint of the over-relaxed first
-    // moments alternates in sign from step to step); zero at the start
+    // right-hand side lambda_phi read in place; warm start projected onto the adjoint potentials
+    // of steps t+1..t+4 (they alternate in sign from step to step, following the adjoint of the
+    // over-relaxed first moments); zero at the start of the sweep
     {
-      const size_t lbo = (t & 1) ? J.lbo2 : J.lbo;
-      hipLaunchKernelGGL(k_extrapolate<T>, dim3(nb), dim3(kBlock), 0, s, N, A(lbx), A(lbo));
+      const int m = (int)std::min<int64_t>(J.t0 + J.T - 1 - t, kProjAdj);
+      if (m > 0) {
+        const T* older[kProjAdj - 1];
+        for (int j = 1; j < kProjAdj; ++j) older[j - 1] = j < m ? A(J.lbr[(t + 1 + j) % kProjAdj]) : A(lbx);
+        // basis (h_k = lambda(t+k)): h_2, h_2 - h_4 (same parity), h_1 + h_2 and
+        // h_1 + h_2 - h_3 - h_4 (the alternating part cancels)
+        static constexpr double kBasis[kProjAdj][kProjAdj] = {
+            {0, 1, 0, 0}, {0, 1, 0, -1}, {1, 1, 0, 0}, {1, 1, -1, -1}};
+        project_warm_start<LT::D, T, kProjAdj>(c, A(lbx), (const T*)A(J.lpot), older, m,
+                                              A(J.lbr[(t + 1) % kProjAdj]), kBasis);
+      }
     }
     if ((st = pcg<LT, T>(c, A(lbx), (const T*)A(J.lpot), c->cg_hist[1]))) return st;
   }
@@ -1092,9 +1143,6 @@ struct AdjFn {
                        A(J.lrhop[cu]), A(J.lqp[cu]));
     HIPCHK(hipMemsetAsync(J.ws + J.vacc, 0, (size_t)kMaxE * J.nvseg * 8, s));
     hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, N, A(J.lb));
-    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, N, A(J.lb2));
-    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, N, A(J.lbo));
-    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, N, A(J.lbo2));
     LAUNCHCHK();
     const auto& sch = c->sched[electrode];
     const int nseg = sch.v.empty() ? 1 : (int)sch.v.size();
@@ -1527,11 +1575,11 @@ ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* c, double lo, double hi, double
   if (!c) return EHDLB_EINVAL;
   if (!(lo > 0.0 && hi > lo && hi <= 2.0)) return fail(c, EHDLB_EINVAL, "need 0 < lo < hi <= 2");
   if (!(overcorrect > 0.0 && overcorrect <= 4.0)) return fail(c, EHDLB_EINVAL, "over-correction must lie in (0, 4]");
-  if (warm_start != 0 && warm_start != 1) return fail(c, EHDLB_EINVAL, "warm_start must be 0 or 1");
+  if (warm_start < 0 || warm_start > 2) return fail(c, EHDLB_EINVAL, "warm_start must be 0, 1 or 2");
   c->mg_lo = lo;
   c->mg_hi = hi;
   c->mg_overcorrect = overcorrect;
-  c->warm_extrapolate = warm_start != 0;
+  c->warm_mode = warm_start;
   return EHDLB_OK;
 }
 

@@ -1262,6 +1262,170 @@ __global__ __launch_bounds__(kBlock) void k_cg_zero(const CgCtl* __restrict__ ct
   if (i < N) x[i] = T(0);
 }
 
+// ---- warm start by Galerkin projection onto earlier solutions ------------------------------
+// For A x = b and up to M earlier solutions h_1..h_m (h_1 = the current content of x), the
+// warm start x0 = sum_j a_j h_j minimising the A-norm of the error over their span (so it is at
+// least as good, in that norm, as the previous solution or any extrapolation of the earlier
+// ones).  The Galerkin system is formed in the basis u_j = sum_k B_jk h_k (FP64, from the stored
+// values): successive solutions are nearly equal (or, for the adjoint, nearly opposite), and
+// differences such as h_1 - h_2 resolve what G_ij = h_i . A h_j in FP64 cannot.  With fewer than
+// M vectors B is the identity.  Three kernels: partial sums of G_ij = u_i . A u_j and
+// g_i = u_i . b (one pass that applies A to every u_j in FP64), a one-block Cholesky solve that
+// maps the coefficients back (a = B^T c), the combination.
+template <class T, int M>
+struct ProjVecs {
+  const T* v[M];
+  double B[M][M];
+};
+template <int M>
+constexpr int proj_sums() { return M * (M + 1) / 2 + M; }
+
+// per-block FP64 partials of G (upper triangle, row-major) and g; also keep <- h_1
+template <int D, class T, int M>
+__global__ __launch_bounds__(kBlock) void k_proj_gram(Level L, const T* __restrict__ cp, const T* __restrict__ diag,
+                                                      const T* __restrict__ b, ProjVecs<T, M> h, int m,
+                                                      T* __restrict__ keep, double* __restrict__ part) {
+  constexpr int P = proj_sums<M>();
+  double acc[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) acc[k] = 0.0;
+  // u_j at cell j from the stored h_k (unused slots point at valid vectors and have zero
+  // columns in B: loads without branches)
+  auto basis = [&](int64_t j, double (&u)[M]) {
+    double hv[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) hv[k] = (double)h.v[k][j];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) s += h.B[r][k] * hv[k];
+      u[r] = s;
+    }
+  };
+  int64_t lo, hi;
+  chunk_range(L.N, lo, hi);
+  const int N = (int)L.N;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+    // every load of the cell is independent of the others (inactive cells are masked, their
+    // neighbour indices are valid), so one iteration is one memory round trip
+    const T dg = diag[i];
+    const double bi = (double)b[i];
+    const T h0 = h.v[0][i];
+    int cx, cy, cz;
+    cell_xyz<D>(L, i, cx, cy, cz);
+    double u[M], au[M], un[M];
+    basis(i, u);
+#pragma unroll
+    for (int r = 0; r < M; ++r) au[r] = (double)dg * u[r];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      int jp, jm;
+      axis_pm<D>(L, (int)i, cx, cy, cz, ax, jp, jm);
+      const double cpp = (double)cp[(int64_t)ax * N + i], cpm = (double)cp[(int64_t)ax * N + jm];
+      basis(jp, un);
+#pragma unroll
+      for (int r = 0; r < M; ++r) au[r] -= cpp * un[r];
+      basis(jm, un);
+#pragma unroll
+      for (int r = 0; r < M; ++r) au[r] -= cpm * un[r];
+    }
+    if (keep) keep[i] = h0;
+    const bool on = dg != T(0);  // selected, not multiplied: inactive cells contribute nothing
+#pragma unroll
+    for (int r = 0; r < M; ++r) u[r] = on ? u[r] : 0.0;
+    int k = 0;
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+#pragma unroll
+      for (int c = r; c < M; ++c) acc[k++] += u[r] * au[c];
+#pragma unroll
+    for (int r = 0; r < M; ++r) acc[k++] += u[r] * bi;
+  }
+  block_reduce<P, false>(acc, part + (int64_t)blockIdx.x * P);
+}
+
+// G c = g from the sums s (upper triangle of G row-major, then g) for the first m vectors
+template <int M>
+__host__ __device__ inline void proj_coefficients(const double* s, int m, double* coef) {
+  double G[M][M], g[M], Lc[M][M], y[M], c[M];
+  bool keepj[M];
+  int k = 0;
+  for (int r = 0; r < M; ++r)
+    for (int cc = r; cc < M; ++cc) G[r][cc] = G[cc][r] = s[k++];
+  for (int r = 0; r < M; ++r) g[r] = s[k++];
+  for (int r = 0; r < M; ++r)
+    for (int i = 0; i < M; ++i) Lc[r][i] = 0.0;
+  for (int j = 0; j < M; ++j) {
+    keepj[j] = false;
+    if (j >= m || !(G[j][j] > 0.0)) continue;
+    double d = G[j][j];
+    for (int i = 0; i < j; ++i) d -= Lc[j][i] * Lc[j][i];
+    if (!(d > 1e-12 * G[j][j])) continue;
+    keepj[j] = true;
+    Lc[j][j] = sqrt(d);
+    for (int r = j + 1; r < m; ++r) {
+      double e = G[r][j];
+      for (int i = 0; i < j; ++i) e -= Lc[r][i] * Lc[j][i];
+      Lc[r][j] = e / Lc[j][j];
+    }
+  }
+  for (int j = 0; j < M; ++j) {
+    y[j] = 0.0;
+    if (!keepj[j]) continue;
+    double e = g[j];
+    for (int i = 0; i < j; ++i) e -= Lc[j][i] * y[i];
+    y[j] = e / Lc[j][j];
+  }
+  for (int j = M - 1; j >= 0; --j) {
+    c[j] = 0.0;
+    if (!keepj[j]) continue;
+    double e = y[j];
+    for (int i = j + 1; i < M; ++i) e -= Lc[i][j] * c[i];
+    c[j] = e / Lc[j][j];
+  }
+  for (int j = 0; j < M; ++j) coef[j] = c[j] - c[j] == 0.0 ? c[j] : 0.0;  // 0 for inf and NaN
+}
+
+// sums the partials in a fixed order and solves G c = g by Cholesky in FP64; a vector whose
+// pivot falls below 1e-12 of its own G_jj (linearly dependent on the earlier ones) gets c_j = 0
+template <class T, int M>
+__global__ __launch_bounds__(kBlock) void k_proj_solve(const double* __restrict__ part, int nblk, int m,
+                                                       ProjVecs<T, M> h, double* __restrict__ coef) {
+  constexpr int P = proj_sums<M>();
+  double v[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) v[k] = 0.0;
+  for (int bb = threadIdx.x; bb < nblk; bb += kBlock)
+#pragma unroll
+    for (int k = 0; k < P; ++k) v[k] += part[(int64_t)bb * P + k];
+  __shared__ double s[P];
+  block_reduce<P, false>(v, s);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double c[M];
+  proj_coefficients<M>(s, m, c);
+  for (int k = 0; k < M; ++k) {
+    double e = 0.0;
+    for (int j = 0; j < M; ++j) e += c[j] * h.B[j][k];
+    coef[k] = k < m ? e : 0.0;
+  }
+}
+
+// x <- sum_j c_j h_j in FP64, rounded once (nearly dependent h_j, such as successive potentials or
+// the sign-alternating adjoint potentials, give large coefficients of opposite sign; h_1 may be x
+// itself: each element is read before it is written)
+template <class T, int M>
+__global__ __launch_bounds__(kBlock) void k_proj_combine(int64_t N, const double* __restrict__ coef,
+                                                         ProjVecs<T, M> h, int m, T* x) {
+  const int64_t i = gidx();
+  if (i >= N) return;
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) s += coef[j] * (double)h.v[j][i];  // coef[j] = 0 for j >= m
+  x[i] = (T)s;
+}
+
 // Linear extrapolation of a warm start from two earlier solutions: x <- 2 x - older, older <- x
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t N, T* __restrict__ x, T* __restrict__ older) {

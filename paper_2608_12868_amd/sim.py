@@ -166,10 +166,10 @@ class Simulation(Context):
         return {k: dict(solves=int(counts[2 * j]), iters=int(counts[2 * j + 1]), max_rel0=float(rel0[j]))
                 for j, k in enumerate(("forward", "adjoint"))}
 
-    def set_solver_options(self, lo=0.5, hi=2.0, overcorrect=2.0, warm_start=0):
+    def set_solver_options(self, lo=0.5, hi=2.0, overcorrect=2.0, warm_start=2):
         """Chebyshev smoothing interval [lo, hi] of D^-1 A, coarse-correction scale, and the
-        forward warm start (0: previous step's potential; 1: extrapolated from the last two,
-        for accurate FP32 gradients)."""
+        forward warm start (0: previous step's potential; 1: extrapolated from the last two;
+        2: Galerkin projection onto the last three, the default)."""
         self._chk(L.lib().ehdlb_set_solver_options(self.h, float(lo), float(hi), float(overcorrect),
                                                    int(warm_start)))
 
