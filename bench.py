@@ -98,7 +98,7 @@ ADJOINT = {
 
 def adjoint_leg(key, fd_h=1e-4, seed=1):
     """Cost of dL/dV for L = (x_c(T) - x*)^2 (x* = initial centroid + 5 lu), FP32 path, with
-    each forward warm start (projected onto the last three potentials, the default; previous
+    each forward warm start (projected onto the last four potentials, the default; previous
     potential; extrapolated from the last two): plain forward,
     checkpointed forward and reverse sweep (recompute included), timed with device syncs; each
     gradient's error against the FP64 adjoint (where it fits in memory) and the directional

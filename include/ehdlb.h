@@ -221,11 +221,11 @@ ehdlb_status ehdlb_adjoint(ehdlb_ctx* ctx, const double dL_dcentroid[3], const d
  * the coarse-grid correction.  warm_start (forward solves): 0 = each step's
  * solve starts from the previous step's potential; 1 = from the linear
  * extrapolation 2 phi(t-1) - phi(t-2); 2 = from the Galerkin projection of the
- * step's system onto the potentials of the last three steps (formed in the
- * basis phi(t-1) and its first and second differences): the A-norm-optimal
+ * step's system onto the potentials of the last four steps (formed in the
+ * basis phi(t-1) and its backward differences): the A-norm-optimal
  * start in their span, so at least as good in that norm as 0 and 1 (fewest
  * iterations).  The adjoint's solves always start from the projection onto
- * the adjoint potentials of steps t+1..t+4.  The earlier potentials are part
+ * the adjoint potentials of steps t+1..t+6.  The earlier potentials are part
  * of the saved state, so replays from a checkpoint take the same iterates;
  * switching modes in mid-run projects once onto stale potentials (still a
  * valid start).  Defaults lo = 0.5, hi = 2, overcorrect = 2, warm_start = 2.

@@ -31,9 +31,9 @@ constexpr int kRedBlocks = 1024;
 // level, fit the tail's LDS run inside the single-workgroup V-cycle tail
 constexpr int64_t kTailMaxCells = 2048;
 constexpr int kSolverParts = 7;
-// earlier solutions spanning the projected warm starts: forward (potentials of steps t-1..t-3)
-// and adjoint (adjoint potentials of steps t+1..t+4, which alternate in sign)
-constexpr int kProjFwd = 3, kProjAdj = 4;
+// earlier solutions spanning the projected warm starts: forward (potentials of steps t-1..t-4)
+// and adjoint (adjoint potentials of steps t+1..t+6, which alternate in sign)
+constexpr int kProjFwd = 4, kProjAdj = 6;
 // grid of the projection's Gram pass (more blocks than the solver's reductions: it is latency bound)
 constexpr int kProjBlocks = 4096;
 // MI355X's Infinity Cache (memory-side last-level cache)
@@ -298,8 +298,8 @@ static void plan_layout(ehdlb_ctx* c) {
   c->off_cg = take(sizeof(CgCtl));
   // solver partials: true residual (3 per block), max|r|, p.q, two r.z
   c->off_spart = take((size_t)kSolverParts * kRedBlocks * 8);
-  c->off_ppart = take((size_t)proj_sums<kProjAdj>() * kProjBlocks * 8);
-  c->off_pcoef = take(kProjAdj * 8);
+  c->off_ppart = take((size_t)std::max(proj_sums<kProjFwd>(), proj_sums<kProjAdj>()) * kProjBlocks * 8);
+  c->off_pcoef = take(std::max(kProjFwd, kProjAdj) * 8);
   c->state_bytes = 256 + align_up((size_t)c->F * c->Q * N * ts) + (c->state_end() - c->off_phi[0]);
   c->total = o;
 }
@@ -614,7 +614,7 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
   ehdlb_status st = pois_setup<LT, T>(c, phi, rho, volts);
   if (st) return st;
   // optional warm starts: extrapolated linearly from the potentials of the two previous steps,
-  // or projected onto the potentials of the last three steps (kept in the saved state, so a
+  // or projected onto the potentials of the last four steps (kept in the saved state, so a
   // replay from a checkpoint takes the same iterates)
   T* pot = c->ptr<T>(c->off_pot);
   if (c->warm_mode == 1) {
@@ -625,8 +625,14 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
     const int m = (int)std::min<int64_t>(t, kProjFwd);
     const T* older[kProjFwd - 1];
     for (int j = 1; j < kProjFwd; ++j) older[j - 1] = j < m ? c->ptr<T>(c->off_pot_hist[(t - 1 - j) % kProjFwd]) : pot;
-    // basis: phi(t-1) and its first and second differences
-    static constexpr double kBasis[kProjFwd][kProjFwd] = {{1, 0, 0}, {1, -1, 0}, {1, -2, 1}};
+    // basis: phi(t-1) and its backward differences up to the third, u_r = sum_k (-1)^k C(r, k) h_k
+    double kBasis[kProjFwd][kProjFwd];
+    for (int r = 0; r < kProjFwd; ++r)
+      for (int k = 0; k < kProjFwd; ++k) {
+        double binom = 1.0;
+        for (int i = 0; i < k; ++i) binom = binom * (r - i) / (i + 1);
+        kBasis[r][k] = k <= r ? ((k & 1) ? -binom : binom) : 0.0;
+      }
     project_warm_start<LT::D, T, kProjFwd>(c, pot, c->ptr<T>(c->off_b), older, m,
                                           c->ptr<T>(c->off_pot_hist[(t - 1) % kProjFwd]), kBasis);
   }
@@ -1074,17 +1080,19 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
     ehdlb_status st = pois_setup<LT, T>(c, rec + (size_t)RL::PHI * N, (const T*)nullptr, v);
     if (st) return st;
     // right-hand side lambda_phi read in place; warm start projected onto the adjoint potentials
-    // of steps t+1..t+4 (they alternate in sign from step to step, following the adjoint of the
+    // of steps t+1..t+6 (they alternate in sign from step to step, following the adjoint of the
     // over-relaxed first moments); zero at the start of the sweep
     {
       const int m = (int)std::min<int64_t>(J.t0 + J.T - 1 - t, kProjAdj);
       if (m > 0) {
         const T* older[kProjAdj - 1];
         for (int j = 1; j < kProjAdj; ++j) older[j - 1] = j < m ? A(J.lbr[(t + 1 + j) % kProjAdj]) : A(lbx);
-        // basis (h_k = lambda(t+k)): h_2, h_2 - h_4 (same parity), h_1 + h_2 and
-        // h_1 + h_2 - h_3 - h_4 (the alternating part cancels)
+        // basis (h_k = lambda(t+k)): the even-step sequence h_2, h_4, h_6 and its first and second
+        // differences, and the sums of consecutive steps h_1 + h_2, h_3 + h_4, h_5 + h_6 (the
+        // alternating part cancels) and their first and second differences
         static constexpr double kBasis[kProjAdj][kProjAdj] = {
-            {0, 1, 0, 0}, {0, 1, 0, -1}, {1, 1, 0, 0}, {1, 1, -1, -1}};
+            {0, 1, 0, 0, 0, 0}, {0, 1, 0, -1, 0, 0}, {0, 1, 0, -2, 0, 1},
+            {1, 1, 0, 0, 0, 0}, {1, 1, -1, -1, 0, 0}, {1, 1, -2, -2, 1, 1}};
         project_warm_start<LT::D, T, kProjAdj>(c, A(lbx), (const T*)A(J.lpot), older, m,
                                               A(J.lbr[(t + 1) % kProjAdj]), kBasis);
       }
