@@ -498,17 +498,15 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
   } else {
     hipLaunchKernelGGL(k_cg_zero<T>, dim3(nb0), dim3(kBlock), 0, s, (const CgCtl*)ctl, N, x);
   }
-  // coarse hierarchy (Galerkin aggregation) and the dense coarsest inverse, only when iterating
+  // coarse hierarchy (Galerkin aggregation, with inverse diagonals) and the dense coarsest
+  // inverse, only when iterating; the fine level's inverse diagonal comes from pois_setup
   if (!stopped) {
-    hipLaunchKernelGGL(k_dinv<T>, dim3(nb0), dim3(kBlock), 0, s, stop, N, (const T*)dg0, c->ptr<T>(m0.dinv));
     for (size_t l = 0; l < c->tail_first; ++l) {
       MGLevel& f = c->mg[l];
       MGLevel& g = c->mg[l + 1];
       hipLaunchKernelGGL((k_coarsen<D, T>), dim3(nblocks(g.L.N)), dim3(kBlock), 0, s, stop, f.L,
                          (const T*)c->ptr<T>(f.cp), (const T*)c->ptr<T>(f.diag), g.L, c->ptr<T>(g.cp),
-                         c->ptr<T>(g.diag));
-      hipLaunchKernelGGL(k_dinv<T>, dim3(nblocks(g.L.N)), dim3(kBlock), 0, s, stop, g.L.N,
-                         (const T*)c->ptr<T>(g.diag), c->ptr<T>(g.dinv));
+                         c->ptr<T>(g.diag), c->ptr<T>(g.dinv));
     }
     hipLaunchKernelGGL((k_tail_setup<D, T>), dim3(1), dim3(kTailThreads), 0, s, tail_args<T>(c),
                        c->ptr<double>(c->off_inv));
@@ -581,7 +579,7 @@ static ehdlb_status pois_setup(ehdlb_ctx* c, const T* phi, const T* rho, const V
   MGLevel& m0 = c->mg[0];
   hipLaunchKernelGGL((k_pois_setup<LT, T>), dim3(nblocks(N)), dim3(kBlock), 0, c->stream, dm,
                      c->ptr<uint8_t>(c->off_flags), phi, rho, make_phys<T>(c->prm), volts, c->ptr<T>(m0.cp),
-                     c->ptr<T>(m0.diag), c->ptr<T>(c->off_b));
+                     c->ptr<T>(m0.diag), c->ptr<T>(m0.dinv), c->ptr<T>(c->off_b));
   LAUNCHCHK();
   return EHDLB_OK;
 }
@@ -605,7 +603,7 @@ static void project_warm_start(ehdlb_ctx* c, T* x, const T* b, const T* const* o
   double* coef = c->ptr<double>(c->off_pcoef);
   hipLaunchKernelGGL((k_proj_gram<D, T, M>), dim3(rb), dim3(kBlock), 0, s, m0.L, (const T*)c->ptr<T>(m0.cp),
                      (const T*)c->ptr<T>(m0.diag), b, h, m, keep, part);
-  hipLaunchKernelGGL((k_proj_solve<T, M>), dim3(1), dim3(kBlock), 0, s, (const double*)part, rb, m, h, coef);
+  hipLaunchKernelGGL((k_proj_solve<T, M>), dim3(1), dim3(kFinalWide), 0, s, (const double*)part, rb, m, h, coef);
   hipLaunchKernelGGL((k_proj_combine<T, M>), dim3(nblocks(N)), dim3(kBlock), 0, s, N, (const double*)coef, h, m, x);
 }
 

@@ -285,8 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_final(const double* __restrict__ par
 // then a fixed tree over the 16 waves).
 constexpr int kFinalWide = 1024;
 template <int K, bool MAX>
-__global__ __launch_bounds__(kFinalWide) void k_final_wide(const double* __restrict__ part, int nblk,
-                                                            double* __restrict__ out) {
+__device__ __forceinline__ void final_wide(const double* __restrict__ part, int nblk, double* __restrict__ out) {
   __shared__ double sm[kFinalWide / 64][K];
   double v[K];
 #pragma unroll
@@ -312,6 +311,11 @@ __global__ __launch_bounds__(kFinalWide) void k_final_wide(const double* __restr
     for (int w = 1; w < kFinalWide / 64; ++w) x = MAX ? fmax(x, sm[w][threadIdx.x]) : x + sm[w][threadIdx.x];
     out[threadIdx.x] = x;
   }
+}
+template <int K, bool MAX>
+__global__ __launch_bounds__(kFinalWide) void k_final_wide(const double* __restrict__ part, int nblk,
+                                                            double* __restrict__ out) {
+  final_wide<K, MAX>(part, nblk, out);
 }
 
 // Sum (or max) of n per-block partials, evaluated by every block in the same fixed order as
@@ -443,13 +447,14 @@ __global__ __launch_bounds__(kBlock) void k_pois_setup(Dims d, const uint8_t* __
                                                         const T* __restrict__ phi, const T* __restrict__ rho,
                                                         Phys<T> p, Volts<T> volts,
                                                         T* __restrict__ cp, T* __restrict__ diag,
-                                                        T* __restrict__ b) {
+                                                        T* __restrict__ dinv, T* __restrict__ b) {
   const int64_t node = sidx();
   if (node >= d.N) return;
   const int64_t N = d.N;
   if (flags[node] != 0) {
     for (int ax = 0; ax < L::D; ++ax) cp[(int64_t)ax * N + node] = T(0);
     diag[node] = T(0);
+    dinv[node] = T(0);
     b[node] = T(0);
     return;
   }
@@ -474,6 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_pois_setup(Dims d, const uint8_t* __
     }
   }
   diag[node] = dg;
+  dinv[node] = dg != T(0) ? T(1) / dg : T(0);
   b[node] = rhs;
 }
 
@@ -1103,7 +1109,8 @@ __global__ __launch_bounds__(kBlock) void k_up_small(const int* __restrict__ sto
 template <int D, class T>
 __global__ __launch_bounds__(kBlock) void k_coarsen(const int* __restrict__ stop, Level Lf,
                                                      const T* __restrict__ cpf, const T* __restrict__ diagf,
-                                                     Level Lc, T* __restrict__ cpc, T* __restrict__ diagc) {
+                                                     Level Lc, T* __restrict__ cpc, T* __restrict__ diagc,
+                                                     T* __restrict__ dinvc) {
   if (*stop) return;
   const int64_t I = gidx();
   if (I >= Lc.N) return;
@@ -1133,19 +1140,9 @@ __global__ __launch_bounds__(kBlock) void k_coarsen(const int* __restrict__ stop
         }
       }
   diagc[I] = dg;
+  dinvc[I] = dg != T(0) ? T(1) / dg : T(0);
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) cpc[(int64_t)ax * Lc.N + I] = c[ax];
-}
-
-// dinv = 1/diag on active cells, 0 on inactive ones
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_dinv(const int* __restrict__ stop, int64_t N, const T* __restrict__ diag,
-                                                  T* __restrict__ dinv) {
-  if (*stop) return;
-  const int64_t i = gidx();
-  if (i >= N) return;
-  const T d = diag[i];
-  dinv[i] = d != T(0) ? T(1) / d : T(0);
 }
 
 // per-block FP64 partial of a.b (grid-stride)
@@ -1387,20 +1384,14 @@ __host__ __device__ inline void proj_coefficients(const double* s, int m, double
   for (int j = 0; j < M; ++j) coef[j] = c[j] - c[j] == 0.0 ? c[j] : 0.0;  // 0 for inf and NaN
 }
 
-// sums the partials in a fixed order and solves G c = g by Cholesky in FP64; a vector whose
+// sums the partials in a fixed order (1024 threads) and solves G c = g by Cholesky in FP64; a vector whose
 // pivot falls below 1e-12 of its own G_jj (linearly dependent on the earlier ones) gets c_j = 0
 template <class T, int M>
-__global__ __launch_bounds__(kBlock) void k_proj_solve(const double* __restrict__ part, int nblk, int m,
-                                                       ProjVecs<T, M> h, double* __restrict__ coef) {
+__global__ __launch_bounds__(kFinalWide) void k_proj_solve(const double* __restrict__ part, int nblk, int m,
+                                                           ProjVecs<T, M> h, double* __restrict__ coef) {
   constexpr int P = proj_sums<M>();
-  double v[P];
-#pragma unroll
-  for (int k = 0; k < P; ++k) v[k] = 0.0;
-  for (int bb = threadIdx.x; bb < nblk; bb += kBlock)
-#pragma unroll
-    for (int k = 0; k < P; ++k) v[k] += part[(int64_t)bb * P + k];
   __shared__ double s[P];
-  block_reduce<P, false>(v, s);
+  final_wide<P, false>(part, nblk, s);
   __syncthreads();
   if (threadIdx.x != 0) return;
   double c[M];
