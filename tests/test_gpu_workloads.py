@@ -115,6 +115,24 @@ def test_config3_fields_vs_oracle(precision, tol, names):
     assert worst <= tol
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_config3_mass_conservation(precision):
+    """Per-component mass over 100 steps at 256x128x96 (the collision conserves each phase's
+    zeroth moment and bounce-back returns every population): round-off in FP64; in FP32 each
+    node's moment is a sum of 19 rounded values, so the drift per step is at most 19 * 2^-24 of
+    the mass, 100 times that over the run."""
+    steps = 100
+    case = make_case("c3", precision=precision)
+    sim = _sim(case, precision, poisson_tol=1e-13 if precision == "fp64" else 1e-5)
+    m0 = sim.observables()["mass"]
+    print("c3", precision, "mass over", steps, "steps", m0, flush=True)
+    sim.step(steps)
+    m1 = sim.observables()["mass"]
+    drift = float(np.max(np.abs(m1 - m0) / m0))
+    print(f"  max relative drift {drift:.3e}", flush=True)
+    assert drift <= (1e-12 if precision == "fp64" else steps * 19 * 2.0 ** -24)
+
+
 def test_config3_fp32_centroid_vs_fp64():
     steps, every = 5000, 250
     tracks = {}
