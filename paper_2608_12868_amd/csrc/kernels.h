@@ -1267,8 +1267,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_zero(const CgCtl* __restrict__ ct
 // values): successive solutions are nearly equal (or, for the adjoint, nearly opposite), and
 // differences such as h_1 - h_2 resolve what G_ij = h_i . A h_j in FP64 cannot.  With fewer than
 // M vectors B is the identity.  Three kernels: partial sums of G_ij = u_i . A u_j and
-// g_i = u_i . b (one pass that applies A to every u_j in FP64), a one-block Cholesky solve that
-// maps the coefficients back (a = B^T c), the combination.
+// g_i = u_i . b (one pass that applies A to every stored h_k in FP64 and forms the basis once per
+// cell), a one-block Cholesky solve that maps the coefficients back (a = B^T c), the combination.
 template <class T, int M>
 struct ProjVecs {
   const T* v[M];
@@ -1286,46 +1286,45 @@ __global__ __launch_bounds__(kBlock) void k_proj_gram(Level L, const T* __restri
   double acc[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) acc[k] = 0.0;
-  // u_j at cell j from the stored h_k (unused slots point at valid vectors and have zero
-  // columns in B: loads without branches)
-  auto basis = [&](int64_t j, double (&u)[M]) {
-    double hv[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) hv[k] = (double)h.v[k][j];
-#pragma unroll
-    for (int r = 0; r < M; ++r) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < M; ++k) s += h.B[r][k] * hv[k];
-      u[r] = s;
-    }
-  };
   int64_t lo, hi;
   chunk_range(L.N, lo, hi);
   const int N = (int)L.N;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-    // every load of the cell is independent of the others (inactive cells are masked, their
-    // neighbour indices are valid), so one iteration is one memory round trip
+    // A h_k in FP64 for every stored vector (the products of FP32 values are exact in FP64, so
+    // the basis differences formed from them below keep their accuracy), then u = B h and
+    // A u = B (A h) once per cell.  Every load of the cell is independent of the others (unused
+    // slots point at valid vectors and have zero columns in B; inactive cells are masked and
+    // their neighbour indices are valid), so one iteration is one memory round trip.
     const T dg = diag[i];
     const double bi = (double)b[i];
-    const T h0 = h.v[0][i];
     int cx, cy, cz;
     cell_xyz<D>(L, i, cx, cy, cz);
-    double u[M], au[M], un[M];
-    basis(i, u);
+    double hv[M], ah[M];
 #pragma unroll
-    for (int r = 0; r < M; ++r) au[r] = (double)dg * u[r];
+    for (int k = 0; k < M; ++k) {
+      hv[k] = (double)h.v[k][i];
+      ah[k] = (double)dg * hv[k];
+    }
+    const T h0 = h.v[0][i];
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) {
       int jp, jm;
       axis_pm<D>(L, (int)i, cx, cy, cz, ax, jp, jm);
       const double cpp = (double)cp[(int64_t)ax * N + i], cpm = (double)cp[(int64_t)ax * N + jm];
-      basis(jp, un);
 #pragma unroll
-      for (int r = 0; r < M; ++r) au[r] -= cpp * un[r];
-      basis(jm, un);
+      for (int k = 0; k < M; ++k) ah[k] -= cpp * (double)h.v[k][jp] + cpm * (double)h.v[k][jm];
+    }
+    double u[M], au[M];
 #pragma unroll
-      for (int r = 0; r < M; ++r) au[r] -= cpm * un[r];
+    for (int r = 0; r < M; ++r) {
+      double su = 0.0, sa = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        su += h.B[r][k] * hv[k];
+        sa += h.B[r][k] * ah[k];
+      }
+      u[r] = su;
+      au[r] = sa;
     }
     if (keep) keep[i] = h0;
     const bool on = dg != T(0);  // selected, not multiplied: inactive cells contribute nothing
