@@ -1344,42 +1344,52 @@ __global__ __launch_bounds__(kBlock) void k_proj_gram(Level L, const T* __restri
 // G c = g from the sums s (upper triangle of G row-major, then g) for the first m vectors
 template <int M>
 __host__ __device__ inline void proj_coefficients(const double* s, int m, double* coef) {
+  // every loop runs to the compile-time M (the vector count m only masks), so the loops unroll
+  // and the small arrays stay in registers
   double G[M][M], g[M], Lc[M][M], y[M], c[M];
   bool keepj[M];
   int k = 0;
+#pragma unroll
   for (int r = 0; r < M; ++r)
+#pragma unroll
     for (int cc = r; cc < M; ++cc) G[r][cc] = G[cc][r] = s[k++];
+#pragma unroll
   for (int r = 0; r < M; ++r) g[r] = s[k++];
+#pragma unroll
   for (int r = 0; r < M; ++r)
+#pragma unroll
     for (int i = 0; i < M; ++i) Lc[r][i] = 0.0;
+#pragma unroll
   for (int j = 0; j < M; ++j) {
-    keepj[j] = false;
-    if (j >= m || !(G[j][j] > 0.0)) continue;
     double d = G[j][j];
+#pragma unroll
     for (int i = 0; i < j; ++i) d -= Lc[j][i] * Lc[j][i];
-    if (!(d > 1e-12 * G[j][j])) continue;
-    keepj[j] = true;
-    Lc[j][j] = sqrt(d);
-    for (int r = j + 1; r < m; ++r) {
+    keepj[j] = j < m && G[j][j] > 0.0 && d > 1e-12 * G[j][j];
+    const double ljj = keepj[j] ? sqrt(d) : 1.0;
+    Lc[j][j] = keepj[j] ? ljj : 0.0;
+#pragma unroll
+    for (int r = j + 1; r < M; ++r) {
       double e = G[r][j];
+#pragma unroll
       for (int i = 0; i < j; ++i) e -= Lc[r][i] * Lc[j][i];
-      Lc[r][j] = e / Lc[j][j];
+      Lc[r][j] = keepj[j] && r < m ? e / ljj : 0.0;
     }
   }
+#pragma unroll
   for (int j = 0; j < M; ++j) {
-    y[j] = 0.0;
-    if (!keepj[j]) continue;
     double e = g[j];
+#pragma unroll
     for (int i = 0; i < j; ++i) e -= Lc[j][i] * y[i];
-    y[j] = e / Lc[j][j];
+    y[j] = keepj[j] ? e / Lc[j][j] : 0.0;
   }
+#pragma unroll
   for (int j = M - 1; j >= 0; --j) {
-    c[j] = 0.0;
-    if (!keepj[j]) continue;
     double e = y[j];
+#pragma unroll
     for (int i = j + 1; i < M; ++i) e -= Lc[i][j] * c[i];
-    c[j] = e / Lc[j][j];
+    c[j] = keepj[j] ? e / Lc[j][j] : 0.0;
   }
+#pragma unroll
   for (int j = 0; j < M; ++j) coef[j] = c[j] - c[j] == 0.0 ? c[j] : 0.0;  // 0 for inf and NaN
 }
 
