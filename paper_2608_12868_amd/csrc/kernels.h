@@ -50,11 +50,11 @@ __device__ __forceinline__ int64_t gidx() { return (int64_t)blockIdx.x * blockDi
 __device__ __forceinline__ int64_t sidx() {
   return (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
 }
-// global thread index of the fused step and the adjoint passes on 3D lattices (plane = nx ny
-// nodes, grid of whole blocks over the lattice): the blocks of each z plane form 8
-// contiguous bands of rows, one per XCD, each walked in order, so the rows above and below a
-// block are read through the same XCD's L2, and the same rows of the next plane follow an
-// eighth of a plane later (plain order when a plane is not a multiple of 8 blocks)
+// global thread index of the fused step, the adjoint passes and the potential operator's set-up
+// on 3D lattices (plane = nx ny nodes, grid of whole blocks over the lattice): the blocks of each
+// z plane form 8 contiguous bands of rows, one per XCD, each walked in order, so the rows above
+// and below a block are read through the same XCD's L2, and the same rows of the next plane
+// follow an eighth of a plane later (plain order when a plane is not a multiple of 8 blocks)
 __device__ __forceinline__ int64_t band_idx(int64_t plane) {
   const int bpp = (int)(plane / blockDim.x);
   int b = blockIdx.x;
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_pois_setup(Dims d, const uint8_t* __
                                                         Phys<T> p, Volts<T> volts,
                                                         T* __restrict__ cp, T* __restrict__ diag,
                                                         T* __restrict__ dinv, T* __restrict__ b) {
-  const int64_t node = sidx();
+  const int64_t node = L::D == 3 ? band_idx(d) : sidx();
   if (node >= d.N) return;
   const int64_t N = d.N;
   if (flags[node] != 0) {
