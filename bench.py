@@ -98,8 +98,9 @@ ADJOINT = {
 
 def adjoint_leg(key, fd_h=1e-4, seed=1):
     """Cost of dL/dV for L = (x_c(T) - x*)^2 (x* = initial centroid + 5 lu), FP32 path, with
-    each forward warm start (projected onto the last four potentials, the default; previous
-    potential; extrapolated from the last two): plain forward,
+    each forward warm start (projected onto the last four potentials then at least one CG
+    iteration, the default; the projection alone; previous potential; extrapolated from the
+    last two): plain forward,
     checkpointed forward and reverse sweep (recompute included), timed with device syncs; each
     gradient's error against the FP64 adjoint (where it fits in memory) and the directional
     derivatives against central differences of the FP64 forward."""
@@ -112,7 +113,8 @@ def adjoint_leg(key, fd_h=1e-4, seed=1):
     case = make_case(name)
     runs = {}
     target = None
-    for mode, label in ((2, "warm_projected"), (0, "warm_previous"), (1, "warm_extrapolated")):
+    for mode, label in ((2, "warm_projected"), (3, "warm_projected_only"), (0, "warm_previous"),
+                        (1, "warm_extrapolated")):
         sim = Simulation.from_case(case, precision="fp32", poisson_tol=1e-5)
         sim.set_solver_options(warm_start=mode)
         sim.set_schedule(0, case.schedule, case.t_total)
@@ -150,6 +152,7 @@ def adjoint_leg(key, fd_h=1e-4, seed=1):
         ws = sim.adjoint_workspace_bytes(T, K) / 1e9
         del sim
         torch.cuda.empty_cache()
+        print(f"adjoint leg {key}: {label} reverse/forward {t_adj / t_fwd:.3f}", file=sys.stderr, flush=True)
     peak32 = torch.cuda.max_memory_allocated() / 1e9
 
     # FP64: adjoint (when the checkpoints fit) and central differences of the forward
@@ -183,6 +186,8 @@ def adjoint_leg(key, fd_h=1e-4, seed=1):
         torch.cuda.synchronize()
         t64["adjoint_s"] = time.perf_counter() - t0
         t64["ratio_adjoint_to_forward"] = t64["adjoint_s"] / t64["forward_s"]
+        print(f"adjoint leg {key}: fp64 reverse/forward {t64['ratio_adjoint_to_forward']:.3f}", file=sys.stderr,
+              flush=True)
         s64.adj_ws = None
         torch.cuda.empty_cache()
 
@@ -192,6 +197,7 @@ def adjoint_leg(key, fd_h=1e-4, seed=1):
         d = rng.standard_normal(len(case.schedule))
         d /= np.linalg.norm(d)
         f = (loss(case64.schedule + fd_h * d) - loss(case64.schedule - fd_h * d)) / (2 * fd_h)
+        print(f"adjoint leg {key}: central difference {len(fd) + 1}/{ndir} done", file=sys.stderr, flush=True)
         # relative to the directional derivative, and to the gradient's norm (the first is
         # inflated on directions where the derivative is much smaller than the gradient)
         row = {"fd": f}

@@ -119,7 +119,9 @@ struct ehdlb_ctx {
   double mg_lo = 0.5, mg_hi = 2.0;
   double mg_overcorrect = 2.0;
   bool stream_pops = false;       // population loads with the non-temporal hint
-  int warm_mode = 2;  // forward warm start: 0 previous potential, 1 extrapolated, 2 projected
+  // forward warm start: 0 previous potential, 1 extrapolated, 2 projected with at least one CG
+  // iteration, 3 projected
+  int warm_mode = 2;
   // smoothing polynomial z += c1 y - c2 D^-1 A y: p(mu) = 1 - c1 mu + c2 mu^2 = T2(s(mu))/T2(s(0)),
   // s(mu) = (hi + lo - 2 mu)/(hi - lo)
   void poly(double& c1, double& c2) const {
@@ -453,7 +455,7 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot
 // the last solve took.  Afterwards it continues one iteration at a time.  The iterates do not
 // depend on this.
 template <class LT, class T>
-static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hist) {
+static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hist, int min1 = 0) {
   constexpr int D = LT::D;
   hipStream_t s = c->stream;
   const int64_t N = c->N;
@@ -479,7 +481,7 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
                      (const double*)nullptr, 0, tol, 0, m0.L, (const T*)cp0, (const T*)dg0, b, (const T*)x, r,
                      ptrue);
   hipLaunchKernelGGL(k_cg_judge, dim3(1), dim3(kBlock), 0, s, ctl, (const double*)ptrue, (const double*)pmax, rb0,
-                     tol, eps_t, 0, 0, 1);
+                     tol, eps_t, 0, 0, 1, min1);
   LAUNCHCHK();
   auto read_ctl = [&]() -> ehdlb_status {
     HIPCHK(hipMemcpyAsync(&c->hctl, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s));
@@ -544,7 +546,7 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
                            (const double*)pmax, rb0, tol, force, m0.L, (const T*)cp0, (const T*)dg0, b, (const T*)x,
                            r, ptrue);
         hipLaunchKernelGGL(k_cg_judge, dim3(1), dim3(kBlock), 0, s, ctl, (const double*)ptrue, (const double*)pmax,
-                           rb0, tol, eps_t, it, force, 0);
+                           rb0, tol, eps_t, it, force, 0, 0);
       }
       LAUNCHCHK();
       if ((st = precondition(prz[it & 1]))) return st;
@@ -618,7 +620,7 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
   if (c->warm_mode == 1) {
     hipLaunchKernelGGL(k_extrapolate<T>, dim3(nblocks(c->N)), dim3(kBlock), 0, c->stream, c->N, pot,
                        c->ptr<T>(c->off_pot_old));
-  } else if (c->warm_mode == 2 && c->t >= 1) {
+  } else if (c->warm_mode >= 2 && c->t >= 1) {
     const int64_t t = c->t;
     const int m = (int)std::min<int64_t>(t, kProjFwd);
     const T* older[kProjFwd - 1];
@@ -634,7 +636,10 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
     project_warm_start<LT::D, T, kProjFwd>(c, pot, c->ptr<T>(c->off_b), older, m,
                                           c->ptr<T>(c->off_pot_hist[(t - 1) % kProjFwd]), kBasis);
   }
-  return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b), c->cg_hist[0]);
+  // mode 2: at least one CG iteration after the projected start (a solve that keeps the start
+  // leaves an error that is carried into the next steps' starts, correlated from step to step,
+  // and biases the gradients of the trajectory)
+  return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b), c->cg_hist[0], c->warm_mode == 2 ? 1 : 0);
 }
 
 // ============================================================================ timing
@@ -1581,7 +1586,7 @@ ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* c, double lo, double hi, double
   if (!c) return EHDLB_EINVAL;
   if (!(lo > 0.0 && hi > lo && hi <= 2.0)) return fail(c, EHDLB_EINVAL, "need 0 < lo < hi <= 2");
   if (!(overcorrect > 0.0 && overcorrect <= 4.0)) return fail(c, EHDLB_EINVAL, "over-correction must lie in (0, 4]");
-  if (warm_start < 0 || warm_start > 2) return fail(c, EHDLB_EINVAL, "warm_start must be 0, 1 or 2");
+  if (warm_start < 0 || warm_start > 3) return fail(c, EHDLB_EINVAL, "warm_start must be 0, 1, 2 or 3");
   c->mg_lo = lo;
   c->mg_hi = hi;
   c->mg_overcorrect = overcorrect;

@@ -1211,12 +1211,14 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(const CgCtl* __restrict__
 }
 
 // Convergence decision from the true-residual partials (one block).  init != 0: the check
-// before the first iteration (sets every field).  Otherwise runs only when k_true_resid ran,
-// i.e. the solve is running and cg_trigger fires; stops on convergence, a non-finite residual
-// or the iteration cap (force).
+// before the first iteration (sets every field; min1 != 0: iterate at least once even if the
+// start already meets the tolerance).  Otherwise runs only when k_true_resid ran, i.e. the
+// solve is running and cg_trigger fires; stops on convergence, a non-finite residual or the
+// iteration cap (force).
 __global__ __launch_bounds__(kBlock) void k_cg_judge(CgCtl* __restrict__ ctl, const double* __restrict__ ptrue,
                                                       const double* __restrict__ pmax, int nblk, double tol,
-                                                      double eps_t, int it, int force, int init) {
+                                                      double eps_t, int it, int force, int init,
+                                                      int min1) {
   if (!init) {
     if (ctl->stop) return;
     if (!cg_trigger(ctl, pmax, nblk, tol, force)) return;
@@ -1240,7 +1242,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_judge(CgCtl* __restrict__ ctl, co
     ctl->rel0 = rel;
     ctl->zero = bmax == 0.0;
     ctl->iters = 0;
-    const bool run = bmax != 0.0 && !done && isfinite(rel);
+    const bool run = bmax != 0.0 && (!done || min1) && isfinite(rel);
     ctl->iterated = run;
     ctl->stop = !run;
     ctl->conv = bmax == 0.0 || done;

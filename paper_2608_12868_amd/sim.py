@@ -169,7 +169,8 @@ class Simulation(Context):
     def set_solver_options(self, lo=0.5, hi=2.0, overcorrect=2.0, warm_start=2):
         """Chebyshev smoothing interval [lo, hi] of D^-1 A, coarse-correction scale, and the
         forward warm start (0: previous step's potential; 1: extrapolated from the last two;
-        2: Galerkin projection onto the last four, the default)."""
+        2: Galerkin projection onto the last four, then at least one CG iteration, the default;
+        3: the projection alone)."""
         self._chk(L.lib().ehdlb_set_solver_options(self.h, float(lo), float(hi), float(overcorrect),
                                                    int(warm_start)))
 
