@@ -153,22 +153,25 @@ def test_config3_fp32_centroid_vs_fp64():
     assert err.max() <= 1e-4
 
 
-def test_config4_fp32_gradient_with_extrapolated_warm_start():
-    """512x256, 64-segment schedule, T = 4000, K = 100: with the extrapolated forward warm start
-    the FP32 gradient of the centroid agrees with the FP64 adjoint to 1e-4 (with the previous
-    potential as warm start the solve lags the exact Gauss law and the agreement is ~4e-3)."""
+@pytest.mark.parametrize("warm", [2, 1])
+def test_config4_fp32_gradient_vs_fp64(warm):
+    """512x256, 64-segment schedule, T = 4000, K = 100: the FP32 gradient of the centroid agrees
+    with the FP64 adjoint to 1e-4 with the default forward warm start (projection, then at least
+    one CG iteration) and with the extrapolated one (a start kept without iterating lags the
+    exact Gauss law by an error correlated from step to step: ~7e-4 with the projection alone,
+    ~4e-3 with the previous potential)."""
     T, K = 4000, 100
     g = {}
     for prec in ("fp64", "fp32"):
         case = make_case("c4", precision=prec)
         sim = _sim(case, prec, poisson_tol=1e-13 if prec == "fp64" else 1e-5)
         if prec == "fp32":
-            sim.set_solver_options(warm_start=1)
+            sim.set_solver_options(warm_start=warm)
         sim.set_schedule(0, case.schedule, case.t_total)
-        print("c4", prec, "T", T, "K", K, flush=True)
+        print("c4", prec, "warm_start", warm, "T", T, "K", K, flush=True)
         sim.forward_checkpointed(T, K)
         g[prec] = sim.adjoint(np.array([1.0, 0.0, 0.0]), np.zeros(3), 0, len(case.schedule))
         del sim
     err = np.abs(g["fp32"] - g["fp64"]).max() / np.abs(g["fp64"]).max()
-    print(f"  FP32 (extrapolated warm start) vs FP64 adjoint: {err:.3e}", flush=True)
+    print(f"  FP32 (warm_start {warm}) vs FP64 adjoint: {err:.3e}", flush=True)
     assert err <= 1e-4
