@@ -8,10 +8,11 @@ It is a plain, slow, whole-array implementation written from the paper's Methods
 section (Eqs. 8-21) in plain PyTorch CPU float64 ops, with no blocking, fusion
 or closed-form shortcuts: the multiple-relaxation-time collisions are applied
 literally in raw-moment space (m* = (I - S) m + S m_eq + (I - S/2) M C, then
-f* = M^-1 m*), and the electric potential is obtained by a sparse direct solve
-of the discrete Gauss law.  Because every operation is a differentiable torch
-op (the direct solve carries its own adjoint), reverse-mode autograd through
-this oracle is the FP64 CPU adjoint of the discrete step.
+f* = M^-1 m*), and the electric potential is obtained by solving the discrete
+Gauss law (2D: sparse LU; 3D: Jacobi-preconditioned conjugate gradients to a
+relative residual of 1e-15).  Because every operation is a differentiable torch
+op (the solve carries its own adjoint), reverse-mode autograd through this
+oracle is the FP64 CPU adjoint of the discrete step.
 
 Where the paper is silent, each module states the reading it takes.
 """
