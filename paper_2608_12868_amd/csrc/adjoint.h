@@ -6,7 +6,8 @@
 // potential solve is treated as exact: its adjoint is one solve with the same symmetric
 // matrix.  Everything the collision needs from the populations is carried by a few moments
 // (MomLayout), which the forward recompute stores per step together with Phi (with wetting
-// ghosts), rho_e, the potential and the previous-step fields.
+// ghosts), rho_e, the potential and the previous step's Phi, u and rho_e (the previous step's
+// Ohmic source enters the charge source linearly, so its value is not needed).
 //
 // Passes per step (all gathers, no atomics, fixed summation order):
 //   A   per fluid node: recompute the forward quantities, gather the streamed population
@@ -28,7 +29,7 @@ namespace ehd {
 template <class L>
 struct RecLayout {
   static constexpr int D = L::D;
-  static constexpr int PHI = 0, RHO = 3, POT = 4, PHIP = 5, UP = 8, RHOP = 8 + D, QP = 9 + D, MOM = 10 + D;
+  static constexpr int PHI = 0, RHO = 3, POT = 4, PHIP = 5, UP = 8, RHOP = 8 + D, MOM = 9 + D;
   static constexpr int COUNT = MOM + MomLayout<L>::COUNT;
 };
 

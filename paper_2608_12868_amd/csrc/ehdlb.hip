@@ -990,7 +990,6 @@ static ehdlb_status step_record(ehdlb_ctx* c, T* rec) {
     HIPCHK(hipMemcpyAsync(rec + (size_t)RL::RHO * N, rho, N * ts, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(rec + (size_t)RL::POT * N, c->ptr<T>(c->off_pot), N * ts, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(rec + (size_t)RL::RHOP * N, c->ptr<T>(c->off_rho[pp]), N * ts, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(rec + (size_t)RL::QP * N, c->ptr<T>(c->off_q[pp]), N * ts, hipMemcpyDeviceToDevice, s));
   }
   StepArgs<T> a{};
   a.d = dm;
