@@ -34,8 +34,10 @@ constexpr int kSolverParts = 7;
 // earlier solutions spanning the projected warm starts: forward (potentials of steps t-1..t-4)
 // and adjoint (adjoint potentials of steps t+1..t+6, which alternate in sign)
 constexpr int kProjFwd = 4, kProjAdj = 6;
-// grid of the projection's Gram pass (more blocks than the solver's reductions: it is latency bound)
-constexpr int kProjBlocks = 4096;
+// grid of the projection's Gram pass: its per-block partials (up to 27 FP64 each) are summed by
+// one workgroup, whose read bandwidth bounds the solve (4096 blocks: 65 us at 384x192x128,
+// 1024: 28 us, with the Gram pass no slower)
+constexpr int kProjBlocks = 1024;
 // MI355X's Infinity Cache (memory-side last-level cache)
 constexpr size_t kInfinityCacheBytes = (size_t)256 << 20;
 int rblocks(int64_t n) { return std::min(nblocks(n), kRedBlocks); }
