@@ -615,9 +615,10 @@ template <class LT, class T>
 static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, const Volts<T>& volts) {
   ehdlb_status st = pois_setup<LT, T>(c, phi, rho, volts);
   if (st) return st;
-  // optional warm starts: extrapolated linearly from the potentials of the two previous steps,
-  // or projected onto the potentials of the last four steps (kept in the saved state, so a
-  // replay from a checkpoint takes the same iterates)
+  // warm start (the potential of the previous step is the plain one): extrapolated linearly from
+  // the potentials of the two previous steps, or projected onto the potentials of the last four
+  // steps (the default; kept in the saved state, so a replay from a checkpoint takes the same
+  // iterates)
   T* pot = c->ptr<T>(c->off_pot);
   if (c->warm_mode == 1) {
     hipLaunchKernelGGL(k_extrapolate<T>, dim3(nblocks(c->N)), dim3(kBlock), 0, c->stream, c->N, pot,
@@ -628,15 +629,15 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
     const T* older[kProjFwd - 1];
     for (int j = 1; j < kProjFwd; ++j) older[j - 1] = j < m ? c->ptr<T>(c->off_pot_hist[(t - 1 - j) % kProjFwd]) : pot;
     // basis: phi(t-1) and its backward differences up to the third, u_r = sum_k (-1)^k C(r, k) h_k
-    double kBasis[kProjFwd][kProjFwd];
+    double basis[kProjFwd][kProjFwd];
     for (int r = 0; r < kProjFwd; ++r)
       for (int k = 0; k < kProjFwd; ++k) {
         double binom = 1.0;
         for (int i = 0; i < k; ++i) binom = binom * (r - i) / (i + 1);
-        kBasis[r][k] = k <= r ? ((k & 1) ? -binom : binom) : 0.0;
+        basis[r][k] = k <= r ? ((k & 1) ? -binom : binom) : 0.0;
       }
     project_warm_start<LT::D, T, kProjFwd>(c, pot, c->ptr<T>(c->off_b), older, m,
-                                          c->ptr<T>(c->off_pot_hist[(t - 1) % kProjFwd]), kBasis);
+                                          c->ptr<T>(c->off_pot_hist[(t - 1) % kProjFwd]), basis);
   }
   // mode 2: at least one CG iteration after the projected start (a solve that keeps the start
   // leaves an error that is carried into the next steps' starts, correlated from step to step,
