@@ -34,6 +34,11 @@ constexpr int kSolverParts = 7;
 // earlier solutions spanning the projected warm starts: forward (potentials of steps t-1..t-4)
 // and adjoint (adjoint potentials of steps t+1..t+6, which alternate in sign)
 constexpr int kProjFwd = 4, kProjAdj = 6;
+// steps between rebuilds of the forward solves' coarse hierarchy (a preconditioner: the coarse
+// operators of a few steps back still precondition the current fine operator well)
+constexpr int64_t kHierLag = 8;
+// saved-state header tag (its layout: t, tag, N, bytes per value, hierarchy step)
+constexpr int64_t kStateMagic = 0x45484443;
 // grid of the projection's Gram pass: its per-block partials (up to 27 FP64 each) are summed by
 // one workgroup, whose read bandwidth bounds the solve (4096 blocks: 65 us at 384x192x128,
 // 1024: 28 us, with the Gram pass no slower)
@@ -86,11 +91,13 @@ struct ehdlb_ctx {
     double max_rel0 = 0.0;
   } cg_hist[2];
   ehd::CgCtl hctl{};  // host copy of the solve's control block
+  int64_t hier_t = -1;  // step whose operator the coarse hierarchy was built from (-1: none); saved
   // layout (byte offsets into ws)
   size_t off_pop[2]{}, off_phi[2]{}, off_rho[2]{}, off_u[2]{}, off_q[2]{}, off_pot = 0, off_pot_old = 0;
   size_t off_pot_hist[kProjFwd]{};  // potentials of earlier steps for the projected warm start (ring by t)
   // end of the state region that save_state copies after the populations
-  size_t state_end() const { return off_pot_hist[kProjFwd - 1] + (size_t)N * tsize; }
+  size_t off_state_end = 0;  // end of the state region (the saved state)
+  size_t state_end() const { return off_state_end; }
   size_t off_flags = 0, off_gnode = 0, off_gsrc = 0, off_glen = 0, off_scratch = 0;
   size_t off_b = 0, off_r = 0, off_z = 0, off_p = 0, off_qv = 0, off_spart = 0;
   size_t off_part = 0, off_red = 0, off_cg = 0, off_inv = 0, off_dbl = 0, off_ppart = 0, off_pcoef = 0;
@@ -99,7 +106,7 @@ struct ehdlb_ctx {
   size_t tail_first = 0;  // first level handled by the single-workgroup tail kernel
   int64_t max_ghost = 0;
   int64_t nparts = 0;
-  int64_t hdr[4]{};  // host staging of the state header (kept alive for async copies)
+  int64_t hdr[5]{};  // host staging of the state header (kept alive for async copies)
   // wetting links sorted by source (for the adjoint's gather of ghost cotangents)
   std::vector<int32_t> gs_node, src_node, src_start;
   std::vector<double> gs_len;
@@ -218,6 +225,22 @@ static void host_lattice(int dim, std::vector<int>& ex, std::vector<int>& ey, st
 }
 
 // ============================================================================ layout
+// dimensions of the potential solver's levels: aggregation of 2 cells per axis down to at most
+// kCoarseMax cells (or until a level stops shrinking)
+static std::vector<Level> mg_levels(const ehdlb_ctx* c) {
+  std::vector<Level> v;
+  v.push_back(Level{{c->lat.n[0], c->lat.n[1], c->lat.n[2]}, c->N});
+  while (v.back().N > kCoarseMax) {
+    const Level f = v.back();
+    Level l{};
+    for (int a = 0; a < 3; ++a) l.n[a] = (a < c->D) ? (f.n[a] + 1) / 2 : 1;
+    l.N = (int64_t)l.n[0] * l.n[1] * l.n[2];
+    if (l.N == f.N) break;
+    v.push_back(l);
+  }
+  return v;
+}
+
 static void plan_layout(ehdlb_ctx* c) {
   const int64_t N = c->N;
   const size_t ts = c->tsize;
@@ -239,6 +262,22 @@ static void plan_layout(ehdlb_ctx* c) {
   c->off_pot = take(N * ts);
   c->off_pot_old = take(N * ts);  // potential of the previous step (warm-start extrapolation)
   for (int k = 0; k < kProjFwd; ++k) c->off_pot_hist[k] = take(N * ts);
+  // the coarse levels of the potential solver's hierarchy (Galerkin operators, inverse
+  // diagonals, dense coarsest inverse) belong to the state: the forward solves rebuild them
+  // every kHierLag steps, and a replay from a saved state must precondition with the same ones
+  std::vector<Level> levels;
+  std::vector<size_t> hcp, hdiag, hdinv;
+  if (c->ehd) {
+    levels = mg_levels(c);
+    for (size_t l = 1; l < levels.size(); ++l) {
+      hcp.push_back(take((size_t)c->D * levels[l].N * ts));
+      hdiag.push_back(take(levels[l].N * ts));
+      hdinv.push_back(take(levels[l].N * ts));
+    }
+    const int64_t nc = levels.back().N;
+    c->off_inv = take((size_t)nc * nc * 8);
+  }
+  c->off_state_end = o;
   // --- geometry
   c->off_flags = take(N);
   c->max_ghost = N;  // upper bound; actual count known at set_geometry
@@ -259,9 +298,8 @@ static void plan_layout(ehdlb_ctx* c) {
     c->off_z = take(N * ts);
     c->off_p = take(N * ts);
     c->off_qv = take(N * ts);
-    Level L0{{c->lat.n[0], c->lat.n[1], c->lat.n[2]}, N};
     MGLevel m0{};
-    m0.L = L0;
+    m0.L = levels[0];
     m0.cp = take((size_t)c->D * N * ts);
     m0.diag = take(N * ts);
     m0.dinv = take(N * ts);
@@ -269,24 +307,17 @@ static void plan_layout(ehdlb_ctx* c) {
     m0.z = take(N * ts);
     m0.t = take(N * ts);
     c->mg.push_back(m0);
-    while (c->mg.back().L.N > kCoarseMax) {
-      Level f = c->mg.back().L;
-      Level l{};
-      for (int a = 0; a < 3; ++a) l.n[a] = (a < c->D) ? (f.n[a] + 1) / 2 : 1;
-      l.N = (int64_t)l.n[0] * l.n[1] * l.n[2];
-      if (l.N == f.N) break;
+    for (size_t l = 1; l < levels.size(); ++l) {
       MGLevel m{};
-      m.L = l;
-      m.cp = take((size_t)c->D * l.N * ts);
-      m.diag = take(l.N * ts);
-      m.dinv = take(l.N * ts);
-      m.r = take(l.N * ts);
-      m.z = take(l.N * ts);
-      m.t = take(l.N * ts);
+      m.L = levels[l];
+      m.cp = hcp[l - 1];
+      m.diag = hdiag[l - 1];
+      m.dinv = hdinv[l - 1];
+      m.r = take(levels[l].N * ts);
+      m.z = take(levels[l].N * ts);
+      m.t = take(levels[l].N * ts);
       c->mg.push_back(m);
     }
-    const int64_t nc = c->mg.back().L.N;
-    c->off_inv = take((size_t)nc * nc * 8);
     c->tail_first = c->mg.size() - 1;
     int64_t tail_cells = c->mg.back().L.N;
     while (c->tail_first > 0) {
@@ -503,8 +534,12 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
     hipLaunchKernelGGL(k_cg_zero<T>, dim3(nb0), dim3(kBlock), 0, s, (const CgCtl*)ctl, N, x);
   }
   // coarse hierarchy (Galerkin aggregation, with inverse diagonals) and the dense coarsest
-  // inverse, only when iterating; the fine level's inverse diagonal comes from pois_setup
-  if (!stopped) {
+  // inverse, only when iterating; the fine level's inverse diagonal comes from pois_setup.  The
+  // forward solves rebuild it every kHierLag steps (it only preconditions the current fine
+  // operator); the adjoint's solves rebuild it every time, which invalidates the forward's.
+  const bool fwd_solve = &hist == &c->cg_hist[0];
+  const bool rebuild = !fwd_solve || c->hier_t < 0 || c->t - c->hier_t >= kHierLag;
+  if (!stopped && rebuild) {
     for (size_t l = 0; l < c->tail_first; ++l) {
       MGLevel& f = c->mg[l];
       MGLevel& g = c->mg[l + 1];
@@ -558,6 +593,8 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
     batch = 1;
   }
   const CgCtl& h = c->hctl;
+  // the build kernels ran iff the solve iterated (they return at once once it has stopped)
+  if (!stopped && rebuild) c->hier_t = fwd_solve && h.iterated ? c->t : -1;
   c->last_resid0 = h.rel0;
   c->last_iters = h.iterated && !h.zero ? h.iters : 0;
   c->last_resid = h.zero ? 0.0 : h.rel;
@@ -1234,6 +1271,7 @@ ehdlb_status ehdlb_bind(ehdlb_ctx* c, void* ws, size_t bytes, void* stream) {
 ehdlb_status ehdlb_set_geometry(ehdlb_ctx* c, const uint8_t* flags) {
   if (!c) return EHDLB_EINVAL;
   if (!flags) return fail(c, EHDLB_EINVAL, "null flags");
+  c->hier_t = -1;
   const int nx = c->lat.n[0], ny = c->lat.n[1], nz = c->lat.n[2];
   const int64_t N = c->N;
   std::vector<int> ex, ey, ez, w36;
@@ -1376,6 +1414,7 @@ ehdlb_status ehdlb_set_phase(ehdlb_ctx* c, const double* phi) {
     if ((st = upload<float>(c, zero.data(), N, c->ptr<float>(c->off_rho[1])))) return st;
   }
   c->t = 0;
+  c->hier_t = -1;
   c->cur = 0;
   c->sticky = 0;
   c->last_iters = 0;
@@ -1502,9 +1541,10 @@ ehdlb_status ehdlb_save_state(ehdlb_ctx* c, void* dst) {
   if (!c->have_state) return fail(c, EHDLB_ESTATE, "save_state before set_phase");
   char* d = (char*)dst;
   c->hdr[0] = c->t;
-  c->hdr[1] = 0x45484442;
+  c->hdr[1] = kStateMagic;
   c->hdr[2] = (int64_t)c->N;
   c->hdr[3] = (int64_t)c->tsize;
+  c->hdr[4] = c->hier_t;
   HIPCHK(hipMemcpyAsync(d, c->hdr, sizeof(c->hdr), hipMemcpyHostToDevice, c->stream));
   const size_t pop_bytes = (size_t)c->F * c->Q * c->N * c->tsize;
   HIPCHK(hipMemcpyAsync(d + 256, c->ws + c->off_pop[c->cur], pop_bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -1519,10 +1559,10 @@ ehdlb_status ehdlb_load_state(ehdlb_ctx* c, const void* src) {
   if (!src) return fail(c, EHDLB_EINVAL, "null source");
   if (!c->bound || !c->have_geometry) return fail(c, EHDLB_ESTATE, "load_state before bind/set_geometry");
   const char* s = (const char*)src;
-  int64_t hdr[4];
+  int64_t hdr[5];
   HIPCHK(hipMemcpyAsync(hdr, s, sizeof(hdr), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  if (hdr[1] != 0x45484442 || hdr[2] != c->N || hdr[3] != (int64_t)c->tsize)
+  if (hdr[1] != kStateMagic || hdr[2] != c->N || hdr[3] != (int64_t)c->tsize)
     return fail(c, EHDLB_EINVAL, "state blob does not match this context");
   const size_t pop_bytes = (size_t)c->F * c->Q * c->N * c->tsize;
   HIPCHK(hipMemcpyAsync(c->ws + c->off_pop[0], s + 256, pop_bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -1530,6 +1570,7 @@ ehdlb_status ehdlb_load_state(ehdlb_ctx* c, const void* src) {
   HIPCHK(hipMemcpyAsync(c->ws + c->off_phi[0], s + 256 + align_up(pop_bytes), rest, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->t = hdr[0];
+  c->hier_t = hdr[4];
   c->cur = 0;
   c->have_state = true;
   return EHDLB_OK;
