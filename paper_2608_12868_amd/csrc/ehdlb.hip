@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 #include <type_traits>
@@ -91,6 +92,8 @@ struct ehdlb_ctx {
     double max_rel0 = 0.0;
   } cg_hist[2];
   ehd::CgCtl hctl{};  // host copy of the solve's control block
+  ehd::CgCtl* hctl_pin = nullptr;  // pinned staging of the control block (allocated at bind)
+  hipEvent_t ev_ctl = nullptr;     // marks the control block's copy in the stream
   int64_t hier_t = -1;  // step whose operator the coarse hierarchy was built from (-1: none); saved
   // layout (byte offsets into ws)
   size_t off_pop[2]{}, off_phi[2]{}, off_rho[2]{}, off_u[2]{}, off_q[2]{}, off_pot = 0, off_pot_old = 0;
@@ -488,7 +491,8 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot
 // the last solve took.  Afterwards it continues one iteration at a time.  The iterates do not
 // depend on this.
 template <class LT, class T>
-static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hist, int min1 = 0) {
+static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hist, int min1 = 0,
+                        const std::function<void()>* spec = nullptr) {
   constexpr int D = LT::D;
   hipStream_t s = c->stream;
   const int64_t N = c->N;
@@ -516,9 +520,18 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
   hipLaunchKernelGGL(k_cg_judge, dim3(1), dim3(kBlock), 0, s, ctl, (const double*)ptrue, (const double*)pmax, rb0,
                      tol, eps_t, 0, 0, 1, min1);
   LAUNCHCHK();
+  hipLaunchKernelGGL(k_cg_zero<T>, dim3(nb0), dim3(kBlock), 0, s, (const CgCtl*)ctl, N, x);
+  // The host reads the control block after an event that follows its copy, not after the whole
+  // stream: `spec` (if given) queues work that depends on the solution behind the copy, gated
+  // on the device by the stop flag, so it runs without a host round trip when the solve has
+  // stopped by then (and returns at once otherwise).  Every exit below follows a read at which
+  // the solve had stopped, so exactly one such launch does its work.
   auto read_ctl = [&]() -> ehdlb_status {
-    HIPCHK(hipMemcpyAsync(&c->hctl, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpyAsync(c->hctl_pin, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(c->ev_ctl, s));
+    if (spec) (*spec)();
+    HIPCHK(hipEventSynchronize(c->ev_ctl));
+    c->hctl = *c->hctl_pin;
     return EHDLB_OK;
   };
   bool stopped = false;
@@ -528,10 +541,7 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
     ehdlb_status e = read_ctl();
     if (e) return e;
     stopped = c->hctl.stop != 0;
-    if (c->hctl.zero) hipLaunchKernelGGL(k_zero<T>, dim3(nb0), dim3(kBlock), 0, s, N, x);
     batch = std::max(hist.last_nonzero - 1, 1);
-  } else {
-    hipLaunchKernelGGL(k_cg_zero<T>, dim3(nb0), dim3(kBlock), 0, s, (const CgCtl*)ctl, N, x);
   }
   // coarse hierarchy (Galerkin aggregation, with inverse diagonals) and the dense coarsest
   // inverse, only when iterating; the fine level's inverse diagonal comes from pois_setup.  The
@@ -649,7 +659,8 @@ static void project_warm_start(ehdlb_ctx* c, T* x, const T* b, const T* const* o
 }
 
 template <class LT, class T>
-static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, const Volts<T>& volts) {
+static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, const Volts<T>& volts,
+                                    const std::function<void()>* spec = nullptr) {
   ehdlb_status st = pois_setup<LT, T>(c, phi, rho, volts);
   if (st) return st;
   // warm start (the potential of the previous step is the plain one): extrapolated linearly from
@@ -679,7 +690,8 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
   // mode 2: at least one CG iteration after the projected start (a solve that keeps the start
   // leaves an error that is carried into the next steps' starts, correlated from step to step,
   // and biases the gradients of the trajectory)
-  return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b), c->cg_hist[0], c->warm_mode == 2 ? 1 : 0);
+  return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b), c->cg_hist[0], c->warm_mode == 2 ? 1 : 0,
+                    spec);
 }
 
 // ============================================================================ timing
@@ -753,11 +765,6 @@ static ehdlb_status step_impl(ehdlb_ctx* c, int64_t n) {
                          c->ptr<int32_t>(c->off_gsrc), c->ptr<T>(c->off_glen), phi, ph);
     LAUNCHCHK();
     if (ev) HIPCHK(hipEventRecord(ev[1], s));
-    if (EHD) {
-      ehdlb_status st = potential_solve<LT, T>(c, phi, rho, v);
-      if (st) return st;
-    }
-    if (ev) HIPCHK(hipEventRecord(ev[2], s));
     StepArgs<T> a{};
     a.d = dm;
     a.flags = flags;
@@ -775,8 +782,27 @@ static ehdlb_status step_impl(ehdlb_ctx* c, int64_t n) {
     a.p = ph;
     a.volts = v;
     a.dt_on = t == 0 ? T(0) : T(1);
-    launch_step<LT, T, EHD, false>(c, a);
-    LAUNCHCHK();
+    if (EHD) {
+      // the fused step is queued behind each read of the solve's control block, gated on the
+      // device by its stop flag: the launch that follows the solve's end does the work, without
+      // waiting for the host to see the control block (the step's timing starts there)
+      const int* gate = &c->ptr<CgCtl>(c->off_cg)->stop;
+      hipError_t launch_err = hipSuccess;
+      const std::function<void()> spec = [&]() {
+        if (ev && launch_err == hipSuccess) launch_err = hipEventRecord(ev[2], s);
+        a.gate = gate;
+        launch_step<LT, T, EHD, false>(c, a);
+        if (launch_err == hipSuccess) launch_err = hipGetLastError();
+      };
+      ehdlb_status st = potential_solve<LT, T>(c, phi, rho, v, &spec);
+      if (st) return st;
+      if (launch_err != hipSuccess)
+        return fail(c, EHDLB_EHIP, std::string("fused step launch: ") + hipGetErrorString(launch_err));
+    } else {
+      if (ev) HIPCHK(hipEventRecord(ev[2], s));
+      launch_step<LT, T, EHD, false>(c, a);
+      LAUNCHCHK();
+    }
     if (ev) {
       HIPCHK(hipEventRecord(ev[3], s));
       c->timed_steps++;
@@ -1262,6 +1288,8 @@ ehdlb_status ehdlb_bind(ehdlb_ctx* c, void* ws, size_t bytes, void* stream) {
   c->ws = (char*)ws;
   c->ws_bytes = bytes;
   c->stream = (hipStream_t)stream;
+  if (!c->hctl_pin) HIPCHK(hipHostMalloc((void**)&c->hctl_pin, sizeof(CgCtl), hipHostMallocDefault));
+  if (!c->ev_ctl) HIPCHK(hipEventCreateWithFlags(&c->ev_ctl, hipEventDisableTiming));
   c->bound = true;
   c->have_state = false;
   if (c->have_geometry) return upload_geometry(c);
@@ -1680,6 +1708,8 @@ const char* ehdlb_last_error(const ehdlb_ctx* c) { return c ? c->err.c_str() : "
 void ehdlb_destroy(ehdlb_ctx* c) {
   if (!c) return;
   for (auto& e : c->ev) (void)hipEventDestroy(e);
+  if (c->ev_ctl) (void)hipEventDestroy(c->ev_ctl);
+  if (c->hctl_pin) (void)hipHostFree(c->hctl_pin);
   delete c;
 }
 

@@ -137,6 +137,7 @@ struct StepArgs {
   Volts<T> volts;
   T dt_on;            // 0 on the first step (no time derivatives), 1 afterwards
   T* rec;             // STORE: population moments for the adjoint, [kMom][N] (see mom_layout)
+  const int* gate;    // if set, the launch does its work only when *gate != 0 (the solve stopped)
 };
 
 // Population moments a step's adjoint needs (the collision depends on the populations only

@@ -15,6 +15,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
   using ML = MomLayout<L>;
   constexpr int Q = L::Q;
   constexpr int D = L::D;
+  if (a.gate != nullptr && *a.gate == 0) return;
   const int64_t node = D == 3 ? band_idx(a.d) : gidx();
   if (node >= a.d.N) return;
   if (a.flags[node] != 0) return;
