@@ -1044,17 +1044,13 @@ static ehdlb_status step_record(ehdlb_ctx* c, T* rec) {
     hipLaunchKernelGGL(k_ghosts<T>, dim3(nblocks(G)), dim3(kBlock), 0, s, N, G, c->ptr<int32_t>(c->off_gnode),
                        c->ptr<int32_t>(c->off_gsrc), c->ptr<T>(c->off_glen), phi, ph);
   LAUNCHCHK();
-  if (EHD) {
-    ehdlb_status st = potential_solve<LT, T>(c, phi, rho, v);
-    if (st) return st;
-  }
+  // record copies that do not depend on the potential come before the solve
   HIPCHK(hipMemcpyAsync(rec + (size_t)RL::PHI * N, phi, 3 * N * ts, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(rec + (size_t)RL::PHIP * N, c->ptr<T>(c->off_phi[pp]), 3 * N * ts, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(rec + (size_t)RL::UP * N, c->ptr<T>(c->off_u[pp]), (size_t)LT::D * N * ts,
                         hipMemcpyDeviceToDevice, s));
   if (EHD) {
     HIPCHK(hipMemcpyAsync(rec + (size_t)RL::RHO * N, rho, N * ts, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(rec + (size_t)RL::POT * N, c->ptr<T>(c->off_pot), N * ts, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(rec + (size_t)RL::RHOP * N, c->ptr<T>(c->off_rho[pp]), N * ts, hipMemcpyDeviceToDevice, s));
   }
   StepArgs<T> a{};
@@ -1075,8 +1071,26 @@ static ehdlb_status step_record(ehdlb_ctx* c, T* rec) {
   a.volts = v;
   a.dt_on = t == 0 ? T(0) : T(1);
   a.rec = rec + (size_t)RL::MOM * N;
-  launch_step<LT, T, EHD, true>(c, a);
-  LAUNCHCHK();
+  if (EHD) {
+    // the potential's record copy and the fused step follow the solve without a host round
+    // trip, gated on its stop flag (as in the plain step)
+    const int* gate = &c->ptr<CgCtl>(c->off_cg)->stop;
+    hipError_t launch_err = hipSuccess;
+    const std::function<void()> spec = [&]() {
+      hipLaunchKernelGGL(k_copy_gated<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, gate, N,
+                         (const T*)c->ptr<T>(c->off_pot), rec + (size_t)RL::POT * N);
+      a.gate = gate;
+      launch_step<LT, T, EHD, true>(c, a);
+      if (launch_err == hipSuccess) launch_err = hipGetLastError();
+    };
+    ehdlb_status st = potential_solve<LT, T>(c, phi, rho, v, &spec);
+    if (st) return st;
+    if (launch_err != hipSuccess)
+      return fail(c, EHDLB_EHIP, std::string("recompute launch: ") + hipGetErrorString(launch_err));
+  } else {
+    launch_step<LT, T, EHD, true>(c, a);
+    LAUNCHCHK();
+  }
   c->cur = 1 - c->cur;
   c->t = t + 1;
   return EHDLB_OK;

@@ -1439,6 +1439,15 @@ __global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t N, T* __restrict
   older[i] = v;
 }
 
+// dst = src when *gate != 0 (a copy queued behind a solve, done only once it has stopped)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_copy_gated(const int* __restrict__ gate, int64_t N,
+                                                         const T* __restrict__ src, T* __restrict__ dst) {
+  if (*gate == 0) return;
+  const int64_t i = gidx();
+  if (i < N) dst[i] = src[i];
+}
+
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_zero(int64_t N, T* __restrict__ x) {
   const int64_t i = gidx();
