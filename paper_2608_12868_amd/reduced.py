@@ -1,0 +1,153 @@
+"""Reduced-order model of an electric-field-driven droplet on a lubricant-infused surface
+(Results, Eqs. 1-7): the drag coefficient from the geometric-mean viscosity and the pillar
+spreading factor (Eq. 1), the point-dipole DEP force of a strip electrode (Eqs. 2-4), the
+equation of motion (Eq. 5), its quasi-steady transport time (Eqs. 6-7), and fits of the drag
+coefficient and the force-balance factor to a trajectory.
+
+This is host-side modelling in numpy/scipy on scalars; it does not touch the lattice.  Units are
+whatever the caller uses consistently (lattice units for trajectories of this package's
+simulations).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def spreading_ratio(gamma_og, gamma_wg, gamma_ow, theta_os, theta_ws):
+    """I_os(w) / I_s (text before Eq. 1): the spreading coefficient of lubricant on the pillars
+    in the presence of the droplet, I_os(w) = gamma_og cos(theta_os) - gamma_wg cos(theta_ws)
+    - gamma_ow, over the reference I_s = -gamma_ow.  Angles in radians; o = lubricant (oil),
+    w = droplet (water), g = ambient gas."""
+    i_osw = gamma_og * math.cos(theta_os) - gamma_wg * math.cos(theta_ws) - gamma_ow
+    return i_osw / (-gamma_ow)
+
+
+def effective_viscosity(mu_w, mu_o, mu_g):
+    """Geometric mean of the three phases' dynamic viscosities (text before Eq. 1)."""
+    return (mu_w * mu_o * mu_g) ** (1.0 / 3.0)
+
+
+def drag_coefficient(c_alpha, ratio, mu_bar, mu_o):
+    """Eq. 1b: C_drag = C_alpha (1 + 1.5 ratio^2) mu_bar / mu_o, ratio = I_os(w) / I_s.  The
+    relation holds in the paper's mobile regime 0 < ratio < 0.8; above 0.8 the droplet is pinned
+    and below 0 the drag no longer depends on the wettability (ratio is then taken as 0)."""
+    r = max(ratio, 0.0)
+    return c_alpha * (1.0 + 1.5 * r * r) * mu_bar / mu_o
+
+
+def drag_force_scaled(c_drag, r0, l_c, ca):
+    """Eq. 1a: F_drag / (2 gamma_ow R0) = 3.5 pi C_drag (R0 / l_c)^0.5 Ca.  The length l_c is not
+    defined in the text; the caller supplies it."""
+    return 3.5 * math.pi * c_drag * math.sqrt(r0 / l_c) * ca
+
+
+def dep_factor(eps_w, r0, sigma_w, sigma_o, reading="clausius-mossotti"):
+    """K_e of Eq. 2 for a sphere of radius r0 and permittivity eps_w.  The printed denominator
+    is sigma_w - 2 sigma_o; the DC Clausius-Mossotti factor of a dipole has sigma_w + 2 sigma_o.
+    reading="clausius-mossotti" (default) takes the latter, reading="printed" the former; for
+    sigma_w >> sigma_o (the paper's regime) both tend to 2 pi eps_w r0^3, and the free factor
+    Lambda of Eq. 5 absorbs what is left."""
+    if reading == "clausius-mossotti":
+        den = sigma_w + 2.0 * sigma_o
+    elif reading == "printed":
+        den = sigma_w - 2.0 * sigma_o
+    else:
+        raise ValueError(f"unknown reading {reading!r}")
+    return 2.0 * math.pi * eps_w * r0 ** 3 * (sigma_w - sigma_o) / den
+
+
+def strip_constants(phi0, h_e, l_e):
+    """Eq. 4: decay rate alpha0 = pi / (2 (h_e + l_e)) of the strip's lowest Laplace mode
+    sin(alpha0 y) (grounded at y = 0, insulating at y = h_e + l_e), the integrals J_N (over the
+    insulating part 0..l_e of the electrode wall) and J_D (over the electrode part l_e..h_e + l_e)
+    of sin^2(alpha0 y), and the amplitude C_ele of the squared field's decay."""
+    a0 = math.pi / (2.0 * (h_e + l_e))
+    s2 = math.sin(2.0 * a0 * l_e) / (4.0 * a0)
+    j_n = l_e / 2.0 - s2
+    j_d = h_e / 2.0 + s2
+    c_ele = 2.0 * a0 * phi0 ** 2 * math.cos(a0 * l_e) ** 2 / (j_d + a0 * j_n) ** 2
+    return dict(alpha0=a0, J_N=j_n, J_D=j_d, C_ele=c_ele)
+
+
+def electric_force(k_e, c_ele, alpha0, s_e):
+    """Eq. 3: DEP force K_e C_ele exp(-2 alpha0 S_e) at droplet-electrode distance s_e."""
+    return k_e * c_ele * math.exp(-2.0 * alpha0 * s_e)
+
+
+def _rhs(state, m, drag, drive, alpha0, s0):
+    s, v = state
+    return np.array([v, (-drag * v + drive * math.exp(-2.0 * alpha0 * (s0 - s))) / m])
+
+
+def integrate_motion(t_end, m, c_drag, r0, mu_bar, drive, alpha0, s0, v0=0.0, n_steps=20000, t_out=None):
+    """Eq. 5, m S'' = -C_drag 2 R0 mu_bar S' + drive exp(-2 alpha0 (S0 - S)) with drive =
+    Lambda K_e C_ele, from S(0) = 0, S'(0) = v0, by classical fourth-order Runge-Kutta with
+    n_steps equal steps.  Returns (t, S, V) at the step times, or at t_out (sorted, within
+    [0, t_end]) by cubic Hermite interpolation of the steps."""
+    drag = 2.0 * c_drag * r0 * mu_bar
+    h = t_end / n_steps
+    ts = np.linspace(0.0, t_end, n_steps + 1)
+    y = np.empty((n_steps + 1, 2))
+    y[0] = (0.0, v0)
+    for i in range(n_steps):
+        yi = y[i]
+        k1 = _rhs(yi, m, drag, drive, alpha0, s0)
+        k2 = _rhs(yi + 0.5 * h * k1, m, drag, drive, alpha0, s0)
+        k3 = _rhs(yi + 0.5 * h * k2, m, drag, drive, alpha0, s0)
+        k4 = _rhs(yi + h * k3, m, drag, drive, alpha0, s0)
+        y[i + 1] = yi + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    if t_out is None:
+        return ts, y[:, 0], y[:, 1]
+    t_out = np.asarray(t_out, dtype=np.float64)
+    idx = np.clip(np.searchsorted(ts, t_out, side="right") - 1, 0, n_steps - 1)
+    u = (t_out - ts[idx]) / h
+    s_a, s_b, v_a, v_b = y[idx, 0], y[idx + 1, 0], y[idx, 1], y[idx + 1, 1]
+    h00, h10, h01, h11 = 2 * u**3 - 3 * u**2 + 1, u**3 - 2 * u**2 + u, -2 * u**3 + 3 * u**2, u**3 - u**2
+    s = h00 * s_a + h10 * h * v_a + h01 * s_b + h11 * h * v_b
+    v = v_a + u * (v_b - v_a)
+    return t_out, s, v
+
+
+def transport_time(s_t, m, c_drag, r0, mu_bar, drive, alpha0, s0, inertia=True):
+    """Eq. 7: time to travel s_t from rest, from the quasi-steady slope of Eq. 6 (the velocity at
+    which drag balances the force, plus the first-order inertial lag 2 alpha0 tau_v with
+    tau_v = m / (2 C_drag R0 mu_bar)).  inertia=False drops the second term."""
+    cr = r0 * mu_bar * c_drag
+    t = cr / (alpha0 * drive) * (math.exp(2.0 * alpha0 * s0) - math.exp(2.0 * alpha0 * (s0 - s_t)))
+    if inertia:
+        t += alpha0 * m / cr * s_t
+    return t
+
+
+def average_velocity(s_t, *args, **kw):
+    """V_avg = S_t / t(S_t) with t from Eq. 7 (same arguments as transport_time)."""
+    return s_t / transport_time(s_t, *args, **kw)
+
+
+def drag_from_deceleration(m, v0, r0, mu_bar, s_max):
+    """C_drag,sim = m V0 / (2 R0 mu_bar S_max): the drag coefficient that stops a droplet
+    launched at V0 after S_max under linear drag alone (Eq. 5 without the electric term)."""
+    return m * v0 / (2.0 * r0 * mu_bar * s_max)
+
+
+def fit_motion(t, s, m, r0, mu_bar, alpha0, s0, guess=(1.0, 1.0), n_steps=4000):
+    """Least-squares fit of (C_drag, drive = Lambda K_e C_ele) of Eq. 5 to a trajectory S(t)
+    that starts from rest at t[0] = 0 (S measured from the start).  Both parameters are fitted
+    in logarithms, so they stay positive.  Returns dict(c_drag, drive, rms)."""
+    from scipy.optimize import least_squares
+
+    t = np.asarray(t, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    scale = max(float(np.max(np.abs(s))), 1e-300)
+
+    def resid(p):
+        c, d = math.exp(p[0]), math.exp(p[1])
+        _, sm, _ = integrate_motion(float(t[-1]), m, c, r0, mu_bar, d, alpha0, s0, n_steps=n_steps, t_out=t)
+        return (sm - s) / scale
+
+    res = least_squares(resid, np.log(np.asarray(guess, dtype=np.float64)), method="lm", xtol=1e-14,
+                        ftol=1e-14, gtol=1e-14)
+    c, d = (float(math.exp(x)) for x in res.x)
+    return dict(c_drag=c, drive=d, rms=float(np.sqrt(np.mean(res.fun ** 2))) * scale)
