@@ -62,7 +62,9 @@ def strip_constants(phi0, h_e, l_e):
     """Eq. 4: decay rate alpha0 = pi / (2 (h_e + l_e)) of the strip's lowest Laplace mode
     sin(alpha0 y) (grounded at y = 0, insulating at y = h_e + l_e), the integrals J_N (over the
     insulating part 0..l_e of the electrode wall) and J_D (over the electrode part l_e..h_e + l_e)
-    of sin^2(alpha0 y), and the amplitude C_ele of the squared field's decay."""
+    of sin^2(alpha0 y), and the amplitude C_ele of the squared field's decay.  alpha0, J_N and
+    J_D follow from the mode itself; C_ele comes from a derivation given outside the main text
+    and is checked only through its phi0^2 scaling (parity unpinned)."""
     a0 = math.pi / (2.0 * (h_e + l_e))
     s2 = math.sin(2.0 * a0 * l_e) / (4.0 * a0)
     j_n = l_e / 2.0 - s2
