@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Dims d, const uint8_t* __restri
 
 // ----------------------------------------------------------------------------- block reductions
 template <int K, bool MAX>
-__device__ __forceinline__ void block_reduce(double (&v)[K], double* __restrict__ out) {
+__device__ __forceinline__ void block_reduce(double (&v)[K], double* __restrict__ out, int64_t ostride = 1) {
   __shared__ double sm[kBlock / 64][K];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -264,7 +264,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[K], double* __restrict_
   if (threadIdx.x < K) {
     double x = sm[0][threadIdx.x];
     for (int w = 1; w < kBlock / 64; ++w) x = MAX ? fmax(x, sm[w][threadIdx.x]) : x + sm[w][threadIdx.x];
-    out[threadIdx.x] = x;
+    out[threadIdx.x * ostride] = x;
   }
 }
 
@@ -283,9 +283,10 @@ __global__ __launch_bounds__(kBlock) void k_final(const double* __restrict__ par
 }
 
 // k_final for many partial rows: 1024 threads, fixed order (thread t sums rows t, t + 1024, ...,
-// then a fixed tree over the 16 waves).
+// then a fixed tree over the 16 waves).  Row b, entry k is part[b * K + k], or part[k * nblk + b]
+// with COLS (partials stored entry by entry, so a wave's loads of one entry are contiguous).
 constexpr int kFinalWide = 1024;
-template <int K, bool MAX>
+template <int K, bool MAX, bool COLS = false>
 __device__ __forceinline__ void final_wide(const double* __restrict__ part, int nblk, double* __restrict__ out) {
   __shared__ double sm[kFinalWide / 64][K];
   double v[K];
@@ -293,7 +294,10 @@ __device__ __forceinline__ void final_wide(const double* __restrict__ part, int 
   for (int k = 0; k < K; ++k) v[k] = MAX ? -INFINITY : 0.0;
   for (int b = threadIdx.x; b < nblk; b += kFinalWide) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = MAX ? fmax(v[k], part[(int64_t)b * K + k]) : v[k] + part[(int64_t)b * K + k];
+    for (int k = 0; k < K; ++k) {
+      const double p = COLS ? part[(int64_t)k * nblk + b] : part[(int64_t)b * K + k];
+      v[k] = MAX ? fmax(v[k], p) : v[k] + p;
+    }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -1280,7 +1284,8 @@ struct ProjVecs {
 template <int M>
 constexpr int proj_sums() { return M * (M + 1) / 2 + M; }
 
-// per-block FP64 partials of G (upper triangle, row-major) and g; also keep <- h_1
+// per-block FP64 partials of G (upper triangle, row-major) and g, entry k of block b at
+// part[k * blocks + b]; also keep <- h_1
 template <int D, class T, int M>
 __global__ __launch_bounds__(kBlock) void k_proj_gram(Level L, const T* __restrict__ cp, const T* __restrict__ diag,
                                                       const T* __restrict__ b, ProjVecs<T, M> h, int m,
@@ -1341,7 +1346,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_gram(Level L, const T* __restri
 #pragma unroll
     for (int r = 0; r < M; ++r) acc[k++] += u[r] * bi;
   }
-  block_reduce<P, false>(acc, part + (int64_t)blockIdx.x * P);
+  block_reduce<P, false>(acc, part + blockIdx.x, gridDim.x);  // entry k of block b at part[k * blocks + b]
 }
 
 // G c = g from the sums s (upper triangle of G row-major, then g) for the first m vectors
@@ -1403,7 +1408,7 @@ __global__ __launch_bounds__(kFinalWide) void k_proj_solve(const double* __restr
                                                            ProjVecs<T, M> h, double* __restrict__ coef) {
   constexpr int P = proj_sums<M>();
   __shared__ double s[P];
-  final_wide<P, false>(part, nblk, s);
+  final_wide<P, false, true>(part, nblk, s);
   __syncthreads();
   if (threadIdx.x != 0) return;
   double c[M];
