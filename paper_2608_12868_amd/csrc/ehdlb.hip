@@ -1024,9 +1024,9 @@ __global__ void k_vacc_add(const double* __restrict__ red, double* __restrict__ 
 template <class LT, class T, bool EHD>
 static ehdlb_status step_record(ehdlb_ctx* c, T* rec) {
   using RL = RecLayout<LT>;
+  static_assert(3 + 3 + LT::D + 2 <= kMaxRows, "record rows exceed the row-copy kernel's capacity");
   hipStream_t s = c->stream;
   const int64_t N = c->N;
-  const size_t ts = sizeof(T);
   const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
   const Phys<T> ph = make_phys<T>(c->prm);
   const uint8_t* flags = c->ptr<uint8_t>(c->off_flags);
@@ -1044,14 +1044,25 @@ static ehdlb_status step_record(ehdlb_ctx* c, T* rec) {
     hipLaunchKernelGGL(k_ghosts<T>, dim3(nblocks(G)), dim3(kBlock), 0, s, N, G, c->ptr<int32_t>(c->off_gnode),
                        c->ptr<int32_t>(c->off_gsrc), c->ptr<T>(c->off_glen), phi, ph);
   LAUNCHCHK();
-  // record copies that do not depend on the potential come before the solve
-  HIPCHK(hipMemcpyAsync(rec + (size_t)RL::PHI * N, phi, 3 * N * ts, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(rec + (size_t)RL::PHIP * N, c->ptr<T>(c->off_phi[pp]), 3 * N * ts, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(rec + (size_t)RL::UP * N, c->ptr<T>(c->off_u[pp]), (size_t)LT::D * N * ts,
-                        hipMemcpyDeviceToDevice, s));
-  if (EHD) {
-    HIPCHK(hipMemcpyAsync(rec + (size_t)RL::RHO * N, rho, N * ts, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(rec + (size_t)RL::RHOP * N, c->ptr<T>(c->off_rho[pp]), N * ts, hipMemcpyDeviceToDevice, s));
+  // the record's fields that do not depend on the potential, in one pass before the solve
+  {
+    RowCopy<T> rc{};
+    int j = 0;
+    auto row = [&](const T* src, size_t slot) {
+      rc.src[j] = src;
+      rc.dst[j] = rec + slot * N;
+      ++j;
+    };
+    for (int k = 0; k < 3; ++k) row(phi + k * N, RL::PHI + k);
+    for (int k = 0; k < 3; ++k) row(c->ptr<T>(c->off_phi[pp]) + k * N, RL::PHIP + k);
+    for (int d = 0; d < LT::D; ++d) row(c->ptr<T>(c->off_u[pp]) + d * N, RL::UP + d);
+    if (EHD) {
+      row(rho, RL::RHO);
+      row(c->ptr<T>(c->off_rho[pp]), RL::RHOP);
+    }
+    rc.nrows = j;
+    hipLaunchKernelGGL(k_copy_rows<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, N, rc);
+    LAUNCHCHK();
   }
   StepArgs<T> a{};
   a.d = dm;

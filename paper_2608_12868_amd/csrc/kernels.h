@@ -1444,6 +1444,29 @@ __global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t N, T* __restrict
   older[i] = v;
 }
 
+// Rows of N values copied in one pass, dst[j][i] = src[j][i] for j < nrows (the adjoint
+// recompute's record of the fields that do not depend on the potential: three phase fields, the
+// previous step's phase fields and velocity, rho_e and the previous rho_e)
+constexpr int kMaxRows = 12;
+template <class T>
+struct RowCopy {
+  const T* src[kMaxRows];
+  T* dst[kMaxRows];
+  int nrows;
+};
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_copy_rows(int64_t N, RowCopy<T> rc) {
+  const int64_t i = gidx();
+  if (i >= N) return;
+  T v[kMaxRows];
+#pragma unroll
+  for (int j = 0; j < kMaxRows; ++j)
+    if (j < rc.nrows) v[j] = rc.src[j][i];
+#pragma unroll
+  for (int j = 0; j < kMaxRows; ++j)
+    if (j < rc.nrows) rc.dst[j][i] = v[j];
+}
+
 // dst = src when *gate != 0 (a copy queued behind a solve, done only once it has stopped)
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_copy_gated(const int* __restrict__ gate, int64_t N,
