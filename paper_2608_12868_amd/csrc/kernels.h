@@ -283,10 +283,9 @@ __global__ __launch_bounds__(kBlock) void k_final(const double* __restrict__ par
 }
 
 // k_final for many partial rows: 1024 threads, fixed order (thread t sums rows t, t + 1024, ...,
-// then a fixed tree over the 16 waves).  Row b, entry k is part[b * K + k], or part[k * nblk + b]
-// with COLS (partials stored entry by entry, so a wave's loads of one entry are contiguous).
+// then a fixed tree over the 16 waves).  Row b, entry k is part[b * K + k].
 constexpr int kFinalWide = 1024;
-template <int K, bool MAX, bool COLS = false>
+template <int K, bool MAX>
 __device__ __forceinline__ void final_wide(const double* __restrict__ part, int nblk, double* __restrict__ out) {
   __shared__ double sm[kFinalWide / 64][K];
   double v[K];
@@ -294,10 +293,7 @@ __device__ __forceinline__ void final_wide(const double* __restrict__ part, int 
   for (int k = 0; k < K; ++k) v[k] = MAX ? -INFINITY : 0.0;
   for (int b = threadIdx.x; b < nblk; b += kFinalWide) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const double p = COLS ? part[(int64_t)k * nblk + b] : part[(int64_t)b * K + k];
-      v[k] = MAX ? fmax(v[k], p) : v[k] + p;
-    }
+    for (int k = 0; k < K; ++k) v[k] = MAX ? fmax(v[k], part[(int64_t)b * K + k]) : v[k] + part[(int64_t)b * K + k];
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -317,6 +313,33 @@ __device__ __forceinline__ void final_wide(const double* __restrict__ part, int 
     out[threadIdx.x] = x;
   }
 }
+// Sums of K entries over nblk partial rows stored entry by entry (entry k of row b at
+// part[k * nblk + b]), with 1024 threads: wave w reduces entries w, w + 16, ...; lane l adds rows
+// l, l + 64, ... in that order (sixteen independent loads at a time), then a fixed shuffle tree.
+// Each wave runs one short tree per entry instead of every wave running one per entry.
+template <int K>
+__device__ __forceinline__ void final_cols(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+  constexpr int kWaves = kFinalWide / 64, kRun = 16;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k = wv; k < K; k += kWaves) {
+    const double* col = part + (int64_t)k * nblk;
+    double x = 0.0;
+    for (int base = 0; base < nblk; base += 64 * kRun) {
+      double v[kRun];
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) {
+        const int b = base + lane + 64 * j;
+        v[j] = b < nblk ? col[b] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) x += v[j];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) out[k] = x;
+  }
+}
+
 template <int K, bool MAX>
 __global__ __launch_bounds__(kFinalWide) void k_final_wide(const double* __restrict__ part, int nblk,
                                                             double* __restrict__ out) {
@@ -1408,7 +1431,7 @@ __global__ __launch_bounds__(kFinalWide) void k_proj_solve(const double* __restr
                                                            ProjVecs<T, M> h, double* __restrict__ coef) {
   constexpr int P = proj_sums<M>();
   __shared__ double s[P];
-  final_wide<P, false, true>(part, nblk, s);
+  final_cols<P>(part, nblk, s);
   __syncthreads();
   if (threadIdx.x != 0) return;
   double c[M];
