@@ -1235,7 +1235,7 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(const CgCtl* __restrict__
     r[i] = (T)res;
     m[0] = fmax(m[0], fabs(res));
   }
-  block_reduce<3, true>(m, part + (int64_t)blockIdx.x * 3);
+  block_reduce<3, true>(m, part + blockIdx.x, gridDim.x);  // entry k of block b at part[k * blocks + b]
 }
 
 // Convergence decision from the true-residual partials (one block).  init != 0: the check
@@ -1251,12 +1251,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_judge(CgCtl* __restrict__ ctl, co
     if (ctl->stop) return;
     if (!cg_trigger(ctl, pmax, nblk, tol, force)) return;
   }
-  double v[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int b = threadIdx.x; b < nblk; b += kBlock)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] = fmax(v[k], ptrue[(int64_t)b * 3 + k]);
+  // entry k of block b at ptrue[k * nblk + b]; wave k (of four) takes the maximum of entry k
+  static_assert(kBlock / 64 >= 3, "one wave per entry");
   __shared__ double out[3];
-  block_reduce<3, true>(v, out);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (wv < 3) {
+    const double* col = ptrue + (int64_t)wv * nblk;
+    double x = -INFINITY;
+    for (int base = 0; base < nblk; base += 64 * 16) {
+      double v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int b = base + lane + 64 * j;
+        v[j] = b < nblk ? col[b] : -INFINITY;
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) x = fmax(x, v[j]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+    if (lane == 0) out[wv] = x;
+  }
   __syncthreads();
   if (threadIdx.x != 0) return;
   const double bmax = out[1];
