@@ -204,8 +204,10 @@ int64_t ehdlb_wetting_links(const ehdlb_ctx* ctx, int64_t* nodes, int32_t* dirs,
  *   recomputes K steps storing their records, and runs the adjoint steps
  *   backwards; the potential solve is differentiated as exact (one solve with
  *   the same symmetric matrix per step).  Deterministic; ends at the final
- *   state again.  ESTATE if the state moved since the checkpointed forward,
- *   EINVAL if the field is off. */
+ *   state again.  ESTATE if anything that changes the state or the steps was
+ *   called since the checkpointed forward (ehdlb_generation differs: set_geometry,
+ *   set_phase, set_charge, set_schedule, set_solver_options, step with n > 0,
+ *   load_state, another forward_checkpointed), EINVAL if the field is off. */
 size_t ehdlb_adjoint_workspace_bytes(const ehdlb_ctx* ctx, int64_t T, int32_t K);
 ehdlb_status ehdlb_forward_checkpointed(ehdlb_ctx* ctx, int64_t T, int32_t K, void* device_workspace,
                                         size_t bytes);
@@ -251,6 +253,13 @@ ehdlb_status ehdlb_timing(ehdlb_ctx* ctx, double* ms3, int64_t* steps);
  * gradient iterations, max_rel0[k] the largest initial relative residual max|b - A x0|/max|b|
  * of the warm start.  counts: int64[4], max_rel0: double[2] (host, either may be NULL). */
 ehdlb_status ehdlb_solver_stats(ehdlb_ctx* ctx, int32_t reset, int64_t* counts, double* max_rel0);
+
+/* Forward generation of the context: a counter bumped by every call that changes
+ * the state or what the next steps compute (set_geometry, set_phase, set_charge,
+ * set_schedule, set_solver_options, step with n > 0, load_state,
+ * forward_checkpointed).  A caller that holds a checkpointed forward (for
+ * example an autograd node) records it and checks it before ehdlb_adjoint. */
+uint64_t ehdlb_generation(const ehdlb_ctx* ctx);
 
 const char* ehdlb_last_error(const ehdlb_ctx* ctx);
 void ehdlb_destroy(ehdlb_ctx* ctx);

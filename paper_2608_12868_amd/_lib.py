@@ -78,6 +78,7 @@ SIGNATURES = {
     "ehdlb_solver_stats": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "ehdlb_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "ehdlb_timing": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ehdlb_generation": (C.c_uint64, [C.c_void_p]),
     "ehdlb_last_error": (C.c_char_p, [C.c_void_p]),
     "ehdlb_destroy": (None, [C.c_void_p]),
 }

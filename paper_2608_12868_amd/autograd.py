@@ -17,6 +17,7 @@ class ScheduleToObservables(torch.autograd.Function):
         sim.forward_checkpointed(T, K)
         ob = sim.observables()
         ctx.sim, ctx.electrode, ctx.n_seg = sim, electrode, v.size
+        ctx.generation = sim.generation
         return (torch.tensor(ob["centroid"], dtype=torch.float64),
                 torch.tensor(ob["velocity"], dtype=torch.float64))
 
@@ -24,6 +25,9 @@ class ScheduleToObservables(torch.autograd.Function):
     def backward(ctx, g_centroid, g_velocity):
         gx = np.zeros(3) if g_centroid is None else g_centroid.detach().cpu().double().numpy()
         gv = np.zeros(3) if g_velocity is None else g_velocity.detach().cpu().double().numpy()
+        if ctx.sim.generation != ctx.generation:
+            raise RuntimeError("the simulation was changed or run again after this forward: its "
+                               "checkpoints no longer belong to this graph node")
         g = ctx.sim.adjoint(gx, gv, ctx.electrode, ctx.n_seg)
         return torch.from_numpy(g), None, None, None, None, None, None
 

@@ -82,6 +82,10 @@ struct ehdlb_ctx {
   int64_t t = 0;
   int cur = 0;
   int sticky = 0;
+  // forward generation: bumped by every public call that changes the state or what a step
+  // computes (set_geometry, set_phase, set_charge, set_schedule, set_solver_options, step with
+  // n > 0, load_state); the checkpointed forward records it and the adjoint requires it unchanged
+  uint64_t gen = 0;
   double last_resid = 0.0, last_resid0 = 0.0;
   int last_iters = 0;
   // iteration counts of the last potential solves of each kind (0: forward, 1: adjoint): they
@@ -125,6 +129,7 @@ struct ehdlb_ctx {
     size_t lgr = 0, llap = 0, lsig = 0, lpnb = 0, lphi_loc = 0, lpot_loc = 0, lrho_loc = 0, lmom = 0;
     size_t lphi = 0, lpot = 0, lb = 0, lbr[kProjAdj]{}, vpart = 0, vred = 0, vacc = 0, obs = 0, total = 0, rec_stride = 0;
     int nvseg = 0;
+    uint64_t gen = 0;  // forward generation at the end of the checkpointed forward
   } adj;
   // potential-solver options (ehdlb_set_solver_options): degree-2 Chebyshev smoothing of the
   // Jacobi-preconditioned operator on [lo, hi], coarse-correction scale
@@ -965,6 +970,8 @@ static ehdlb_status upload_geometry(ehdlb_ctx* c) {
 }
 
 // ============================================================================ adjoint
+static ehdlb_status load_state_impl(ehdlb_ctx* c, const void* src);
+
 static int rec_count(const ehdlb_ctx* c) {
   return c->D == 2 ? RecLayout<D2Q9>::COUNT : RecLayout<D3Q19>::COUNT;
 }
@@ -1248,7 +1255,7 @@ struct AdjFn {
     const auto& sch = c->sched[electrode];
     const int nseg = sch.v.empty() ? 1 : (int)sch.v.size();
     for (int j = J.nck - 1; j >= 0; --j) {
-      if ((st = ehdlb_load_state(c, J.ws + J.ckpt + (size_t)j * align_up(c->state_bytes)))) return st;
+      if ((st = load_state_impl(c, J.ws + J.ckpt + (size_t)j * align_up(c->state_bytes)))) return st;
       const int64_t ta = J.t0 + (int64_t)j * J.K;
       const int64_t tb = std::min<int64_t>(ta + J.K, J.t0 + J.T);
       for (int64_t t = ta; t < tb; ++t)
@@ -1272,7 +1279,7 @@ struct AdjFn {
     HIPCHK(hipStreamSynchronize(s));
     for (int k = 0; k < nseg; ++k) out[k] = h[(size_t)electrode * J.nvseg + k];
     // back to the final state of the checkpointed forward
-    return ehdlb_load_state(c, J.ws + J.fin);
+    return load_state_impl(c, J.ws + J.fin);
   }
 };
 
@@ -1444,6 +1451,7 @@ ehdlb_status ehdlb_set_geometry(ehdlb_ctx* c, const uint8_t* flags) {
     c->src_start.push_back((int32_t)G);
   }
   c->flags.assign(flags, flags + N);
+  ++c->gen;
   c->have_geometry = true;
   c->have_state = false;
   c->adj.ready = false;
@@ -1466,6 +1474,7 @@ ehdlb_status ehdlb_set_phase(ehdlb_ctx* c, const double* phi) {
     if ((st = upload<float>(c, phi, 3 * N, c->ptr<float>(c->off_phi[1])))) return st;
     if ((st = upload<float>(c, zero.data(), N, c->ptr<float>(c->off_rho[1])))) return st;
   }
+  ++c->gen;
   c->t = 0;
   c->hier_t = -1;
   c->cur = 0;
@@ -1483,6 +1492,7 @@ ehdlb_status ehdlb_set_charge(ehdlb_ctx* c, const double* rho) {
   if (!rho) return fail(c, EHDLB_EINVAL, "null charge array");
   if (!c->have_state || c->t != 0) return fail(c, EHDLB_ESTATE, "set_charge needs a fresh set_phase");
   if (!c->ehd) return fail(c, EHDLB_EINVAL, "set_charge with the field off");
+  ++c->gen;
   // the initial fields sit in the t = -1 slots; replace the charge there and rebuild
   ehdlb_status st;
   if (c->tsize == 8) {
@@ -1498,6 +1508,7 @@ ehdlb_status ehdlb_set_charge(ehdlb_ctx* c, const double* rho) {
 ehdlb_status ehdlb_set_schedule(ehdlb_ctx* c, int32_t k, int32_t n_seg, const double* volts, int64_t t_total) {
   if (!c) return EHDLB_EINVAL;
   if (k < 0 || k >= EHDLB_MAX_ELECTRODES) return fail(c, EHDLB_EINVAL, "electrode index out of range");
+  ++c->gen;
   if (n_seg == 0) {
     c->sched[k].v.clear();
     return EHDLB_OK;
@@ -1512,6 +1523,7 @@ ehdlb_status ehdlb_step(ehdlb_ctx* c, int64_t n) {
   if (!c) return EHDLB_EINVAL;
   if (n < 0) return fail(c, EHDLB_EINVAL, "negative step count");
   if (!c->have_state) return fail(c, EHDLB_ESTATE, "step before set_phase");
+  if (n > 0) ++c->gen;
   return dispatch<StepFn>(c, n);
 }
 
@@ -1609,6 +1621,13 @@ ehdlb_status ehdlb_save_state(ehdlb_ctx* c, void* dst) {
 
 ehdlb_status ehdlb_load_state(ehdlb_ctx* c, const void* src) {
   if (!c) return EHDLB_EINVAL;
+  ++c->gen;
+  return load_state_impl(c, src);
+}
+
+}  // extern "C"
+
+static ehdlb_status load_state_impl(ehdlb_ctx* c, const void* src) {
   if (!src) return fail(c, EHDLB_EINVAL, "null source");
   if (!c->bound || !c->have_geometry) return fail(c, EHDLB_ESTATE, "load_state before bind/set_geometry");
   const char* s = (const char*)src;
@@ -1628,6 +1647,8 @@ ehdlb_status ehdlb_load_state(ehdlb_ctx* c, const void* src) {
   c->have_state = true;
   return EHDLB_OK;
 }
+
+extern "C" {
 
 int64_t ehdlb_wetting_links(const ehdlb_ctx* c, int64_t* nodes, int32_t* dirs, int64_t cap) {
   if (!c) return EHDLB_EINVAL;
@@ -1659,8 +1680,10 @@ ehdlb_status ehdlb_forward_checkpointed(ehdlb_ctx* c, int64_t T, int32_t K, void
   a.bytes = bytes;
   a.t0 = c->t;
   c->adj = a;
+  ++c->gen;
   ehdlb_status st = dispatch<FwdCkptFn>(c, 0);
   if (st) return st;
+  c->adj.gen = c->gen;
   c->adj.ready = true;
   return EHDLB_OK;
 }
@@ -1673,7 +1696,8 @@ ehdlb_status ehdlb_adjoint(ehdlb_ctx* c, const double* dL_dcentroid, const doubl
   if (!c->ehd) return fail(c, EHDLB_EINVAL, "adjoint with respect to voltages needs the field on");
   if (!c->adj.ready) return fail(c, EHDLB_ESTATE, "adjoint before forward_checkpointed");
   if (c->sched[electrode].v.size() > (size_t)c->adj.nvseg) return fail(c, EHDLB_EINVAL, "too many schedule segments");
-  if (c->t != c->adj.t0 + c->adj.T) return fail(c, EHDLB_ESTATE, "state moved since forward_checkpointed");
+  if (c->gen != c->adj.gen || c->t != c->adj.t0 + c->adj.T)
+    return fail(c, EHDLB_ESTATE, "state or schedule changed since forward_checkpointed");
   return dispatch<AdjFn>(c, dL_dcentroid, dL_dvelocity, (int)electrode, dL_dvolts);
 }
 
@@ -1683,6 +1707,7 @@ ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* c, double lo, double hi, double
   if (!(lo > 0.0 && hi > lo && hi <= 2.0)) return fail(c, EHDLB_EINVAL, "need 0 < lo < hi <= 2");
   if (!(overcorrect > 0.0 && overcorrect <= 4.0)) return fail(c, EHDLB_EINVAL, "over-correction must lie in (0, 4]");
   if (warm_start < 0 || warm_start > 3) return fail(c, EHDLB_EINVAL, "warm_start must be 0, 1, 2 or 3");
+  ++c->gen;
   c->mg_lo = lo;
   c->mg_hi = hi;
   c->mg_overcorrect = overcorrect;
@@ -1727,6 +1752,8 @@ ehdlb_status ehdlb_solver_stats(ehdlb_ctx* c, int32_t reset, int64_t* counts, do
   }
   return EHDLB_OK;
 }
+
+uint64_t ehdlb_generation(const ehdlb_ctx* c) { return c ? c->gen : 0; }
 
 const char* ehdlb_last_error(const ehdlb_ctx* c) { return c ? c->err.c_str() : "null context"; }
 

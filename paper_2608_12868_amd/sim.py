@@ -4,6 +4,7 @@ PyTorch provides the device workspace (one uint8 tensor) and the stream; every
 step of the method runs in the library's HIP kernels.
 """
 import ctypes as C
+import weakref
 
 import numpy as np
 
@@ -48,13 +49,9 @@ class Context:
         if st != L.OK:
             raise L.EhdlbError(st, "ehdlb_create rejected the lattice or parameters")
         self.h = h
-
-    def __del__(self):
-        h = getattr(self, "h", None)
-        lib = L._LIB
-        if h and lib is not None:
-            lib.ehdlb_destroy(h)
-            self.h = None
+        # destroy the context when this object is collected, or at interpreter exit while the
+        # library and ctypes are still loaded (a __del__ could run after module teardown)
+        self._finalizer = weakref.finalize(self, L.lib().ehdlb_destroy, h)
 
     def _chk(self, st):
         return L.check(self.h, st)
@@ -73,6 +70,11 @@ class Context:
         dirs = np.zeros(n, np.int32)
         L.lib().ehdlb_wetting_links(self.h, nodes.ctypes.data, dirs.ctypes.data, n)
         return nodes, dirs
+
+    @property
+    def generation(self):
+        """Counter bumped by every call that changes the state or the steps (ehdlb_generation)."""
+        return int(L.lib().ehdlb_generation(self.h))
 
     @property
     def workspace_bytes(self):
