@@ -3,7 +3,10 @@ droplet R=40, electrode 0.05 lu): the droplet centroid and velocity every 100 st
 steps, and every field at 1000 steps on a fixed sample of 4096 nodes plus its per-field
 max-norm.  Calls only the oracle and the shared input generator.
 
-    python tests/golden/make_config2_oracle.py [--steps 20000]
+    python tests/golden/make_config2_oracle.py [--steps 20000] [--out PATH]
+
+The output is written to PATH (default: config2_oracle.json beside this script) every 1000
+steps; a run writing elsewhere leaves the stored reference untouched until it is copied over.
 """
 import argparse
 import json
@@ -25,6 +28,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--threads", type=int, default=6)
+    ap.add_argument("--out", default=os.path.join(HERE, "config2_oracle.json"))
     args = ap.parse_args()
     torch.set_num_threads(args.threads)
     case = make_case("c2")
@@ -36,7 +40,7 @@ def main():
     traj = []
     fields_1000 = None
     t0 = time.time()
-    path = os.path.join(HERE, "config2_oracle.json")
+    path = args.out
     for k in range(args.steps + 1):
         if k % 100 == 0:
             ob = o.observables(s)

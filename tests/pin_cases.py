@@ -124,3 +124,79 @@ def contact_angle(phi1_2d, wall_y=0.5, min_y=2.0):
     xc, yc, cc = np.linalg.lstsq(A, (P ** 2).sum(1), rcond=None)[0]
     R = math.sqrt(cc + xc * xc + yc * yc)
     return math.degrees(math.acos((wall_y - yc) / R)), R
+
+
+def lens(nx=160, ny=112, area=628.3185307179587, W=4.0, **p):
+    """A droplet (phase 1) at the flat interface between a lubricant layer (phase 2, below
+    y0 = ny/2) and the ambient (phase 3, above): a disc of the given area centred on the
+    interface, tanh profiles.  Periodic in x; walls at y = 0 and ny-1, each touched by one
+    phase only (so the wetting condition does not act)."""
+    n = (nx, ny, 1)
+    x, y, z = grid(n)
+    flags = np.zeros(nx * ny, np.uint8)
+    flags[y == 0] = GROUND
+    flags[y == ny - 1] = NEUMANN
+    y0 = ny / 2.0
+    r0 = np.sqrt(area / np.pi)
+    r = np.sqrt((x - nx / 2.0) ** 2 + (y - y0) ** 2)
+    p1 = 0.5 * (1 + np.tanh(2 * (r0 - r) / W))
+    below = 0.5 * (1 + np.tanh(2 * (y0 - y) / W))
+    p2 = (1 - p1) * below
+    phi = np.stack([p1, p2, 1 - p1 - p2])
+    phi[:, flags != FLUID] = 0
+    return n, (1, 0, 0), default_params(2, width=W, **p), flags, phi
+
+
+def contour_points(f, level=0.5):
+    """Crossings of the level set of a 2D field (rows y, columns x) along rows and columns,
+    by linear interpolation: an (n, 2) array of (x, y)."""
+    ny, nx = f.shape
+    pts = []
+    for yy in range(ny):
+        row = f[yy]
+        for xx in range(nx - 1):
+            a, b = row[xx], row[xx + 1]
+            if (a - level) * (b - level) < 0:
+                pts.append((xx + (level - a) / (b - a), yy))
+    for xx in range(nx):
+        col = f[:, xx]
+        for yy in range(ny - 1):
+            a, b = col[yy], col[yy + 1]
+            if (a - level) * (b - level) < 0:
+                pts.append((xx, yy + (level - a) / (b - a)))
+    return np.asarray(pts, dtype=np.float64)
+
+
+def fit_circle(P):
+    """Least-squares circle through the points P (n, 2): centre (xc, yc) and radius."""
+    import math
+    A = np.c_[2 * P[:, 0], 2 * P[:, 1], np.ones(len(P))]
+    xc, yc, cc = np.linalg.lstsq(A, (P ** 2).sum(1), rcond=None)[0]
+    return xc, yc, math.sqrt(cc + xc * xc + yc * yc)
+
+
+def lens_geometry(phi3d):
+    """Geometry of a lens of phase 1 at the 2-3 interface from the fields (3, ny, nx): the level
+    y0 of the 2-3 interface far from the lens (Phi_2 = Phi_3 in the 15 outermost columns on
+    each side), and circles fitted to the Phi_1 = 1/2 contour above (upper cap, in phase 3) and
+    below (lower cap, in phase 2) y0 +- 3.  Returns y0 and per cap: the angle between its chord
+    on y = y0 and its arc at the triple points (degrees, inside phase 1), its height and chord,
+    and its radius."""
+    import math
+    f1, f2, f3 = phi3d
+    ny, nx = f1.shape
+    lv = []
+    for c in list(range(0, 15)) + list(range(nx - 15, nx)):
+        d = f2[:, c] - f3[:, c]
+        for yy in range(ny - 1):
+            if d[yy] * d[yy + 1] < 0:
+                lv.append(yy + d[yy] / (d[yy] - d[yy + 1]))
+    y0 = float(np.mean(lv))
+    P = contour_points(f1)
+    out = dict(y0=y0)
+    for name, sel, sgn in (("upper", P[:, 1] > y0 + 3, 1.0), ("lower", P[:, 1] < y0 - 3, -1.0)):
+        xc, yc, r = fit_circle(P[sel])
+        d = sgn * (y0 - yc)                # distance of the centre behind the chord
+        out[name] = dict(angle=math.degrees(math.acos(d / r)), height=r - d,
+                         chord=2 * math.sqrt(r * r - d * d), radius=r)
+    return out

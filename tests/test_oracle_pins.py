@@ -367,3 +367,211 @@ def test_v12_charge_advection_diffusion():
           advance_ref)
     assert np.abs(ratio / ratio_ref - 1).max() < 1e-4
     assert np.abs(advance - advance_ref).max() < 1e-3
+
+
+# ---------------------------------------------------------------- V5 at tau != 1, 2D and 3D
+@pytest.mark.parametrize("dim,tau", [(2, 0.8), (2, 1.3), (3, 0.8), (3, 1.3)])
+def test_v5_poiseuille_tau_and_wall_location(dim, tau):
+    """Body-force channel flow away from tau = 1 (flow second-order moments at 1/tau, higher
+    moments at 1), walls normal to y (2D) or z (3D, D3Q19).  The steady profile is a parabola of
+    curvature -F/nu, nu = (tau - 1/2)/3, and with halfway bounce-back its zeros sit where the
+    two-relaxation-time analysis of bounce-back puts them: a channel of nominal width H between
+    the half-way planes behaves as one of width sqrt(H^2 + (16 Lambda - 3)/3), Lambda =
+    (tau_even - 1/2)(tau_odd - 1/2) = (tau - 1/2)/2 (Ginzburg, Verhaeghe & d'Humieres, Commun.
+    Comput. Phys. 3, 2008).  A second-order rate other than 1/tau moves the curvature, a
+    third-order rate other than 1 moves the zeros."""
+    from inputs import default_params
+    F, nw = 1e-6, 12
+    n = (4, nw, 1) if dim == 2 else (4, 4, nw)
+    x, y, z = pc.grid(n)
+    h = y if dim == 2 else z
+    flags = np.zeros(x.size, np.uint8)
+    flags[h == 0] = GROUND
+    flags[h == nw - 1] = NEUMANN
+    phi = np.zeros((3, x.size))
+    phi[2] = 1.0
+    phi[:, flags != FLUID] = 0
+    periodic = (1, 0, 0) if dim == 2 else (1, 1, 0)
+    params = default_params(dim, body_force=(F, 0.0, 0.0), tau_flow=(tau, tau, tau))
+    o, s, aux = _run((n, periodic, params, flags, phi), 2500)
+    u = aux["u"][0].numpy()
+    prof = np.array([u[(h == k) & (x == 0) & (y == 0 if dim == 3 else True)][0] for k in range(1, nw - 1)])
+    hh = np.arange(1, nw - 1, dtype=np.float64)
+    c = np.polyfit(hh, prof, 2)
+    nu = (tau - 0.5) / 3.0
+    assert abs(2 * c[0] / (-F / nu) - 1) < 1e-9
+    lam = (tau - 0.5) * 0.5
+    weff = math.sqrt((nw - 2) ** 2 + (16 * lam - 3) / 3)
+    roots = np.sort(np.roots(c).real)
+    mid = (nw - 1) / 2.0
+    assert np.abs(roots - np.array([mid - weff / 2, mid + weff / 2])).max() < 1e-9
+    assert float(aux["u"][1:].abs().max()) < 1e-18
+
+
+# ---------------------------------------------------------------- V3 lens (ternary)
+@pytest.mark.parametrize("tensions,steps", [((0.02, 0.02, 0.02), 2500), ((0.02, 0.028, 0.02), 4000)])
+def test_v3_lens_neumann_angles(tensions, steps):
+    """A droplet lens at a flat lubricant/ambient interface, with no wall involved (Eqs. 10-11,
+    18): at equilibrium its two caps are circular arcs meeting the straight 2-3 interface at the
+    angles of the Neumann triangle of the three tensions, gamma_jk^2 = gamma_ij^2 + gamma_ik^2 +
+    2 gamma_ij gamma_ik cos(theta_i) for the angle theta_i inside phase i, and the pressures
+    balance across both caps, gamma_13 / r_upper = gamma_12 / r_lower.  Equal tensions: 120
+    degrees in every phase, so each cap subtends 60 degrees at its chord; for the area of a
+    semicircle of radius 20 (628.3) each cap then has radius 22.62, chord 39.17, height 11.31.
+    gamma_13 = 1.4 gamma_12 = 1.4 gamma_23: 134.4 degrees in phases 1 and 3, 91.1 in phase 2, so
+    the upper cap meets the interface at 45.6 degrees and the lower at 88.9.  Tensions 0.02 lu
+    and tau = 1 relax the lens in about 2000 steps, with a capillary oscillation of about a
+    degree left at the step counts used (the cap angles carry a further ~2 degree diffuse-
+    interface bias when a cap is only ~1.7 W high)."""
+    g12, g13, g23 = tensions
+    case = pc.lens(nx=112, ny=96, gamma12=g12, gamma13=g13, gamma23=g23, mobility=0.05)
+    o, s, aux = _run(case, steps)
+    geo = pc.lens_geometry(o.fields(s)["phi"].numpy().reshape(3, 96, 112))
+    up, lo = geo["upper"], geo["lower"]
+    th = {}
+    for i, (a, b, c) in enumerate(((g12, g13, g23), (g12, g23, g13), (g13, g23, g12))):
+        th[i + 1] = math.degrees(math.acos((c * c - a * a - b * b) / (2 * a * b)))
+    assert abs(sum(th.values()) - 360.0) < 1e-9
+    print("lens", tensions, "angles upper/lower", up["angle"], lo["angle"], "expected", 180 - th[3], 180 - th[2],
+          "heights", up["height"], lo["height"], "chords", up["chord"], lo["chord"], "radii", up["radius"],
+          lo["radius"])
+    assert abs(up["angle"] - (180 - th[3])) < 5.0
+    assert abs(lo["angle"] - (180 - th[2])) < 5.0
+    assert abs(up["angle"] + lo["angle"] - th[1]) < 1.5          # the angle inside the lens
+    assert abs((up["radius"] / lo["radius"]) / (g13 / g12) - 1) < 0.03
+    if g12 == g13 == g23:
+        r = math.sqrt(628.3185307179587 / (2 * (math.pi / 3 - math.sin(math.pi / 3) * 0.5)))
+        for cap in (up, lo):
+            assert abs(cap["chord"] - 2 * r * math.sin(math.pi / 3)) < 2.0
+            assert abs(cap["height"] - r * (1 - 0.5)) < 2.0
+
+
+# ---------------------------------------------------------------- 3D closed forms
+def _column3d(nz, top=ELECTRODE0, layer=None, **p):
+    from inputs import default_params
+    n = (4, 4, nz)
+    x, y, z = pc.grid(n)
+    flags = np.zeros(x.size, np.uint8)
+    flags[z == 0] = GROUND
+    flags[z == nz - 1] = top
+    phi = np.zeros((3, x.size))
+    if layer is None:
+        phi[2] = 1.0
+    else:
+        phi[0] = (z < layer).astype(np.float64)
+        phi[2] = 1.0 - phi[0]
+    phi[:, flags != FLUID] = 0
+    return n, (1, 1, 0), default_params(3, **p), flags, phi, z
+
+
+def test_v6_capacitor_3d_layered():
+    """The 3D potential (the oracle's conjugate-gradient branch) between a grounded plate and an
+    electrode along z, permittivity 80 below z = 17 and 1 above: the series-resistance solution
+    of the discrete Gauss law (Eq. 13), with half-cell resistances at the Dirichlet faces."""
+    V, nz = 0.05, 34
+    n, per, p, fl, phi, z = _column3d(nz, layer=17, ehd=1, electrode_volts=(V, 0, 0, 0), cond=(0.0, 0.0, 0.0))
+    o, s, aux = _run((n, per, p, fl, phi), 1)
+    pot = aux["pot"].numpy()
+    col = np.array([pot[(z == k)][0] for k in range(nz)])
+    assert np.ptp(pot.reshape(nz, 16), axis=1).max() < 1e-16          # uniform in x and y
+    eps = np.where(np.arange(nz) < 17, 80.0, 1.0)
+    res = [1.0 / (2 * eps[1])]
+    for j in range(1, nz - 2):
+        res.append(1.0 / (0.5 * (eps[j] + eps[j + 1])))
+    res.append(1.0 / (2 * eps[nz - 2]))
+    cum = np.cumsum(res)
+    assert np.abs(col[1:-1] - V * cum[:-1] / cum[-1]).max() < 1e-13 * V
+
+
+def test_v9_coulomb_force_total_3d():
+    """Uniform charge between a grounded plate and an electrode along z: the face-mirrored
+    central-difference field sums to -V over a column, so rho0 E_z sums to -rho0 V (Eq. 12)."""
+    V, nz, rho0 = 0.03, 20, 2e-4
+    n, per, p, fl, phi, z = _column3d(nz, ehd=1, electrode_volts=(V, 0, 0, 0), cond=(0, 0, 0))
+    r0 = np.where(fl == FLUID, rho0, 0.0)
+    o, s, aux = _run((n, per, p, fl, phi), 1, rho0=r0)
+    Fz = aux["Fe"][2].numpy()
+    assert abs(Fz[(np.arange(Fz.size) % 16) == 5].sum() - (-rho0 * V)) < 1e-18
+    assert float(aux["Fe"][:2].abs().max()) < 1e-20
+
+
+def test_v1_flat_interface_3d():
+    """D3Q19: a sharp slab of phase 1 normal to z relaxes to the tanh profile of width W
+    (sum Phi(1 - Phi) = W/4 per interface, profile within 1e-2), with x and y uniform."""
+    W, nz = 4.0, 64
+    from inputs import default_params
+    n = (4, 4, nz)
+    x, y, z = pc.grid(n)
+    p1 = ((z >= 16) & (z < 48)).astype(np.float64)
+    phi = np.stack([p1, np.zeros_like(p1), 1 - p1])
+    params = default_params(3, width=W, mobility=0.1)
+    o, s, aux = _run((n, (1, 1, 1), params, np.zeros(x.size, np.uint8), phi), 1500)
+    f1 = o.fields(s)["phi"][0].numpy().reshape(nz, 16)
+    assert np.ptp(f1, axis=1).max() < 1e-14
+    col = f1[:, 0]
+    zz = np.arange(nz)
+    prof = 0.5 * (np.tanh(2 * (zz - 15.5) / W) - np.tanh(2 * (zz - 47.5) / W))
+    assert abs(np.sum(col * (1 - col)) - 2 * W / 4) < 1e-5 * W
+    assert np.abs(col - prof).max() < 1e-2
+
+
+# ---------------------------------------------------------------- V11 Taylor remainder
+def test_v11_oracle_adjoint_taylor_remainder():
+    """The CPU adjoint's gradient g of L(V) against the function itself: the first-order Taylor
+    remainder |L(V + h d) - L(V) - h g.d| falls as h^2 over four halvings of h (ratios 4 to
+    within 1e-5 here), while the zeroth-order one |L(V + h d) - L(V)| tends to falling as h."""
+    from oracle.adjoint import observables_after, schedule_gradient
+    case = make_case("c4s")
+    o = Oracle(case.dim, case.n, case.periodic, case.params, case.flags)
+    sched = np.array([0.03, 0.07, 0.05])
+    T = t_total = 9
+    gx = np.array([1.0, -0.5, 0.0])
+    gv = np.array([30.0, 10.0, 0.0])
+    g, _, _ = schedule_gradient(o, case.phi, sched, T, t_total, gx, gv)
+    d = np.array([0.6, -0.3, 0.74])
+
+    def L(v):
+        xc, vc = observables_after(o, case.phi, torch.tensor(v, dtype=F64), T, t_total)
+        return float((torch.tensor(gx) * xc).sum() + (torch.tensor(gv) * vc).sum())
+    L0 = L(sched)
+    hs = [0.04, 0.02, 0.01, 0.005, 0.0025]
+    r1, r0 = [], []
+    for h in hs:
+        Lh = L(sched + h * d)
+        r0.append(abs(Lh - L0))
+        r1.append(abs(Lh - L0 - h * float(g @ torch.tensor(d))))
+    q1 = [r1[k] / r1[k + 1] for k in range(len(hs) - 1)]
+    q0 = [r0[k] / r0[k + 1] for k in range(len(hs) - 1)]
+    print("remainder ratios", q1, "zeroth order", q0)
+    assert all(3.9 < q < 4.1 for q in q1)
+    assert 1.9 < q0[-1] < 2.2 and q0[-1] < q0[0]
+
+
+# ---------------------------------------------------------------- observables (a10)
+def test_observables_of_a_translating_droplet():
+    """A droplet carried by a uniform flow in a fully periodic box (populations at equilibrium
+    with velocity u0): the phase masses stay constant, the reported velocity (Phi_1-weighted
+    mean of the last step's u) is u0, and the centroid (Phi_1-weighted mean node coordinate)
+    advances by u0 t."""
+    from oracle import model
+    n = (48, 48, 1)
+    case = pc.periodic_droplet(n=n, radius=8.0, mobility=0.02)
+    _, per, p, fl, phi = case
+    p = dict(p)
+    o = Oracle(2, n, (1, 1, 0), p, fl)
+    s = o.init_state(phi)
+    u0 = torch.tensor([0.02, -0.01, 0.0], dtype=F64)
+    u = u0.reshape(3, 1).expand(3, o.N).clone()
+    phi_t = torch.as_tensor(phi, dtype=F64)
+    s.g = model.flow_equilibrium(torch.zeros(o.N, dtype=F64), u, o.lat)
+    s.f = torch.stack([model.phase_equilibrium(phi_t[i], u, o.lat) for i in range(3)])
+    s.u_prev = u.clone()
+    ob0 = o.observables(s)
+    steps = 150
+    s, _ = o.run(s, steps)
+    ob = o.observables(s)
+    print("velocity", ob["velocity"], "centroid advance", ob["centroid"] - ob0["centroid"], "expected", u0 * steps)
+    assert torch.all((ob["mass"] - ob0["mass"]).abs() <= 1e-12 * ob0["mass"])
+    assert float((ob["velocity"] - u0).abs().max()) < 1e-3 * float(u0.abs().max())
+    adv = (ob["centroid"] - ob0["centroid"])[:2]
+    assert float((adv - u0[:2] * steps).abs().max()) < 1e-3 * float(u0.abs().max() * steps)
