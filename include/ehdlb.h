@@ -103,6 +103,14 @@ typedef struct {
                                path's precision, 8 eps max_i sum_j |A_ij phi_j|           */
   int32_t poisson_max_iter; /* iteration cap of the potential solve (>= 1)                */
   int32_t poisson_check_every;  /* residual check period in iterations (>= 1)             */
+  double s_high;            /* relaxation rate of the raw moments the paper leaves unspecified
+                               (Eq. 15 and the Eq. 20 pair give S without its entries): order
+                               >= 2 for the phase fields and the charge, >= 3 for the flow,
+                               in (0, 2); 0 means the default 1 (those moments then leave
+                               the collision at equilibrium)                              */
+  double rho[3];            /* density per phase; density ratio 1 only (every entry 1, or 0
+                               for the default 1): the flow equilibrium is the
+                               incompressible one about the unit density                 */
 } ehdlb_params;
 
 typedef struct {
@@ -120,7 +128,8 @@ typedef struct {
 
 /* Validate lattice and parameters and create a context (no device work).
  * EINVAL: dim not 2/3, sizes < 1, Nz != 1 in 2D, tau <= 1/2, M <= 0, W <= 0,
- * any Upsilon_i <= 0, eps <= 0, cond < 0, alpha < 0, tol <= 0, max_iter < 1. */
+ * any Upsilon_i <= 0, eps <= 0, cond < 0, alpha < 0, tol <= 0, max_iter < 1,
+ * s_high outside (0, 2), a density other than 1. */
 ehdlb_status ehdlb_create(const ehdlb_lattice* lattice, const ehdlb_params* params,
                           ehdlb_ctx** out);
 
@@ -162,9 +171,13 @@ ehdlb_status ehdlb_set_schedule(ehdlb_ctx* ctx, int32_t electrode, int32_t n_seg
  * synchronises only for the potential solve's residual checks. */
 ehdlb_status ehdlb_step(ehdlb_ctx* ctx, int64_t n);
 
-/* Copy one field to a host float64 array of N values (POPS: see above).
- * Synchronises the bound stream. */
-ehdlb_status ehdlb_read_field(ehdlb_ctx* ctx, int32_t field, double* dst_host);
+/* Copy one field, as float64, to N values at dst (POPS: see above), the droplet
+ * and flow fields the paper reports (Results: charge and flow fields, Fig. 2-3).
+ * dst_is_device = 0: dst is host memory; the call synchronises the bound stream.
+ * dst_is_device = 1: dst is device memory on the bound device (8-byte aligned);
+ * the conversion is enqueued on the bound stream and the call returns without
+ * waiting (dst is valid once the stream reaches that point).  The caller owns dst. */
+ehdlb_status ehdlb_read_field(ehdlb_ctx* ctx, int32_t field, void* dst, int32_t dst_is_device);
 
 /* Number of doubles ehdlb_read_field(EHDLB_FIELD_POPS) writes. */
 size_t ehdlb_num_populations(const ehdlb_ctx* ctx);
@@ -253,6 +266,35 @@ ehdlb_status ehdlb_timing(ehdlb_ctx* ctx, double* ms3, int64_t* steps);
  * gradient iterations, max_rel0[k] the largest initial relative residual max|b - A x0|/max|b|
  * of the warm start.  counts: int64[4], max_rel0: double[2] (host, either may be NULL). */
 ehdlb_status ehdlb_solver_stats(ehdlb_ctx* ctx, int32_t reset, int64_t* counts, double* max_rel0);
+
+/* Host-only workload presets (no context, no device): the droplet / lubricant /
+ * ambient configurations of the paper's problem statement (Results, Fig. 1 and
+ * its text: micropillars of solid fraction 0.25 infused with lubricant to their
+ * tops, a droplet cap on the lubricant, an electrode segment on the opposite
+ * wall, grounded pillars and substrate, insulating walls elsewhere; Methods:
+ * M = 0.0025, W = 4; Fig. 2 contact angles theta_13 = 100, theta_23 = 5 degrees)
+ * at the sizes of the named workloads:
+ *   EHDLB_PRESET_C1  2D 128x64, 6-cell lubricant film, droplet R = 20, no field,
+ *                    initial phase fields jittered by +-1e-6 (counter-based
+ *                    SplitMix64 draws keyed by seed, node and component)
+ *   EHDLB_PRESET_C2  2D 512x256, pillars 8/16/12, droplet R = 40, electrode 0.05
+ *                    on 64 cells of the top wall 40 lu ahead of the droplet
+ *   EHDLB_PRESET_C3  3D 256x128x96, pillars 6x6x10 at pitch 12, droplet R = 30
+ *   EHDLB_PRESET_C4  the C2 geometry in the FP32 path (the schedule is the
+ *                    caller's: ehdlb_set_schedule)
+ *   EHDLB_PRESET_C5  3D 384x192x128, droplet R = 48
+ *   EHDLB_PRESET_C1S..C4S reduced variants with the same structure (64x32,
+ *                    128x64, 48x32x24, 96x48).
+ * Writes the lattice and parameters; flags (N uint8) and phi ([3][N] float64) if
+ * the pointers are not NULL (N = nx ny nz of the written lattice: call once with
+ * NULL arrays to learn it).  seed keys the jitter of C1 and C1S only.  EINVAL on
+ * an unknown id. */
+enum {
+  EHDLB_PRESET_C1 = 1, EHDLB_PRESET_C2 = 2, EHDLB_PRESET_C3 = 3, EHDLB_PRESET_C4 = 4, EHDLB_PRESET_C5 = 5,
+  EHDLB_PRESET_C1S = 11, EHDLB_PRESET_C2S = 12, EHDLB_PRESET_C3S = 13, EHDLB_PRESET_C4S = 14
+};
+ehdlb_status ehdlb_preset(int32_t preset_id, ehdlb_lattice* lattice, ehdlb_params* params, uint8_t* flags,
+                          double* phi, uint64_t seed);
 
 /* Forward generation of the context: a counter bumped by every call that changes
  * the state or what the next steps compute (set_geometry, set_phase, set_charge,

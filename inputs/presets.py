@@ -81,6 +81,8 @@ def default_params(dim: int, **over) -> dict:
         poisson_tol=1e-13,
         poisson_max_iter=400,
         poisson_check_every=1,
+        s_high=1.0,
+        rho=(1.0, 1.0, 1.0),
     )
     for k, v in over.items():
         if k not in p:

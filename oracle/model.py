@@ -129,11 +129,12 @@ def mrt_collide(f, feq, C, rates, lat):
     return Minv @ mstar
 
 
-def moment_rates(lat, by_order, N=None):
-    """Diagonal of S from a map order -> rate (scalar or (N,) tensor); unlisted orders relax at 1."""
+def moment_rates(lat, by_order, N=None, default=1.0):
+    """Diagonal of S from a map order -> rate (scalar or (N,) tensor); unlisted orders relax at
+    `default` (the rate of the moments the paper leaves unspecified, 1 unless chosen)."""
     rows = []
     for k in range(lat.Q):
-        r = by_order.get(lat.order[k], 1.0)
+        r = by_order.get(lat.order[k], default)
         if torch.is_tensor(r):
             rows.append(r)
         else:

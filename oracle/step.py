@@ -23,7 +23,8 @@ Readings (paper silent or garbled):
   * Flow (equilibrium and forcing deferred by the paper): incompressible
     He-Luo equilibrium with rho0 = 1 stored as the deviation dg = g - w; Guo
     forcing; u = j + F/2; p = cs2 drho.  Second-order raw moments relax at
-    1/tau(x) with tau = 1/2 + nu/cs2, nu linear in Phi; higher moments at 1.
+    1/tau(x) with tau = 1/2 + nu/cs2, nu linear in Phi; higher moments at
+    s_high (1 unless chosen; also for orders >= 2 of the phase fields and charge).
   * Charge: equilibrium rho_e w (1 + e.u/cs2); R = (w/cs2) e.d(rho_e u)/dt
     inside the MRT; C = w Q added after the collision with the half time
     derivative; first-order moments at 1/tau_e, alpha = cs2 (tau_e - 1/2).
@@ -74,6 +75,9 @@ class Oracle:
         cs2 = self.lat.cs2
         self.s_phi = 1.0 / (0.5 + p["mobility"] / cs2)
         self.s_e = 1.0 / (0.5 + p["charge_diffusion"] / cs2) if self.ehd else 1.0
+        # rate of every raw moment not named by the scheme (orders >= 2 of the phase fields and
+        # the charge, >= 3 of the flow; Eq. 15 and Eq. 20b leave S unspecified): 1 by default
+        self.s_high = float(p.get("s_high", 1.0) or 1.0)
         self.nu = [cs2 * (t - 0.5) for t in p["tau_flow"]]
         self.eps = [float(v) for v in p["eps"]]
         self.cond = [float(v) for v in p["cond"]]
@@ -215,12 +219,12 @@ class Oracle:
         Fg = model.guo_source(u, F, lat)
         nu = sum(self.nu[i] * phi[i] for i in range(3))
         tau = 0.5 + nu / cs2
-        rates_g = model.moment_rates(lat, {2: 1.0 / tau}, N)
+        rates_g = model.moment_rates(lat, {2: 1.0 / tau}, N, default=self.s_high)
         gstar = model.mrt_collide(s.g, geq, Fg, rates_g, lat)
         g_new = self.stream(gstar)
         # O8 phase fields
         Fphi = model.phase_flux(phi, nrm, self.W)          # (3 comps, 3 axes, N)
-        rates_f = model.moment_rates(lat, {1: self.s_phi})
+        rates_f = model.moment_rates(lat, {1: self.s_phi}, default=self.s_high)
         f_new = []
         for i in range(3):
             dphiu = dt_on * (phi[i] * u - s.phi_prev[i] * s.u_prev)
@@ -235,7 +239,7 @@ class Oracle:
             drhou = dt_on * (rho * u - s.rho_prev * s.u_prev)
             R = model.vector_source(drhou, lat)
             heq = model.phase_equilibrium(rho, u, lat)
-            rates_h = model.moment_rates(lat, {1: self.s_e})
+            rates_h = model.moment_rates(lat, {1: self.s_e}, default=self.s_high)
             hstar = model.mrt_collide(s.h, heq, R, rates_h, lat)
             hstar = hstar + lat.w.reshape(-1, 1) * (Qsrc + 0.5 * dt_on * (Qsrc - s.q_prev))
             h_new = self.stream(hstar)

@@ -14,6 +14,7 @@ OK, EINVAL, ESTATE, EHIP, ENOMEM, ENONFINITE, ENOCONV = 0, -1, -2, -3, -4, -5, -
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "EHIP", -4: "ENOMEM", -5: "ENONFINITE", -6: "ENOCONV"}
 FP64, FP32_DEV = 0, 1
 FIELDS = dict(phi1=0, phi2=1, phi3=2, ux=3, uy=4, uz=5, p=6, rho_e=7, pot=8, q=9, pops=10)
+PRESETS = dict(c1=1, c2=2, c3=3, c4=4, c5=5, c1s=11, c2s=12, c3s=13, c4s=14)
 
 
 class Lattice(C.Structure):
@@ -34,6 +35,7 @@ class Params(C.Structure):
         ("electrode_volts", C.c_double * MAX_ELECTRODES),
         ("poisson_tol", C.c_double),
         ("poisson_max_iter", C.c_int32), ("poisson_check_every", C.c_int32),
+        ("s_high", C.c_double), ("rho", C.c_double * 3),
     ]
 
 
@@ -64,7 +66,7 @@ SIGNATURES = {
     "ehdlb_set_charge": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ehdlb_set_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64]),
     "ehdlb_step": (C.c_int, [C.c_void_p, C.c_int64]),
-    "ehdlb_read_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "ehdlb_read_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
     "ehdlb_num_populations": (C.c_size_t, [C.c_void_p]),
     "ehdlb_observables": (C.c_int, [C.c_void_p, C.POINTER(Obs)]),
     "ehdlb_state_bytes": (C.c_size_t, [C.c_void_p]),
@@ -79,6 +81,8 @@ SIGNATURES = {
     "ehdlb_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "ehdlb_timing": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ehdlb_generation": (C.c_uint64, [C.c_void_p]),
+    "ehdlb_preset": (C.c_int, [C.c_int32, C.POINTER(Lattice), C.POINTER(Params), C.c_void_p, C.c_void_p,
+                               C.c_uint64]),
     "ehdlb_last_error": (C.c_char_p, [C.c_void_p]),
     "ehdlb_destroy": (None, [C.c_void_p]),
 }

@@ -62,7 +62,10 @@ struct AdjArgs {
 };
 
 // ----------------------------------------------------------------------------- pass A
-template <class L, class T, bool EHD>
+// HIGH: the higher moments relax at p.s_high (see k_step): every equilibrium and source term
+// of the collision is scaled accordingly, and the population cotangents of step t receive
+// (1 - s_high) times the streamed cotangents directly (pass CD)
+template <class L, class T, bool EHD, bool HIGH>
 __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
   using ML = MomLayout<L>;
   using RL = RecLayout<L>;
@@ -212,21 +215,24 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) dru[c] = dt * (rq * u[c] - rp * up[c]);
       T lsrc = 0, ldru[3] = {0, 0, 0}, lJe[3] = {0, 0, 0};
-      const T om = T(1) - p.s_e;
+      const T sh = HIGH ? p.s_high : T(1);
+      const T om = sh - p.s_e;
+      const T cR = T(3) - T(1.5) * sh;  // (1 - s_high/2) times the 3 w e of the source
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
         const T w = T(L::w36[q]) / T(36);
         const T lo = lout(4, q);
+        const T los = HIGH ? sh * lo : lo;
         const T eu = T(ix) * u[0] + T(iy) * u[1] + T(iz) * u[2];
         lsrc += lo * w;
-        lrho += lo * w * (T(1) + T(3) * eu);
-        lu[0] += lo * w * rq * T(3) * T(ix);
-        lu[1] += lo * w * rq * T(3) * T(iy);
-        lu[2] += lo * w * rq * T(3) * T(iz);
-        ldru[0] += lo * T(1.5) * w * T(ix);
-        ldru[1] += lo * T(1.5) * w * T(iy);
-        ldru[2] += lo * T(1.5) * w * T(iz);
+        lrho += los * w * (T(1) + T(3) * eu);
+        lu[0] += los * w * rq * T(3) * T(ix);
+        lu[1] += los * w * rq * T(3) * T(iy);
+        lu[2] += los * w * rq * T(3) * T(iz);
+        ldru[0] += lo * cR * w * T(ix);
+        ldru[1] += lo * cR * w * T(iy);
+        ldru[2] += lo * cR * w * T(iz);
         if (ix * ix + iy * iy + iz * iz == 1) {
           lJe[0] += lo * T(0.5) * om * T(ix);
           lJe[1] += lo * T(0.5) * om * T(iy);
@@ -271,7 +277,9 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
       for (int c = 0; c < 3; ++c) tot[c] = amag[0] * nrm[0][c] + amag[1] * nrm[1][c] + amag[2] * nrm[2][c];
       T den = pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2];
       if (!(den > T(0))) den = T(1);
-      const T om = T(1) - p.s_phi;
+      const T sh = HIGH ? p.s_high : T(1);
+      const T om = sh - p.s_phi;
+      const T cC = T(3) - T(1.5) * sh;  // (1 - s_high/2) times the 3 w e of the source
       T lFphi[3][3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -282,14 +290,15 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
           const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
           const T w = T(L::w36[q]) / T(36);
           const T lo = lout(1 + i, q);
+          const T los = HIGH ? sh * lo : lo;
           const T eu = T(ix) * u[0] + T(iy) * u[1] + T(iz) * u[2];
-          lphi[i] += lo * w * (T(1) + T(3) * eu);
-          lu[0] += lo * w * pc[i] * T(3) * T(ix);
-          lu[1] += lo * w * pc[i] * T(3) * T(iy);
-          lu[2] += lo * w * pc[i] * T(3) * T(iz);
-          lG[0] += lo * T(1.5) * w * T(ix);
-          lG[1] += lo * T(1.5) * w * T(iy);
-          lG[2] += lo * T(1.5) * w * T(iz);
+          lphi[i] += los * w * (T(1) + T(3) * eu);
+          lu[0] += los * w * pc[i] * T(3) * T(ix);
+          lu[1] += los * w * pc[i] * T(3) * T(iy);
+          lu[2] += los * w * pc[i] * T(3) * T(iz);
+          lG[0] += lo * cC * w * T(ix);
+          lG[1] += lo * cC * w * T(iy);
+          lG[2] += lo * cC * w * T(iz);
           if (ix * ix + iy * iy + iz * iz == 1) {
             lJ[0] += lo * T(0.5) * om * T(ix);
             lJ[1] += lo * T(0.5) * om * T(iy);
@@ -378,7 +387,8 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
           Pk[k] = Pi[k < P ? k : 0];
         }
       }
-      const T omn = T(1) - s_nu;
+      const T sh = HIGH ? p.s_high : T(1);
+      const T omn = sh - s_nu;
       T ls = 0;
 #pragma unroll
       for (int k = 0; k < P; ++k) {
@@ -400,8 +410,8 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
         }
         const T w = T(L::w36[q]) / T(36);
         const T lq = lout(0, q);  // re-read (cache hit) rather than kept live
-        const T lgeq = lq - ld;
-        const T lFq = T(0.5) * (lq + ld);
+        const T lgeq = (HIGH ? sh * lq : lq) - ld;
+        const T lFq = (HIGH ? (T(1) - T(0.5) * sh) * lq : T(0.5) * lq) + T(0.5) * ld;
         const T eu = exq * u[0] + eyq * u[1] + ezq * u[2];
         const T eF = exq * F[0] + eyq * F[1] + ezq * F[2];
         ldrho += lgeq * w;
@@ -533,16 +543,16 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
   if (EHD) block_reduce<kMaxE, false>(vloc, a.vpart + (int64_t)blockIdx.x * kMaxE);
 }
 
-template <class L, class T, bool EHD>
+template <class L, class T, bool EHD, bool HIGH>
 __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
-  adj_a_body<L, T, EHD>(a);
+  adj_a_body<L, T, EHD, HIGH>(a);
 }
 // FP32: capped at 256 registers so that two waves fit per SIMD (one 8-byte spill in 3D);
 // uncapped, the kernel needs just over 256 and runs one wave per SIMD.  The FP64 variants
 // would spill heavily under the same cap.
-template <class L, bool EHD>
+template <class L, bool EHD, bool HIGH>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_a32(AdjArgs<float> a) {
-  adj_a_body<L, float, EHD>(a);
+  adj_a_body<L, float, EHD, HIGH>(a);
 }
 
 // ----------------------------------------------------------------------------- pass B
@@ -633,13 +643,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_ghost(int64_t N, int nsrc, const
 
 // ----------------------------------------------------------------------------- pass CD
 // Permittivity and charge cotangents from the potential adjoint lb, then the population
-// cotangents of step t.
-template <class L, class T, bool EHD>
+// cotangents of step t.  HIGH: plus (1 - s_high) times the streamed cotangents of step t+1
+// (lP_next, gathered as in pass A).
+template <class L, class T, bool EHD, bool HIGH>
 __global__ __launch_bounds__(kBlock) void k_adj_cd(Dims d, const uint8_t* __restrict__ flags, Phys<T> p,
                                                     Volts<T> volts, const T* __restrict__ rec,
                                                     const T* __restrict__ lphi, const T* __restrict__ lrho_loc,
                                                     const T* __restrict__ lb, const T* __restrict__ lmom,
-                                                    T* __restrict__ lP, double* __restrict__ vpart) {
+                                                    const T* __restrict__ lP_next, T* __restrict__ lP,
+                                                    double* __restrict__ vpart) {
   using ML = MomLayout<L>;
   using RL = RecLayout<L>;
   constexpr int Q = L::Q;
@@ -712,6 +724,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_cd(Dims d, const uint8_t* __rest
           lP[((int64_t)(1 + i) * Q + q) * N + x] = v;
         }
         if (EHD) lP[((int64_t)4 * Q + q) * N + x] = lrho + exq * ljh[0] + eyq * ljh[1] + ezq * ljh[2];
+      }
+      if (HIGH) {
+        int nb[Q];
+        neighbours<L>(d, x, nb);
+        const T k1 = T(1) - p.s_high;
+        for (int f = 0; f < F; ++f) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const T lo = flags[nb[q]] != 0 ? lP_next[((int64_t)f * Q + L::opp[q]) * N + x]
+                                           : lP_next[((int64_t)f * Q + q) * N + nb[q]];
+            lP[((int64_t)f * Q + q) * N + x] += k1 * lo;
+          }
+        }
       }
     }
   }

@@ -15,6 +15,7 @@
 #include "kernels.h"
 #include "step.h"
 #include "adjoint.h"
+#include "preset.h"
 
 using namespace ehd;
 
@@ -197,6 +198,7 @@ static Phys<T> make_phys(const ehdlb_params& p) {
   r.cos23 = (T)p.cos23;
   r.s_phi = (T)(1.0 / (0.5 + 3.0 * p.mobility));
   r.s_e = (T)(1.0 / (0.5 + 3.0 * p.charge_diffusion));
+  r.s_high = (T)p.s_high;
   for (int i = 0; i < 3; ++i) {
     r.nu[i] = (T)((p.tau_flow[i] - 0.5) / 3.0);
     r.eps[i] = (T)p.eps[i];
@@ -362,6 +364,10 @@ static ehdlb_status validate(ehdlb_ctx* c, const ehdlb_lattice* L, const ehdlb_p
     if (p->ehd && !(p->eps[i] > 0.0)) return fail(c, EHDLB_EINVAL, "permittivity must be > 0");
     if (p->ehd && !(p->cond[i] >= 0.0)) return fail(c, EHDLB_EINVAL, "conductivity must be >= 0");
   }
+  if (!(p->s_high > 0.0 && p->s_high < 2.0)) return fail(c, EHDLB_EINVAL, "s_high must lie in (0, 2)");
+  for (int i = 0; i < 3; ++i)
+    if (p->rho[i] != 1.0)
+      return fail(c, EHDLB_EINVAL, "density ratio 1 only: rho must be 1 for every phase (or 0 for the default)");
   if (!(p->mobility > 0.0)) return fail(c, EHDLB_EINVAL, "mobility must be > 0");
   if (!(p->width > 0.0)) return fail(c, EHDLB_EINVAL, "interface width must be > 0");
   double u[3], ut;
@@ -728,12 +734,21 @@ static void launch_moments(const ehdlb_ctx* c, int families, const Dims& dm, con
                        fam0);
 }
 
+template <class LT, class T, bool EHD, bool STORE, bool HIGH>
+static void launch_step_h(const ehdlb_ctx* c, const StepArgs<T>& a) {
+  if (c->stream_pops)
+    hipLaunchKernelGGL((k_step<LT, T, EHD, STORE, true, HIGH>), dim3(nblocks(a.d.N)), dim3(kBlock), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL((k_step<LT, T, EHD, STORE, false, HIGH>), dim3(nblocks(a.d.N)), dim3(kBlock), 0, c->stream, a);
+}
+
+// the variant with the higher moments away from rate 1 only when they are
 template <class LT, class T, bool EHD, bool STORE>
 static void launch_step(const ehdlb_ctx* c, const StepArgs<T>& a) {
-  if (c->stream_pops)
-    hipLaunchKernelGGL((k_step<LT, T, EHD, STORE, true>), dim3(nblocks(a.d.N)), dim3(kBlock), 0, c->stream, a);
+  if (c->prm.s_high != 1.0)
+    launch_step_h<LT, T, EHD, STORE, true>(c, a);
   else
-    hipLaunchKernelGGL((k_step<LT, T, EHD, STORE, false>), dim3(nblocks(a.d.N)), dim3(kBlock), 0, c->stream, a);
+    launch_step_h<LT, T, EHD, STORE, false>(c, a);
 }
 
 // ============================================================================ step
@@ -904,6 +919,11 @@ struct InitFn {
     hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(npop)), dim3(kBlock), 0, c->stream, npop, c->ptr<T>(c->off_pop[1]));
     hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, c->stream, N, c->ptr<T>(c->off_pot));
     hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, c->stream, N, c->ptr<T>(c->off_pot_old));
+    // the t = 0 slots of u and Q: the steps write them at fluid nodes only, so their solid nodes
+    // (read out as zero velocity and source) are set here
+    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks((int64_t)c->D * N)), dim3(kBlock), 0, c->stream, (int64_t)c->D * N,
+                       c->ptr<T>(c->off_u[0]));
+    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, c->stream, N, c->ptr<T>(c->off_q[0]));
     LAUNCHCHK();
     return EHDLB_OK;
   }
@@ -1157,10 +1177,18 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
   double* vpart = reinterpret_cast<double*>(J.ws + J.vpart);
   double* vred = reinterpret_cast<double*>(J.ws + J.vred);
   double* vacc = reinterpret_cast<double*>(J.ws + J.vacc);
-  if constexpr (std::is_same<T, float>::value)
-    hipLaunchKernelGGL((k_adj_a32<LT, EHD>), dim3(nb), dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_adj_a<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, a);
+  const bool high = c->prm.s_high != 1.0;
+  if constexpr (std::is_same<T, float>::value) {
+    if (high)
+      hipLaunchKernelGGL((k_adj_a32<LT, EHD, true>), dim3(nb), dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_adj_a32<LT, EHD, false>), dim3(nb), dim3(kBlock), 0, s, a);
+  } else {
+    if (high)
+      hipLaunchKernelGGL((k_adj_a<LT, T, EHD, true>), dim3(nb), dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_adj_a<LT, T, EHD, false>), dim3(nb), dim3(kBlock), 0, s, a);
+  }
   if (EHD) {
     hipLaunchKernelGGL((k_final_wide<kMaxE, false>), dim3(1), dim3(kFinalWide), 0, s, vpart, nb, vred);
     hipLaunchKernelGGL(k_vacc_add, dim3(1), dim3(64), 0, s, vred, vacc, seg, J.nvseg);
@@ -1199,8 +1227,14 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
     }
     if ((st = pcg<LT, T>(c, A(lbx), (const T*)A(J.lpot), c->cg_hist[1]))) return st;
   }
-  hipLaunchKernelGGL((k_adj_cd<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, v, rec, (const T*)A(J.lphi),
-                     (const T*)A(J.lrho_loc), (const T*)A(lbx), (const T*)A(J.lmom), A(J.lP[cu]), vpart);
+  if (high)
+    hipLaunchKernelGGL((k_adj_cd<LT, T, EHD, true>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, v, rec,
+                       (const T*)A(J.lphi), (const T*)A(J.lrho_loc), (const T*)A(lbx), (const T*)A(J.lmom),
+                       (const T*)A(J.lP[nx]), A(J.lP[cu]), vpart);
+  else
+    hipLaunchKernelGGL((k_adj_cd<LT, T, EHD, false>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, v, rec,
+                       (const T*)A(J.lphi), (const T*)A(J.lrho_loc), (const T*)A(lbx), (const T*)A(J.lmom),
+                       (const T*)A(J.lP[nx]), A(J.lP[cu]), vpart);
   if (EHD) {
     hipLaunchKernelGGL((k_final_wide<kMaxE, false>), dim3(1), dim3(kFinalWide), 0, s, vpart, nb, vred);
     hipLaunchKernelGGL(k_vacc_add, dim3(1), dim3(64), 0, s, vred, vacc, seg, J.nvseg);
@@ -1286,9 +1320,16 @@ struct AdjFn {
 // ============================================================================ C ABI
 extern "C" {
 
-ehdlb_status ehdlb_create(const ehdlb_lattice* lattice, const ehdlb_params* params, ehdlb_ctx** out) {
+ehdlb_status ehdlb_create(const ehdlb_lattice* lattice, const ehdlb_params* params_in, ehdlb_ctx** out) {
   if (!out) return EHDLB_EINVAL;
   *out = nullptr;
+  if (!params_in) return EHDLB_EINVAL;
+  // zero means the default for the fields a zero-initialised struct leaves at 0
+  ehdlb_params pn = *params_in;
+  if (pn.s_high == 0.0) pn.s_high = 1.0;
+  for (int i = 0; i < 3; ++i)
+    if (pn.rho[i] == 0.0) pn.rho[i] = 1.0;
+  const ehdlb_params* params = &pn;
   ehdlb_ctx tmp;
   ehdlb_status st = validate(&tmp, lattice, params);
   if (st) return st;
@@ -1527,16 +1568,44 @@ ehdlb_status ehdlb_step(ehdlb_ctx* c, int64_t n) {
   return dispatch<StepFn>(c, n);
 }
 
-ehdlb_status ehdlb_read_field(ehdlb_ctx* c, int32_t field, double* dst) {
+ehdlb_status ehdlb_read_field(ehdlb_ctx* c, int32_t field, void* dst_v, int32_t dst_is_device) {
   if (!c) return EHDLB_EINVAL;
-  if (!dst) return fail(c, EHDLB_EINVAL, "null destination");
+  if (!dst_v) return fail(c, EHDLB_EINVAL, "null destination");
+  if (dst_is_device != 0 && dst_is_device != 1) return fail(c, EHDLB_EINVAL, "dst_is_device must be 0 or 1");
+  if (dst_is_device && ((uintptr_t)dst_v) % 8) return fail(c, EHDLB_EINVAL, "device destination must be 8-byte aligned");
   if (!c->have_state) return fail(c, EHDLB_ESTATE, "read_field before set_phase");
+  if (field < EHDLB_FIELD_PHI1 || field > EHDLB_FIELD_POPS) return fail(c, EHDLB_EINVAL, "unknown field id");
+  double* dst = static_cast<double*>(dst_v);
   const int64_t N = c->N;
   const int pi = (int)(c->t & 1), pp = 1 - pi;
   ehdlb_status st;
-  auto out = [&](size_t off, int64_t n) -> ehdlb_status {
-    return c->tsize == 8 ? copy_out<double>(c, c->ptr<double>(off), n, dst)
+  // n values from workspace offset off (times scale, if not 1), to the host or the device
+  auto out = [&](size_t off, int64_t n, double scale = 1.0) -> ehdlb_status {
+    if (!dst_is_device) {
+      st = c->tsize == 8 ? copy_out<double>(c, c->ptr<double>(off), n, dst)
                          : copy_out<float>(c, c->ptr<float>(off), n, dst);
+      if (st) return st;
+      if (scale != 1.0)
+        for (int64_t i = 0; i < n; ++i) dst[i] *= scale;
+      return EHDLB_OK;
+    }
+    if (c->tsize == 8)
+      hipLaunchKernelGGL(k_to_double_scaled<double>, dim3(nblocks(n)), dim3(kBlock), 0, c->stream, n,
+                         (const double*)c->ptr<double>(off), scale, dst);
+    else
+      hipLaunchKernelGGL(k_to_double_scaled<float>, dim3(nblocks(n)), dim3(kBlock), 0, c->stream, n,
+                         (const float*)c->ptr<float>(off), scale, dst);
+    LAUNCHCHK();
+    return EHDLB_OK;
+  };
+  auto zeros = [&]() -> ehdlb_status {
+    if (!dst_is_device) {
+      std::fill(dst, dst + N, 0.0);
+      return EHDLB_OK;
+    }
+    hipLaunchKernelGGL(k_zero<double>, dim3(nblocks(N)), dim3(kBlock), 0, c->stream, N, dst);
+    LAUNCHCHK();
+    return EHDLB_OK;
   };
   switch (field) {
     case EHDLB_FIELD_PHI1:
@@ -1545,46 +1614,27 @@ ehdlb_status ehdlb_read_field(ehdlb_ctx* c, int32_t field, double* dst) {
     case EHDLB_FIELD_RHO_E:
     case EHDLB_FIELD_P:
       if ((st = dispatch<MomFn>(c, 0))) return st;
-      if (field == EHDLB_FIELD_RHO_E) {
-        if (!c->ehd) {
-          std::fill(dst, dst + N, 0.0);
-          return EHDLB_OK;
-        }
-        return out(c->off_rho[pi], N);
-      }
-      if (field == EHDLB_FIELD_P) {
-        if ((st = out(c->off_scratch, N))) return st;
-        for (int64_t i = 0; i < N; ++i) dst[i] *= 1.0 / 3.0;
-        return EHDLB_OK;
-      }
+      if (field == EHDLB_FIELD_RHO_E) return c->ehd ? out(c->off_rho[pi], N) : zeros();
+      if (field == EHDLB_FIELD_P) return out(c->off_scratch, N, 1.0 / 3.0);
       return out(c->off_phi[pi] + (size_t)(field - EHDLB_FIELD_PHI1) * N * c->tsize, N);
     case EHDLB_FIELD_UX:
     case EHDLB_FIELD_UY:
     case EHDLB_FIELD_UZ: {
       const int a = field - EHDLB_FIELD_UX;
-      if (a >= c->D) {
-        std::fill(dst, dst + N, 0.0);
-        return EHDLB_OK;
-      }
-      return out(c->off_u[pp] + (size_t)a * N * c->tsize, N);
+      return a >= c->D ? zeros() : out(c->off_u[pp] + (size_t)a * N * c->tsize, N);
     }
     case EHDLB_FIELD_POT:
-      if (!c->ehd) {
-        std::fill(dst, dst + N, 0.0);
-        return EHDLB_OK;
-      }
-      return out(c->off_pot, N);
+      return c->ehd ? out(c->off_pot, N) : zeros();
     case EHDLB_FIELD_Q:
-      if (!c->ehd) {
-        std::fill(dst, dst + N, 0.0);
-        return EHDLB_OK;
-      }
-      return out(c->off_q[pp], N);
-    case EHDLB_FIELD_POPS:
+      return c->ehd ? out(c->off_q[pp], N) : zeros();
+    default:  // EHDLB_FIELD_POPS
       return out(c->off_pop[c->cur], (int64_t)c->F * c->Q * N);
-    default:
-      return fail(c, EHDLB_EINVAL, "unknown field id");
   }
+}
+
+ehdlb_status ehdlb_preset(int32_t preset_id, ehdlb_lattice* lattice, ehdlb_params* params, uint8_t* flags,
+                          double* phi, uint64_t seed) {
+  return ehd_preset::preset(preset_id, lattice, params, flags, phi, seed);
 }
 
 ehdlb_status ehdlb_observables(ehdlb_ctx* c, ehdlb_obs* o) {

@@ -108,6 +108,7 @@ struct Phys {
   T cos12, cos13, cos23;
   T s_phi;        // first-order rate of the phase fields, 1/(1/2 + M/cs2)
   T s_e;          // first-order rate of the charge, 1/(1/2 + alpha/cs2)
+  T s_high;       // rate of the higher moments: order >= 2 (phase, charge), >= 3 (flow)
   T nu[3];        // kinematic viscosity per phase
   T eps[3], cond[3];
   T body[3];
@@ -1525,6 +1526,17 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_to_double(int64_t N, const T* __restrict__ a, double* __restrict__ out) {
   const int64_t i = gidx();
   if (i < N) out[i] = (double)a[i];
+}
+
+// T -> double copy times a factor (the pressure cs^2 drho), rounded as the host does it
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_to_double_scaled(int64_t N, const T* __restrict__ a, double scale,
+                                                             double* __restrict__ out) {
+  const int64_t i = gidx();
+  if (i < N) {
+    const double v = (double)a[i];
+    out[i] = v * scale;
+  }
 }
 
 }  // namespace ehd

@@ -9,8 +9,14 @@
 namespace ehd {
 
 // ----------------------------------------------------------------------------- fused collide-stream
-// NT: population loads with the non-temporal hint (as in k_moments)
-template <class L, class T, bool EHD, bool STORE, bool NT>
+// NT: population loads with the non-temporal hint (as in k_moments).  HIGH: the higher moments
+// relax at p.s_high instead of 1.  With S the diagonal of rates, the raw-moment MRT
+// m* = m - S(m - m_eq) + (I - S/2) M C is f* = f_eq + C/2 + M^-1 (I - S) M d with
+// d = f - f_eq + C/2, whose zeroth moment vanishes (and, for the flow, its first moment too:
+// j - u + F/2 = 0), so M^-1 (I - S) M d = (1 - s_high) d + (s_high - s_k) P_k d with P_k the
+// projection on the moments of the one order k relaxing at its own rate s_k (first order for
+// the phase fields and the charge, second order for the flow).
+template <class L, class T, bool EHD, bool STORE, bool NT, bool HIGH>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
   using ML = MomLayout<L>;
   constexpr int Q = L::Q;
@@ -160,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
         Pyz += eyq * ezq * dq;
       }
     }
-    const T om = T(1) - s_nu;
+    const T om = (HIGH ? p.s_high : T(1)) - s_nu;
     if (STORE) {
       T* r = a.rec;
       r[(int64_t)ML::DRHO * N + node] = drho;
@@ -197,12 +203,16 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
       } else {
         corr = T(0.25) * (iz == 0 ? exq * eyq * Pxy : (iy == 0 ? exq * ezq * Pxz : eyq * ezq * Pyz));
       }
-      emit(0, q, geq + T(0.5) * fq + om * corr);
+      if (HIGH)
+        emit(0, q, p.s_high * geq + (T(1) - T(0.5) * p.s_high) * fq + (T(1) - p.s_high) * gq[q] + om * corr);
+      else
+        emit(0, q, geq + T(0.5) * fq + om * corr);
     }
   }
 
   // ---- a8: phase fields (Eqs. 15-18).  G_i = cs2 F_Phi_i + d(Phi_i u)/dt; first-order raw
-  // moments at s_phi, others at 1: f* = f_eq + C/2 + (1 - s_phi)/2 e.J on the axis links.
+  // moments at s_phi, others at 1: f* = f_eq + C/2 + (1 - s_phi)/2 e.J on the axis links
+  // (HIGH: f* = s_high f_eq + (1 - s_high/2) C + (1 - s_high) f + (s_high - s_phi)/2 e.J).
   {
     T nrm[3][3], amag[3];
 #pragma unroll
@@ -218,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
     for (int c = 0; c < 3; ++c) tot[c] = amag[0] * nrm[0][c] + amag[1] * nrm[1][c] + amag[2] * nrm[2][c];
     T den = pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2];
     if (!(den > T(0))) den = T(1);
-    const T om = T(1) - p.s_phi;
+    const T om = (HIGH ? p.s_high : T(1)) - p.s_phi;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const T share = pc[i] * pc[i] / den;
@@ -250,7 +260,12 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
         const T w = T(L::w36[q]) / T(36);
         const T eu = T(ix) * u[0] + T(iy) * u[1] + T(iz) * u[2];
         const T eG = T(ix) * G[0] + T(iy) * G[1] + T(iz) * G[2];
-        T val = w * pc[i] * (T(1) + T(3) * eu) + T(1.5) * w * eG;
+        T val;
+        if (HIGH)
+          val = p.s_high * w * pc[i] * (T(1) + T(3) * eu) + (T(3) - T(1.5) * p.s_high) * w * eG +
+                (T(1) - p.s_high) * fq[q];
+        else
+          val = w * pc[i] * (T(1) + T(3) * eu) + T(1.5) * w * eG;
         if (ix * ix + iy * iy + iz * iz == 1) val += T(0.5) * om * (T(ix) * J[0] + T(iy) * J[1] + T(iz) * J[2]);
         emit(1 + i, q, val);
       }
@@ -282,14 +297,19 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
       J[c] = jh[c] - rq * u[c] + T(0.5) * dru[c];
     }
     const T src = Qs + T(0.5) * a.dt_on * (Qs - a.q_prev[node]);
-    const T om = T(1) - p.s_e;
+    const T om = (HIGH ? p.s_high : T(1)) - p.s_e;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int ix = L::ex[q], iy = L::ey[q], iz = L::ez[q];
       const T w = T(L::w36[q]) / T(36);
       const T eu = T(ix) * u[0] + T(iy) * u[1] + T(iz) * u[2];
       const T eR = T(ix) * dru[0] + T(iy) * dru[1] + T(iz) * dru[2];
-      T val = w * rq * (T(1) + T(3) * eu) + T(1.5) * w * eR + w * src;
+      T val;
+      if (HIGH)
+        val = p.s_high * w * rq * (T(1) + T(3) * eu) + (T(3) - T(1.5) * p.s_high) * w * eR +
+              (T(1) - p.s_high) * hq[q] + w * src;
+      else
+        val = w * rq * (T(1) + T(3) * eu) + T(1.5) * w * eR + w * src;
       if (ix * ix + iy * iy + iz * iz == 1) val += T(0.5) * om * (T(ix) * J[0] + T(iy) * J[1] + T(iz) * J[2]);
       emit(4, q, val);
     }

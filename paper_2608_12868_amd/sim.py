@@ -32,7 +32,25 @@ def make_structs(dim, n, periodic, precision, params):
         p.electrode_volts[k] = float(params["electrode_volts"][k])
     p.poisson_max_iter = int(params["poisson_max_iter"])
     p.poisson_check_every = int(params["poisson_check_every"])
+    p.s_high = float(params.get("s_high", 1.0))
+    for i, v in enumerate(params.get("rho", (1.0, 1.0, 1.0))):
+        p.rho[i] = float(v)
     return lat, p
+
+
+def preset(name, seed=0):
+    """The library's host-only workload preset: (lattice, params, flags, phi) as ctypes structs
+    and numpy arrays (ehdlb_preset)."""
+    pid = L.PRESETS[name]
+    lat, p = L.Lattice(), L.Params()
+    st = L.lib().ehdlb_preset(pid, C.byref(lat), C.byref(p), None, None, int(seed))
+    if st != L.OK:
+        raise L.EhdlbError(st, f"ehdlb_preset rejected {name}")
+    N = lat.n[0] * lat.n[1] * lat.n[2]
+    flags = np.zeros(N, np.uint8)
+    phi = np.zeros((3, N), np.float64)
+    L.lib().ehdlb_preset(pid, C.byref(lat), C.byref(p), flags.ctypes.data, phi.ctypes.data, int(seed))
+    return lat, p, flags, phi
 
 
 class Context:
@@ -119,11 +137,17 @@ class Simulation(Context):
     def step(self, n=1):
         self._chk(L.lib().ehdlb_step(self.h, int(n)))
 
-    def field(self, name):
+    def field(self, name, device=False):
+        """One field as float64: a numpy array, or (device=True) a torch tensor on the
+        simulation's device written by the library on its stream."""
         fid = L.FIELDS[name]
         size = int(L.lib().ehdlb_num_populations(self.h)) if name == "pops" else self.N
+        if device:
+            out = self.torch.empty(size, dtype=self.torch.float64, device=self.device)
+            self._chk(L.lib().ehdlb_read_field(self.h, fid, C.c_void_p(out.data_ptr()), 1))
+            return out
         out = np.empty(size, np.float64)
-        self._chk(L.lib().ehdlb_read_field(self.h, fid, out.ctypes.data))
+        self._chk(L.lib().ehdlb_read_field(self.h, fid, out.ctypes.data, 0))
         return out
 
     def observables(self, strict=True):

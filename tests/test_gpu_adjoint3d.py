@@ -102,3 +102,21 @@ def test_adjoint3d_fp32_against_fp64():
     print("3D fp32 vs fp64 adjoint", rel, g32, g64, flush=True)
     assert np.all(np.isfinite(g32))
     assert rel <= 1e-2
+
+
+def test_adjoint3d_higher_moment_rate_matches_oracle_autograd():
+    from oracle import Oracle
+    from oracle.adjoint import schedule_gradient
+    case = make_case("c3s", precision="fp64")
+    over = dict(s_high=0.8, tau_flow=(0.8, 1.3, 0.65))
+    T = t_total = 8
+    print("case c3s", case.n, "T", T, "s_high 0.8", flush=True)
+    g_gpu, ob = _gpu_grad(case, SCHED, T, t_total, K=3, **over)
+    p = dict(case.params)
+    p.update(over)
+    o = Oracle(case.dim, case.n, case.periodic, p, case.flags)
+    g_ref, xc, vc = schedule_gradient(o, case.phi, SCHED, T, t_total, GX, GV)
+    g_ref = g_ref.numpy()
+    err = np.abs(g_gpu - g_ref).max() / np.abs(g_ref).max()
+    print("3D adjoint (s_high 0.8) vs oracle autograd", err, flush=True)
+    assert err <= 1e-8

@@ -201,3 +201,37 @@ def test_fp64_zero_potential():
     ob = sim.observables()
     assert ob["poisson_iters"] == 0 and ob["poisson_residual"] == 0.0
     _compare(sim, o, s, aux, FP64_TOL)
+
+
+@pytest.mark.parametrize("name,steps,s_high", [("c2s", 120, 1.3), ("c3s", 10, 0.8)])
+def test_fp64_parity_higher_moment_rate(name, steps, s_high):
+    """The higher raw moments away from rate 1 (s_high: orders >= 2 of the phase fields and the
+    charge, >= 3 of the flow), with per-phase viscosities: fields and populations."""
+    case = make_case(name, precision="fp64")
+    over = dict(s_high=s_high, tau_flow=(0.8, 1.3, 0.65))
+    print("case", name, case.n, "steps", steps, "s_high", s_high, flush=True)
+    sim = _gpu(case, **over)
+    sim.step(steps)
+    o, s, aux = gu.oracle_run(case, steps, params=over)
+    _compare(sim, o, s, aux, FP64_TOL)
+    assert gu.rel_err(sim.field("pops"), gu.oracle_pops(o, s)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_read_field_to_device_memory(precision):
+    """Every field read into device memory equals the host read-out bit for bit (after an odd
+    number of steps, when the velocity and Ohmic source come from the slots the first step
+    writes; their solid nodes read as zero)."""
+    import torch
+    from paper_2608_12868_amd import _lib as L
+    case = make_case("c2s", precision=precision)
+    sim = _gpu(case, precision=precision, poisson_tol=1e-13 if precision == "fp64" else 1e-5)
+    sim.step(7)
+    for name in L.FIELDS:
+        host = sim.field(name)
+        if name != "pops":
+            assert np.all(host[case.flags != 0] == 0.0), name
+        dev = sim.field(name, device=True)
+        torch.cuda.synchronize()
+        assert dev.device.type == "cuda" and dev.dtype == torch.float64
+        assert np.array_equal(dev.cpu().numpy(), host), name

@@ -104,17 +104,47 @@ def test_config3_fields_vs_oracle(precision, tol, names):
         g = json.load(f)
     case = make_case("c3", precision=precision)
     sim = _sim(case, precision, poisson_tol=1e-14 if precision == "fp64" else 1e-5)
-    steps = g["steps_done"]
-    print("c3", precision, case.n, steps, "steps vs stored oracle fields", flush=True)
-    sim.step(steps)
+    records = g.get("fields_at") or {str(g["steps_done"]): g["fields"]}
     idx = np.asarray(g["sample_nodes"])
     worst = 0.0
-    for name in names:
-        ref = g["fields"][name]
-        a = sim.field(name)[idx]
-        err = float(np.abs(a - np.asarray(ref["sample"])).max() / max(ref["max_abs"], 1e-300))
-        print(f"  {name}: {err:.3e}", flush=True)
-        worst = max(worst, err)
+    t = 0
+    for step in sorted(int(k) for k in records):
+        print("c3", precision, case.n, step, "steps vs stored oracle fields", flush=True)
+        sim.step(step - t)
+        t = step
+        for name in names:
+            ref = records[str(step)][name]
+            a = sim.field(name)[idx]
+            err = float(np.abs(a - np.asarray(ref["sample"])).max() / max(ref["max_abs"], 1e-300))
+            print(f"  {name}: {err:.3e}", flush=True)
+            worst = max(worst, err)
+    assert worst <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_config3_centroid_vs_oracle(precision, tol):
+    """The droplet centroid at 256x128x96 every 10 steps over the stored oracle trajectory."""
+    with open(GOLD3) as f:
+        g = json.load(f)
+    traj = g.get("trajectory")
+    if not traj or traj[-1]["step"] < 10:
+        pytest.skip("no stored 3D oracle trajectory")
+    case = make_case("c3", precision=precision)
+    sim = _sim(case, precision, poisson_tol=1e-14 if precision == "fp64" else 1e-5)
+    print("c3", precision, "centroid vs oracle to step", traj[-1]["step"], flush=True)
+    worst = worst_abs = 0.0
+    t = 0
+    for rec in traj:
+        sim.step(rec["step"] - t)
+        t = rec["step"]
+        ob = sim.observables()
+        ref = np.asarray(rec["centroid"])
+        worst = max(worst, float(np.linalg.norm(ob["centroid"] - ref) / np.linalg.norm(ref)))
+        worst_abs = max(worst_abs, float(np.linalg.norm(ob["centroid"] - ref)))
+        assert np.allclose(ob["mass"], rec["mass"], rtol=1e-12 if precision == "fp64" else 1e-5, atol=0)
+    disp = float(np.linalg.norm(np.asarray(traj[-1]["centroid"]) - np.asarray(traj[0]["centroid"])))
+    print(f"  max relative centroid error {worst:.3e}; absolute {worst_abs:.3e} lu "
+          f"(displacement {disp:.4f} lu)", flush=True)
     assert worst <= tol
 
 

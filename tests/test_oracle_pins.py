@@ -370,16 +370,18 @@ def test_v12_charge_advection_diffusion():
 
 
 # ---------------------------------------------------------------- V5 at tau != 1, 2D and 3D
-@pytest.mark.parametrize("dim,tau", [(2, 0.8), (2, 1.3), (3, 0.8), (3, 1.3)])
-def test_v5_poiseuille_tau_and_wall_location(dim, tau):
+@pytest.mark.parametrize("dim,tau,s_high", [(2, 0.8, 1.0), (2, 1.3, 1.0), (3, 0.8, 1.0), (3, 1.3, 1.0),
+                                            (2, 1.0, 1.6), (3, 0.8, 1.3)])
+def test_v5_poiseuille_tau_and_wall_location(dim, tau, s_high):
     """Body-force channel flow away from tau = 1 (flow second-order moments at 1/tau, higher
     moments at 1), walls normal to y (2D) or z (3D, D3Q19).  The steady profile is a parabola of
     curvature -F/nu, nu = (tau - 1/2)/3, and with halfway bounce-back its zeros sit where the
     two-relaxation-time analysis of bounce-back puts them: a channel of nominal width H between
     the half-way planes behaves as one of width sqrt(H^2 + (16 Lambda - 3)/3), Lambda =
     (tau_even - 1/2)(tau_odd - 1/2) = (tau - 1/2)/2 (Ginzburg, Verhaeghe & d'Humieres, Commun.
-    Comput. Phys. 3, 2008).  A second-order rate other than 1/tau moves the curvature, a
-    third-order rate other than 1 moves the zeros."""
+    Comput. Phys. 3, 2008), with tau_odd = 1/s_high the relaxation time of the third-order
+    moments (1 by default).  A second-order rate other than 1/tau moves the curvature, a
+    third-order rate other than s_high moves the zeros."""
     from inputs import default_params
     F, nw = 1e-6, 12
     n = (4, nw, 1) if dim == 2 else (4, 4, nw)
@@ -392,7 +394,7 @@ def test_v5_poiseuille_tau_and_wall_location(dim, tau):
     phi[2] = 1.0
     phi[:, flags != FLUID] = 0
     periodic = (1, 0, 0) if dim == 2 else (1, 1, 0)
-    params = default_params(dim, body_force=(F, 0.0, 0.0), tau_flow=(tau, tau, tau))
+    params = default_params(dim, body_force=(F, 0.0, 0.0), tau_flow=(tau, tau, tau), s_high=s_high)
     o, s, aux = _run((n, periodic, params, flags, phi), 2500)
     u = aux["u"][0].numpy()
     prof = np.array([u[(h == k) & (x == 0) & (y == 0 if dim == 3 else True)][0] for k in range(1, nw - 1)])
@@ -400,7 +402,7 @@ def test_v5_poiseuille_tau_and_wall_location(dim, tau):
     c = np.polyfit(hh, prof, 2)
     nu = (tau - 0.5) / 3.0
     assert abs(2 * c[0] / (-F / nu) - 1) < 1e-9
-    lam = (tau - 0.5) * 0.5
+    lam = (tau - 0.5) * (1.0 / s_high - 0.5)
     weff = math.sqrt((nw - 2) ** 2 + (16 * lam - 3) / 3)
     roots = np.sort(np.roots(c).real)
     mid = (nw - 1) / 2.0
