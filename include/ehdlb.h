@@ -186,6 +186,21 @@ size_t ehdlb_num_populations(const ehdlb_ctx* ctx);
  * Synchronises.  Returns ENONFINITE / ENOCONV (sticky) after filling *out. */
 ehdlb_status ehdlb_observables(ehdlb_ctx* ctx, ehdlb_obs* out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the droplet observables of
+ * ehdlb_observables, computed by the same kernels in the same order, enqueued on
+ * the bound stream without any host synchronisation or allocation; their
+ * per-block partials live in a library-held device array (9 MiB per device,
+ * kept until the process ends) instead of the workspace.  dev_out: 12 float64 in
+ * device memory (8-byte aligned, caller-owned): mass[3], centroid[3],
+ * velocity[3], total charge, max |sum Phi - 1|, count of fluid nodes with a
+ * non-finite value (the context's sticky flags are not updated).  EINVAL for a
+ * lattice above 2^24 nodes (16,777,216) or a null/misaligned dev_out; ESTATE
+ * before set_phase or with another device current than at ehdlb_bind.  Every
+ * call on one GPU shares that array: calls that overlap on one GPU (other
+ * contexts, other streams or threads) race and must be serialised by the caller. */
+ehdlb_status ehdlb_observables_device(ehdlb_ctx* ctx, double* dev_out);
+
 /* Full state (populations, previous-step fields, potential, step counter) as
  * an opaque device blob of ehdlb_state_bytes bytes; save/load copy on the
  * bound stream (device to device). */

@@ -69,6 +69,7 @@ SIGNATURES = {
     "ehdlb_read_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
     "ehdlb_num_populations": (C.c_size_t, [C.c_void_p]),
     "ehdlb_observables": (C.c_int, [C.c_void_p, C.POINTER(Obs)]),
+    "ehdlb_observables_device": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ehdlb_state_bytes": (C.c_size_t, [C.c_void_p]),
     "ehdlb_save_state": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ehdlb_load_state": (C.c_int, [C.c_void_p, C.c_void_p]),

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 #include <type_traits>
@@ -56,6 +57,21 @@ struct MGLevel {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------- library-held scratch
+// Device scratch of ehdlb_observables_device (for callers that cannot allocate): the observables'
+// per-block FP64 partials (kObs sums and one maximum per block of kBlock nodes) and the final
+// sums, for lattices of at most kNoAllocMaxNodes nodes (9 MiB per device, held until the process
+// ends).  Host code never passes the array's name to a kernel: each device's address comes from
+// hipGetSymbolAddress at ehdlb_bind, with that device current, and is kept in g_scratch.
+constexpr int64_t kNoAllocMaxNodes = (int64_t)1 << 24;
+constexpr int64_t kNoAllocBlocks = kNoAllocMaxNodes / ehd::kBlock;
+constexpr int64_t kNoAllocRed = 64;  // final sums (kObs) and maximum
+constexpr size_t kNoAllocDoubles = (size_t)kNoAllocBlocks * (ehd::kObs + 1) + kNoAllocRed;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+constexpr int kMaxDevices = 64;
+static double* g_scratch[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
 struct ehdlb_ctx {
   ehdlb_lattice lat{};
   ehdlb_params prm{};
@@ -96,6 +112,7 @@ struct ehdlb_ctx {
     int64_t solves = 0, iters = 0;  // statistics (ehdlb_solver_stats)
     double max_rel0 = 0.0;
   } cg_hist[2];
+  int device = -1;     // HIP device current at ehdlb_bind
   ehd::CgCtl hctl{};  // host copy of the solve's control block
   ehd::CgCtl* hctl_pin = nullptr;  // pinned staging of the control block (allocated at bind)
   hipEvent_t ev_ctl = nullptr;     // marks the control block's copy in the stream
@@ -846,25 +863,32 @@ static ehdlb_status moments_now(ehdlb_ctx* c, T* drho) {
   return EHDLB_OK;
 }
 
+// The observables' reductions: moments of the current populations, per-block FP64 partials
+// (sums [nblocks][kObs] at psum, maxima [nblocks] at pmax) and their fixed-order sums into red
+// (kObs sums, then the maximum).
 template <class LT, class T, bool EHD>
-static ehdlb_status observables_impl(ehdlb_ctx* c, ehdlb_obs* o) {
+static ehdlb_status observables_reduce(ehdlb_ctx* c, double* psum, double* pmax, double* red) {
   ehdlb_status st = moments_now<LT, T, EHD>(c, nullptr);
   if (st) return st;
   const int64_t N = c->N;
   const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
   const int pi = (int)(c->t & 1), pp = 1 - pi;
-  // per-block partials: sums [nblocks][kObs] in the FP64 scratch, maxima [nblocks] in the
-  // reduction buffer
-  double* psum = c->ptr<double>(c->off_dbl);
-  double* pmax = c->ptr<double>(c->off_part);
   const int nb = nblocks(N);
   hipLaunchKernelGGL((k_obs<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, c->stream, dm, c->ptr<uint8_t>(c->off_flags),
                      c->ptr<T>(c->off_phi[pi]), c->ptr<T>(c->off_phi[pp]), c->ptr<T>(c->off_u[pp]),
                      c->ptr<T>(c->off_rho[pi]), psum, pmax);
-  double* red = c->ptr<double>(c->off_red);
   hipLaunchKernelGGL((k_final_wide<kObs, false>), dim3(1), dim3(kFinalWide), 0, c->stream, psum, nb, red);
   hipLaunchKernelGGL((k_final_wide<1, true>), dim3(1), dim3(kFinalWide), 0, c->stream, pmax, nb, red + kObs);
   LAUNCHCHK();
+  return EHDLB_OK;
+}
+
+template <class LT, class T, bool EHD>
+static ehdlb_status observables_impl(ehdlb_ctx* c, ehdlb_obs* o) {
+  // partials in the workspace: sums in the FP64 scratch, maxima in the reduction buffer
+  double* red = c->ptr<double>(c->off_red);
+  ehdlb_status st = observables_reduce<LT, T, EHD>(c, c->ptr<double>(c->off_dbl), c->ptr<double>(c->off_part), red);
+  if (st) return st;
   double h[kObs + 1];
   HIPCHK(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -904,6 +928,33 @@ template <class LT, class T, bool EHD>
 struct ObsFn {
   static ehdlb_status run(ehdlb_ctx* c, ehdlb_obs* o) { return observables_impl<LT, T, EHD>(c, o); }
 };
+// droplet observables from the final sums, as ehdlb_observables forms them on the host:
+// out = mass[3], centroid[3], velocity[3], total charge, max |sum Phi - 1|, non-finite count
+__global__ void k_obs_finish(const double* __restrict__ red, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < 3; ++i) out[i] = red[i];
+  for (int a = 0; a < 3; ++a) out[3 + a] = red[3 + a] / red[0];
+  for (int a = 0; a < 3; ++a) out[6 + a] = red[9] != 0.0 ? red[6 + a] / red[9] : 0.0;
+  out[9] = red[10];
+  out[10] = red[kObs];
+  out[11] = red[11];
+}
+
+template <class LT, class T, bool EHD>
+struct ObsDevFn {
+  static ehdlb_status run(ehdlb_ctx* c, double* out) {
+    double* base = g_scratch[c->device];
+    double* psum = base;
+    double* pmax = base + (size_t)kNoAllocBlocks * kObs;
+    double* red = pmax + kNoAllocBlocks;
+    ehdlb_status st = observables_reduce<LT, T, EHD>(c, psum, pmax, red);
+    if (st) return st;
+    hipLaunchKernelGGL(k_obs_finish, dim3(1), dim3(64), 0, c->stream, (const double*)red, out);
+    LAUNCHCHK();
+    return EHDLB_OK;
+  }
+};
+
 template <class LT, class T, bool EHD>
 struct InitFn {
   static ehdlb_status run(ehdlb_ctx* c, int dummy) {
@@ -1358,6 +1409,18 @@ ehdlb_status ehdlb_bind(ehdlb_ctx* c, void* ws, size_t bytes, void* stream) {
   if (!ws) return fail(c, EHDLB_EINVAL, "null workspace");
   if (((uintptr_t)ws) % 256 != 0) return fail(c, EHDLB_EINVAL, "workspace must be 256-byte aligned");
   if (bytes < c->total) return fail(c, EHDLB_ENOMEM, "workspace too small");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, EHDLB_EINVAL, "device index beyond the library's table");
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+      void* p = nullptr;
+      HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      g_scratch[dev] = static_cast<double*>(p);
+    }
+  }
+  c->device = dev;
   c->ws = (char*)ws;
   c->ws_bytes = bytes;
   c->stream = (hipStream_t)stream;
@@ -1646,6 +1709,21 @@ ehdlb_status ehdlb_observables(ehdlb_ctx* c, ehdlb_obs* o) {
   if (c->sticky & 1) return fail(c, EHDLB_ENONFINITE, "non-finite field");
   if (c->sticky & 2) return fail(c, EHDLB_ENOCONV, "potential solve hit its iteration cap");
   return EHDLB_OK;
+}
+
+ehdlb_status ehdlb_observables_device(ehdlb_ctx* c, double* dev_out) {
+  if (!c) return EHDLB_EINVAL;
+  if (!dev_out || ((uintptr_t)dev_out) % 8) return fail(c, EHDLB_EINVAL, "null or misaligned device output");
+  if (!c->have_state) return fail(c, EHDLB_ESTATE, "observables before set_phase");
+  if (c->N > kNoAllocMaxNodes)
+    return fail(c, EHDLB_EINVAL, "ehdlb_observables_device: the lattice has " + std::to_string(c->N) +
+                                     " nodes, more than the library-held scratch serves (" +
+                                     std::to_string(kNoAllocMaxNodes) + ")");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != c->device || !g_scratch[dev])
+    return fail(c, EHDLB_ESTATE, "ehdlb_observables_device: call it with the bound device current");
+  return dispatch<ObsDevFn>(c, dev_out);
 }
 
 // state blob: [256-byte header: t, magic, N, sizeof(T)][current populations][field slots
