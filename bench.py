@@ -1,6 +1,6 @@
 """Benchmark of the ternary EHD lattice-Boltzmann step on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c2-fp64|c1] [--adjoint c4|c5|none]
+    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c2-fp64|c1] [--adjoint c4,c5|c5full|none]
 
 Prints one JSON line: throughput in MLUPS (million lattice-node updates per
 second, all nodes counted; fluid-only MLUPS beside it) of whole steps (moments
@@ -88,33 +88,41 @@ def copy_ceiling(nbytes=1 << 30, reps=10):
     return dict(bytes_per_copy=2 * nbytes, gbs=2 * nbytes / (ms * 1e-3) / 1e9)
 
 
+# adjoint legs: workload, T, K, central-difference directions, FP64 adjoint, every warm start, description
 ADJOINT = {
-    "c4": ("c4", 4000, 100, 3, "2D D2Q9 ternary EHD LB, 512x256 (pillars, droplet R=40, electrode), FP32-deviation "
-                               "storage, 64-segment voltage schedule, T=4000, checkpoint every 100 steps"),
-    "c5": ("c5", 2000, 50, 1, "3D D3Q19 ternary EHD LB, 384x192x128 (pillars pitch 12, droplet R=48, electrode "
-                              "strip), FP32-deviation storage, 32-segment schedule, T=2000, checkpoint every 50"),
+    "c4": ("c4", 4000, 100, 3, True, True,
+           "2D D2Q9 ternary EHD LB, 512x256 (pillars, droplet R=40, electrode), FP32-deviation storage, 64-segment "
+           "voltage schedule, T=4000, checkpoint every 100 steps"),
+    "c5": ("c5", 200, 50, 1, False, False,
+           "3D D3Q19 ternary EHD LB, 384x192x128 (pillars pitch 12, droplet R=48, electrode strip), FP32-deviation "
+           "storage, the 32-segment schedule over T=200 (of its 2000), checkpoint every 50"),
+    "c5full": ("c5", 2000, 50, 1, False, True,
+               "3D D3Q19 ternary EHD LB, 384x192x128 (pillars pitch 12, droplet R=48, electrode strip), "
+               "FP32-deviation storage, 32-segment schedule, T=2000, checkpoint every 50"),
 }
+FD_H = (1e-3, 1e-4)   # central-difference steps: 1e-4 as the workload names it, 1e-3 above its round-off floor
 
 
-def adjoint_leg(key, fd_h=1e-4, seed=1):
-    """Cost of dL/dV for L = (x_c(T) - x*)^2 (x* = initial centroid + 5 lu), FP32 path, with
-    each forward warm start (projected onto the last four potentials then at least one CG
-    iteration, the default; the projection alone; previous potential; extrapolated from the
-    last two): plain forward,
-    checkpointed forward and reverse sweep (recompute included), timed with device syncs; each
-    gradient's error against the FP64 adjoint (where it fits in memory) and the directional
-    derivatives against central differences of the FP64 forward."""
+def adjoint_leg(key, seed=1):
+    """Cost of dL/dV for L = (x_c(T) - x*)^2 (x* = initial centroid + 5 lu), FP32 path: plain
+    forward, checkpointed forward and reverse sweep (recompute included), timed with device
+    syncs, with the default forward warm start (projected onto the last four potentials then at
+    least one CG iteration) and, for the 2D leg, the other three (the projection alone; previous
+    potential; extrapolated from the last two); each gradient's error against the FP64 adjoint
+    (2D leg) and the directional derivatives against central differences of the FP64 forward at
+    each step of FD_H."""
     import numpy as np
     import torch
     from inputs import make_case
     from paper_2608_12868_amd import Simulation
-    name, T, K, ndir, desc = ADJOINT[key]
+    name, T, K, ndir, with_fp64_adjoint, all_modes, desc = ADJOINT[key]
+    torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
     case = make_case(name)
     runs = {}
     target = None
-    for mode, label in ((2, "warm_projected"), (3, "warm_projected_only"), (0, "warm_previous"),
-                        (1, "warm_extrapolated")):
+    modes = ((2, "warm_projected"), (3, "warm_projected_only"), (0, "warm_previous"), (1, "warm_extrapolated"))
+    for mode, label in (modes if all_modes else modes[:1]):
         sim = Simulation.from_case(case, precision="fp32", poisson_tol=1e-5)
         sim.set_solver_options(warm_start=mode)
         sim.set_schedule(0, case.schedule, case.t_total)
@@ -171,7 +179,7 @@ def adjoint_leg(key, fd_h=1e-4, seed=1):
         t64["forward_s"] = time.perf_counter() - t0
         return float((s64.observables()["centroid"][0] - target) ** 2)
 
-    if key == "c4":
+    if with_fp64_adjoint:
         loss(case64.schedule)
         s64.set_phase(case64.phi)
         s64.set_schedule(0, case64.schedule, case64.t_total)
@@ -196,31 +204,39 @@ def adjoint_leg(key, fd_h=1e-4, seed=1):
     for _ in range(ndir):
         d = rng.standard_normal(len(case.schedule))
         d /= np.linalg.norm(d)
-        f = (loss(case64.schedule + fd_h * d) - loss(case64.schedule - fd_h * d)) / (2 * fd_h)
+        row = {}
+        for h in FD_H:
+            f = (loss(case64.schedule + h * d) - loss(case64.schedule - h * d)) / (2 * h)
+            # relative to the directional derivative, and to the gradient's norm (the first is
+            # inflated on directions where the derivative is much smaller than the gradient)
+            r_h = {"fd": f}
+            for label, r in runs.items():
+                r_h[label] = float(r["grad"] @ d)
+                r_h[label + "_rel_err"] = abs(r_h[label] - f) / abs(f)
+                r_h[label + "_err_over_norm"] = abs(r_h[label] - f) / float(np.linalg.norm(r["grad"]))
+            if g64 is not None:
+                r_h.update(fp64_adjoint=float(g64 @ d), fp64_rel_err=abs(float(g64 @ d) - f) / abs(f),
+                           fp64_err_over_norm=abs(float(g64 @ d) - f) / float(np.linalg.norm(g64)))
+            row[f"h={h:g}"] = r_h
         print(f"adjoint leg {key}: central difference {len(fd) + 1}/{ndir} done", file=sys.stderr, flush=True)
-        # relative to the directional derivative, and to the gradient's norm (the first is
-        # inflated on directions where the derivative is much smaller than the gradient)
-        row = {"fd": f}
-        for label, r in runs.items():
-            row[label] = float(r["grad"] @ d)
-            row[label + "_rel_err"] = abs(row[label] - f) / abs(f)
-            row[label + "_err_over_norm"] = abs(row[label] - f) / float(np.linalg.norm(r["grad"]))
-        if g64 is not None:
-            row.update(fp64_adjoint=float(g64 @ d), fp64_rel_err=abs(float(g64 @ d) - f) / abs(f),
-                       fp64_err_over_norm=abs(float(g64 @ d) - f) / float(np.linalg.norm(g64)))
         fd.append(row)
-    out = {"workload": desc, "dtype": "f32", "adjoint_workspace_gb": ws, "peak_hbm_gb": peak32, "fd_h": fd_h,
-           "fd_directions": fd}
+    out = {"workload": desc, "dtype": "f32", "T": T, "K": K, "adjoint_workspace_gb": ws, "peak_hbm_gb": peak32,
+           "fd_h": list(FD_H), "fd_directions": fd}
+
+    def worst(key_, h):
+        return max(row[f"h={h:g}"][key_] for row in fd)
     for label, r in runs.items():
         g = r.pop("grad")
-        r["fd_rel_err_max"] = max(row[label + "_rel_err"] for row in fd)
-        r["fd_err_over_norm_max"] = max(row[label + "_err_over_norm"] for row in fd)
+        for h in FD_H:
+            r[f"fd_rel_err_max_h={h:g}"] = worst(label + "_rel_err", h)
+            r[f"fd_err_over_norm_max_h={h:g}"] = worst(label + "_err_over_norm", h)
         if g64 is not None:
             r["grad_rel_err_vs_fp64_adjoint"] = float(np.abs(g - g64).max() / np.abs(g64).max())
         out[label] = r
     if g64 is not None:
-        t64["fd_rel_err_max"] = max(row["fp64_rel_err"] for row in fd)
-        t64["fd_err_over_norm_max"] = max(row["fp64_err_over_norm"] for row in fd)
+        for h in FD_H:
+            t64[f"fd_rel_err_max_h={h:g}"] = worst("fp64_rel_err", h)
+            t64[f"fd_err_over_norm_max_h={h:g}"] = worst("fp64_err_over_norm", h)
         out["fp64"] = t64
     return out
 
@@ -251,13 +267,16 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--spin-up", type=int, default=200,
+                    help="steps run before the warm-up (not timed): the state the timed steps start from")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true",
                     help="skip the plain 1 GiB device copy (practical bandwidth ceiling; the "
                          "calibration kernel of the rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
-    ap.add_argument("--adjoint", default="c4", choices=sorted(ADJOINT) + ["none"],
-                    help="adjoint leg: c4 (2D, default, about half a minute), c5 (3D at scale: "
-                         "about 250 GB of HBM and two minutes), none")
+    ap.add_argument("--adjoint", default="c4,c5",
+                    help="comma-separated adjoint legs: c4 (2D 512x256, T = 4000, every forward warm "
+                         "start), c5 (3D 384x192x128 over T = 200), c5full (3D at T = 2000: about "
+                         "250 GB of HBM and two minutes), or none")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the step is built for a single MI355X (multi-GPU slab "
@@ -275,6 +294,10 @@ def main():
     if prec == "fp32":
         over["poisson_tol"] = 1e-5
     sim = Simulation.from_case(case, precision=prec, **over)
+    # the configured runs are thousands of steps long; their first ~50 steps carry a start-up
+    # transient of the potential solve (from rest: about 2 CG iterations per step instead of 1.2),
+    # so the state is advanced first and the timed steps are representative of the whole run
+    sim.step(args.spin_up)
     sim.step(args.warmup)
     torch.cuda.synchronize()
     sim.solver_stats(reset=True)
@@ -311,7 +334,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "lattice": list(case.n), "nodes": N, "fluid_nodes": nfluid},
+        "config": {"workload": desc, "lattice": list(case.n), "nodes": N, "fluid_nodes": nfluid,
+                   "spin_up_steps": args.spin_up, "steps_configured": case.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "phase_ms_per_step": {"moments_ghosts": ms3[0] / max(nt, 1), "potential_solve": ms3[1] / max(nt, 1),
@@ -327,7 +351,11 @@ def main():
     del sim
     torch.cuda.empty_cache()
     if args.adjoint != "none":
-        out["adjoint"] = adjoint_leg(args.adjoint)
+        legs = [k for k in args.adjoint.split(",") if k]
+        for k in legs:
+            if k not in ADJOINT:
+                ap.error(f"unknown adjoint leg {k}")
+        out["adjoint"] = {k: adjoint_leg(k) for k in legs}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
