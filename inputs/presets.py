@@ -194,7 +194,9 @@ def make_case(name: str, seed: int = 0, precision: str | None = None, **over) ->
     c1s 2D 64x32, c2s 2D 128x64, c3s 3D 48x32x24, c4s 2D 96x48 with a schedule.
     """
     alpha_star = over.pop("alpha_star", 1e-4)
-    volts = over.pop("volts", 0.05)
+    volts = over.pop("volts", None)
+    if volts is None:
+        volts = {"m2": 1.0, "m2s": 0.7}.get(name, 0.05)
     jitter = over.pop("jitter", None)
     if name in ("c1", "c1s"):
         n = (128, 64, 1) if name == "c1" else (64, 32, 1)
@@ -270,6 +272,32 @@ def make_case(name: str, seed: int = 0, precision: str | None = None, **over) ->
         if name == "c5":
             sched = voltage_schedule(seed, 32)
             t_total = steps
+    elif name in ("m2", "m2s"):
+        # migrating workload: a droplet sliding on a flat lubricant film (the lubricant wets the
+        # solid and the film is thicker than the interface, so the droplet never touches it: the
+        # regime I_os(w)/I_s < 0 of the drag model), pulled by top-wall electrodes; tensions and
+        # voltage raised so that it travels 3 R0 in about 2e5 steps at an electric capillary
+        # number eps_a (V/L)^2 R0 / gamma ~ 0.3 (m2: 1.0 lu; m2s: 0.7 lu).  Electrode 0 lies 3 R0 ahead of the droplet's
+        # front, electrode 1 as far behind its back (for two-electrode switching).
+        dim = 2
+        n, radius, xc, film = ((384, 64, 1), 12.0, 120.0, 8) if name == "m2" else ((192, 48, 1), 8.0, 64.0, 6)
+        gap, elen = int(3 * radius), 64 if name == "m2" else 32
+        e0 = int(xc + radius) + gap
+        e1_hi = int(xc - radius) - gap
+        electrode = (e0, e0 + elen)
+        x, y, z = _grid(n)
+        flags = _lis_geometry(dim, n, 0, 1, 0, electrode)
+        top = y == n[1] - 1
+        flags[top & (x >= e1_hi - elen) & (x < e1_hi)] = ELECTRODE0 + 1
+        level = film + 0.5
+        g = 0.01
+        params = default_params(2, gamma12=g, gamma13=g, gamma23=g)
+        phi = _droplet_on_film(dim, n, flags, (xc,), radius, level, params["width"])
+        # charge diffusion 1e-4 (alpha* = 1e-4 would give 1.7e-3 here: a charge layer that
+        # spreads over the droplet and stalls its motion in these lattice units)
+        params.update(ehd=1, charge_diffusion=1e-4, electrode_volts=(volts, 0.0, 0.0, 0.0))
+        steps, prec = (200000, "fp32") if name == "m2" else (60000, "fp32")
+        sched, t_total = None, 0
     else:
         raise KeyError(name)
     if jitter is not None:
@@ -278,10 +306,12 @@ def make_case(name: str, seed: int = 0, precision: str | None = None, **over) ->
         params[k] = v
     periodic = (1, 1, 0) if dim == 3 else (1, 0, 0)
     meta = dict(radius=radius, electrode=electrode)
+    if name in ("m2", "m2s"):
+        meta.update(electrode2=(e1_hi - elen, e1_hi), film=film, channel=n[1] - 2)
     return Case(name=name, dim=dim, n=n, periodic=periodic, precision=precision or prec,
                 params=params, flags=flags, phi=phi, steps=steps, schedule=sched,
                 t_total=t_total, meta=meta)
 
 
 def case_names():
-    return ["c1", "c2", "c3", "c4", "c5", "c1s", "c2s", "c3s", "c4s"]
+    return ["c1", "c2", "c3", "c4", "c5", "c1s", "c2s", "c3s", "c4s", "m2", "m2s"]

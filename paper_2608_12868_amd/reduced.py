@@ -153,3 +153,57 @@ def fit_motion(t, s, m, r0, mu_bar, alpha0, s0, guess=(1.0, 1.0), n_steps=4000):
                         ftol=1e-14, gtol=1e-14)
     c, d = (float(math.exp(x)) for x in res.x)
     return dict(c_drag=c, drive=d, rms=float(np.sqrt(np.mean(res.fun ** 2))) * scale)
+
+
+def overdamped_time(s, v0, alpha0):
+    """Eq. 7 without its inertial term: the time to travel s from rest when drag balances the
+    electric force at every instant, t(s) = (1 - exp(-2 alpha0 s)) / (2 alpha0 v0), with v0 =
+    Lambda K_e C_ele exp(-2 alpha0 S0) / (2 C_drag R0 mu_bar) the balance velocity at the start."""
+    s = np.asarray(s, dtype=np.float64)
+    return (1.0 - np.exp(-2.0 * alpha0 * s)) / (2.0 * alpha0 * v0)
+
+
+def fit_overdamped(t, s, alpha0):
+    """Least-squares fit of the start velocity v0 of the overdamped transport law (Eq. 7 without
+    inertia) to a trajectory S(t) from rest: t_i = g(S_i) / v0 with g(S) = (1 - exp(-2 alpha0 S))
+    / (2 alpha0), linear in 1/v0.  Where the viscous relaxation time m / (2 C_drag R0 mu_bar) is
+    many orders below the travel time (the lattice-unit workloads), a trajectory fixes only this
+    ratio of drive to drag, not C_drag and Lambda separately.  Returns dict(v0, rms_t) with the
+    root-mean-square time residual."""
+    t = np.asarray(t, dtype=np.float64)
+    g = (1.0 - np.exp(-2.0 * alpha0 * np.asarray(s, dtype=np.float64))) / (2.0 * alpha0)
+    v0 = float(g @ g / (g @ t))
+    return dict(v0=v0, rms_t=float(np.sqrt(np.mean((t - g / v0) ** 2))))
+
+
+def drag_to_drive(v0, alpha0, s0, r0, mu_bar):
+    """C_drag / (Lambda K_e C_ele) from the fitted start velocity v0 of fit_overdamped."""
+    return math.exp(-2.0 * alpha0 * s0) / (2.0 * r0 * mu_bar * v0)
+
+
+# ------------------------------------------------------------------ two-electrode switching (Fig. 5b)
+def _leg_time(x_from, x_to, u, alpha0, dist_from, dist_to):
+    """Overdamped travel time between two positions under one electrode pulling with velocity
+    u exp(-2 alpha0 S_e): (exp(2 alpha0 S_from) - exp(2 alpha0 S_to)) / (2 alpha0 u), S the
+    distances to that electrode."""
+    return (math.exp(2.0 * alpha0 * dist_from) - math.exp(2.0 * alpha0 * dist_to)) / (2.0 * alpha0 * u)
+
+
+def two_electrode_switch_times(u, alpha0, half_gap, s_sw, t_sw1=None):
+    """The periodic protocol of the Results (Fig. 5b) in the overdamped form of Eq. 5: a droplet
+    midway between two electrodes at distance half_gap from each is pulled by electrode 1 until
+    its distance to it falls to s_sw (time t_sw1), then by electrode 2 until its distance to that
+    one falls to s_sw (time t_sw2).  u is the pull velocity at zero distance (v0 exp(2 alpha0
+    S0)).  Given t_sw1 (e.g. advanced or delayed), the first leg stops where the droplet is then;
+    returns (t_sw1, t_sw2, position at the first switch), positions measured from the midpoint
+    towards electrode 1.  A t_sw1 at or beyond the electrode's arrival time is invalid."""
+    t_arrive = math.exp(2.0 * alpha0 * half_gap) / (2.0 * alpha0 * u)
+    if t_sw1 is None:
+        t_sw1 = _leg_time(0.0, half_gap - s_sw, u, alpha0, half_gap, s_sw)
+    if not t_sw1 < t_arrive:
+        raise ValueError("the droplet reaches electrode 1 before the switch")
+    # position under electrode 1 after t: exp(2 a0 S_e1) = exp(2 a0 half_gap) - 2 a0 u t
+    s_e1 = math.log(math.exp(2.0 * alpha0 * half_gap) - 2.0 * alpha0 * u * t_sw1) / (2.0 * alpha0)
+    x1 = half_gap - s_e1
+    t2 = _leg_time(x1, -(half_gap - s_sw), u, alpha0, half_gap + x1, s_sw)
+    return t_sw1, t_sw1 + t2, x1

@@ -57,3 +57,62 @@ def design_schedule(sim, phi0, volts0, t_total, T, K, target, axis=0, electrode=
         v, r = v_new, r_new
         history.append(dict(iteration=k, residual=r, step=step, **sweeps))
     return v, history
+
+
+def switch_schedules(t_sw, volts, n_seg, T):
+    """Schedules of two electrodes for one switch at step t_sw (electrode 1 on before, electrode 2
+    on after, both at `volts`) over n_seg segments of T / n_seg steps: the segment containing the
+    switch holds each electrode at its on-time fraction of the segment (the time average of the
+    switched voltage over the segment), so x_c(T) depends continuously on t_sw."""
+    width = T / n_seg
+    s = min(int(t_sw // width), n_seg - 1)
+    frac = (t_sw - s * width) / width
+    v1 = np.zeros(n_seg)
+    v1[:s] = volts
+    v1[s] = volts * frac
+    v2 = volts - v1
+    return v1, v2, s
+
+
+def switch_time_gradient(sim, phi0, t_sw, volts, n_seg, T, K, axis=0, electrodes=(0, 1)):
+    """x_c(T)[axis] and its derivative with respect to the switch time, from one checkpointed
+    forward and the adjoint with respect to each electrode's schedule: d x / d t_sw =
+    (dx/dV1[s] - dx/dV2[s]) volts n_seg / T for the switching segment s."""
+    e1, e2 = electrodes
+    v1, v2, s = switch_schedules(t_sw, volts, n_seg, T)
+    sim.set_phase(phi0)
+    sim.set_schedule(e1, v1, T)
+    sim.set_schedule(e2, v2, T)
+    sim.forward_checkpointed(T, K)
+    x = float(sim.observables()["centroid"][axis])
+    gx = np.zeros(3)
+    gx[axis] = 1.0
+    g1 = sim.adjoint(gx, np.zeros(3), e1, n_seg)
+    g2 = sim.adjoint(gx, np.zeros(3), e2, n_seg)
+    return x, (g1[s] - g2[s]) * volts * n_seg / T
+
+
+def design_switch_time(sim, phi0, t_sw0, target, volts, n_seg, T, K, axis=0, electrodes=(0, 1), iters=6,
+                       atol=1e-6, max_halvings=6):
+    """Newton iteration on the switch time so that the droplet centroid reaches `target` at step
+    T (the two-electrode protocols of the Results, Fig. 5b-c, one switch at a time), each step from
+    switch_time_gradient, halved until |x - target| decreases.  Returns (t_sw, history)."""
+    t = float(t_sw0)
+    x, d = switch_time_gradient(sim, phi0, t, volts, n_seg, T, K, axis, electrodes)
+    history = [dict(iteration=0, t_sw=t, residual=x - target, slope=d)]
+    for k in range(1, iters + 1):
+        r = x - target
+        if abs(r) <= atol or d == 0.0:
+            break
+        step = -r / d
+        for _ in range(max_halvings + 1):
+            t_new = min(max(t + step, 0.0), T * (1.0 - 1e-9))
+            x_new, d_new = switch_time_gradient(sim, phi0, t_new, volts, n_seg, T, K, axis, electrodes)
+            if abs(x_new - target) < abs(r):
+                break
+            step *= 0.5
+        else:
+            break
+        t, x, d = t_new, x_new, d_new
+        history.append(dict(iteration=k, t_sw=t, residual=x - target, slope=d))
+    return t, history

@@ -112,3 +112,58 @@ def test_fit_recovers_parameters_of_a_trajectory():
     assert fit["c_drag"] == pytest.approx(c_true, rel=1e-3)
     assert fit["drive"] == pytest.approx(d_true, rel=1e-3)
     assert fit["rms"] <= 1e-5 * float(s_obs[-1])
+
+
+def test_overdamped_transport_fit():
+    """The overdamped form of Eq. 7 is the exact solution of Eq. 5 without inertia (dS/dt =
+    v0 exp(2 alpha0 S)), and its fit recovers v0 from a noisy trajectory of that law; with the
+    inertial lag tau_v 1e-4 of the travel time the full Eq. 5 gives the same times."""
+    a0, v0 = 0.025, 8e-5
+    s = np.linspace(0.0, 36.0, 60)
+    # dS/dt = v0 exp(2 a0 S) -> t(S) = (1 - exp(-2 a0 S)) / (2 a0 v0)
+    t = np.array([quad(lambda x: math.exp(-2 * a0 * x) / v0, 0.0, si)[0] for si in s])
+    assert np.allclose(rm.overdamped_time(s, v0, a0), t, rtol=1e-12, atol=1e-6)
+    rng = np.random.default_rng(5)
+    fit = rm.fit_overdamped(t * (1 + 0.01 * rng.standard_normal(t.size)), s, a0)
+    assert abs(fit["v0"] / v0 - 1) < 0.01
+    # Eq. 5 with drag 2 C R0 mu and drive chosen to have the same start velocity
+    m, r0, mu, c = 226.0, 12.0, 1.0 / 6.0, 10.0
+    s0 = 48.0
+    drive = v0 * 2 * c * r0 * mu * math.exp(2 * a0 * s0)
+    ratio = rm.drag_to_drive(v0, a0, s0, r0, mu)
+    assert ratio == pytest.approx(c / drive, rel=1e-12)
+    t_end = float(t[-1])
+    ts, ss, _ = rm.integrate_motion(1.01 * t_end, m, c, r0, mu, drive, a0, s0, n_steps=200000)
+    t36 = float(np.interp(36.0, ss, ts))
+    assert abs(t36 / t_end - 1) < 1e-3
+
+
+def test_two_electrode_switch_times_and_sensitivity():
+    """The two-electrode protocol (Results, Fig. 5b) in the overdamped Eq. 5: the switch times
+    from the closed-form legs agree with a direct integration of dS/dt = +-u exp(-2 alpha0 S_e);
+    moving the first switch by +-10 % moves the second by several times more (the force grows
+    exponentially towards the first electrode, so the return leg starts from a very different
+    place), the sensitivity the paper points out (about 50 % there)."""
+    u, a0, half, s_sw = 8.3e-5 * math.exp(2 * 0.02533 * 48.0), 0.02533, 48.0, 24.0
+    t1, t2, x1 = rm.two_electrode_switch_times(u, a0, half, s_sw)
+    assert x1 == pytest.approx(half - s_sw, rel=1e-12)
+    # direct integration (forward Euler in small steps) of the same law
+    x, t, dt = 0.0, 0.0, 1.0
+    while half - x > s_sw:
+        x += dt * u * math.exp(-2 * a0 * (half - x))
+        t += dt
+    assert t / t1 == pytest.approx(1.0, abs=1e-3)
+    while x + half > s_sw:
+        x -= dt * u * math.exp(-2 * a0 * (x + half))
+        t += dt
+    assert t / t2 == pytest.approx(1.0, abs=1e-3)
+    late = rm.two_electrode_switch_times(u, a0, half, s_sw, t_sw1=1.1 * t1)
+    early = rm.two_electrode_switch_times(u, a0, half, s_sw, t_sw1=0.9 * t1)
+    leg = t2 - t1
+    d_late = (late[1] - late[0]) / leg - 1
+    d_early = (early[1] - early[0]) / leg - 1
+    print("second leg", leg, "late switch", d_late, "early switch", d_early)
+    assert d_late > 0.1 and d_early < -0.1
+    assert abs(late[1] / t2 - 1) > 0.1 and abs(early[1] / t2 - 1) > 0.1
+    with pytest.raises(ValueError):
+        rm.two_electrode_switch_times(u, a0, half, s_sw, t_sw1=10 * t1)
