@@ -115,6 +115,11 @@ def guo_source(u, F, lat):
     return lat.w.reshape(-1, 1) * ((eF - uF) / cs2 + eu * eF / (cs2 * cs2))
 
 
+def second_moments(f, lat):
+    """Pi_ab = sum_q e_qa e_qb f_q: (Q, N) -> (3, 3, N)."""
+    return torch.einsum("qa,qb,qn->abn", lat.e, lat.e, f)
+
+
 def mrt_collide(f, feq, C, rates, lat):
     """Raw-moment MRT, literally (Eq. 15 / Eq. 20b):
     m = M f, m_eq = M f_eq, m* = (I - S) m + S m_eq + (I - S/2) M C, f* = M^-1 m*.

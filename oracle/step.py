@@ -22,7 +22,10 @@ Readings (paper silent or garbled):
     s = 1/tau_Phi with M = cs2 (tau_Phi - 1/2); all higher moments at 1.
   * Flow (equilibrium and forcing deferred by the paper): incompressible
     He-Luo equilibrium with rho0 = 1 stored as the deviation dg = g - w; Guo
-    forcing; u = j + F/2; p = cs2 drho.  Second-order raw moments relax at
+    forcing; u = j + F/2; p = cs2 drho.  Unequal phase densities (Eq. 9 with
+    rho(Phi) = sum rho_i Phi_i): the same populations in the velocity-based
+    form, whose zeroth moment is p* = p / (rho cs2); the acceleration F / rho
+    replaces F, with F adding -cs2 p* grad(rho) and nu (grad u + grad u^T).grad(rho).  Second-order raw moments relax at
     1/tau(x) with tau = 1/2 + nu/cs2, nu linear in Phi; higher moments at
     s_high (1 unless chosen; also for orders >= 2 of the phase fields and charge).
   * Charge: equilibrium rho_e w (1 + e.u/cs2); R = (w/cs2) e.d(rho_e u)/dt
@@ -78,6 +81,10 @@ class Oracle:
         # rate of every raw moment not named by the scheme (orders >= 2 of the phase fields and
         # the charge, >= 3 of the flow; Eq. 15 and Eq. 20b leave S unspecified): 1 by default
         self.s_high = float(p.get("s_high", 1.0) or 1.0)
+        # density per phase (mixed linearly); unequal densities select the velocity-based
+        # variable-density form of the flow (the paper's Eq. 9 with rho(Phi))
+        self.rho = [float(v) or 1.0 for v in p.get("rho", (1.0, 1.0, 1.0))]
+        self.var_rho = not (self.rho[0] == self.rho[1] == self.rho[2] == 1.0)
         self.nu = [cs2 * (t - 0.5) for t in p["tau_flow"]]
         self.eps = [float(v) for v in p["eps"]]
         self.cond = [float(v) for v in p["cond"]]
@@ -214,11 +221,28 @@ class Oracle:
             aux.update(pot=pot, E=E, Q=Qsrc, Fe=Fe * self.fl, eps=epsn, sigma=sig)
         F = F * self.fl
         # O7 flow
-        u = (j + 0.5 * F) * self.fl
-        geq = model.flow_equilibrium(drho, u, lat)
-        Fg = model.guo_source(u, F, lat)
         nu = sum(self.nu[i] * phi[i] for i in range(3))
         tau = 0.5 + nu / cs2
+        if self.var_rho:
+            # density linear in the phase fields; the flow populations carry p* = p / (rho cs2)
+            # and the velocity, so the momentum equation divided by rho needs, besides F / rho,
+            # the pressure force -cs2 p* grad(rho) and the viscous force nu (grad u + grad u^T)
+            # . grad(rho), the latter from the non-equilibrium second moments of a provisional
+            # collision with the other forces: nu S_ab = -(nu / (cs2 tau)) Pi_ab
+            rho_m = sum(self.rho[i] * phi[i] for i in range(3)) * self.fl + (1.0 - self.fl)
+            grad_rho = sum(self.rho[i] * grad[i] for i in range(3))
+            u1 = (j + 0.5 * F / rho_m) * self.fl
+            pi_neq = model.second_moments(s.g - model.flow_equilibrium(drho, u1, lat)
+                                          + 0.5 * model.guo_source(u1, F / rho_m, lat), lat)
+            F_mu = -(nu / (cs2 * tau)) * (pi_neq * grad_rho.unsqueeze(0)).sum(1)
+            F_p = -cs2 * drho * grad_rho
+            F = (F + F_p + F_mu) * self.fl
+            acc = F / rho_m
+        else:
+            acc = F
+        u = (j + 0.5 * acc) * self.fl
+        geq = model.flow_equilibrium(drho, u, lat)
+        Fg = model.guo_source(u, acc, lat)
         rates_g = model.moment_rates(lat, {2: 1.0 / tau}, N, default=self.s_high)
         gstar = model.mrt_collide(s.g, geq, Fg, rates_g, lat)
         g_new = self.stream(gstar)
