@@ -61,8 +61,9 @@ typedef enum {
 
 /* Fields readable with ehdlb_read_field, always returned as float64 on the host.
  * PHI*: phase fields of the current populations (Eq. 19).  UX..UZ: velocity of
- * the last completed step (u = j + F/2).  P: pressure cs^2 (rho - 1) of the
- * current populations.  RHO_E: charge density of the current populations.
+ * the last completed step (u = j + F/2, F / rho with unequal densities).  P: cs^2
+ * times the zeroth moment of the flow populations' deviation, the pressure at unit
+ * density (p / rho with unequal densities).  RHO_E: charge density of the current populations.
  * POT: potential solved in the last completed step.  Q: Ohmic source of the
  * last completed step.  POPS: the current populations in canonical order
  * [family][q][node] with families g (deviation from w), f1, f2, f3, h (the
@@ -108,9 +109,14 @@ typedef struct {
                                >= 2 for the phase fields and the charge, >= 3 for the flow,
                                in (0, 2); 0 means the default 1 (those moments then leave
                                the collision at equilibrium)                              */
-  double rho[3];            /* density per phase; density ratio 1 only (every entry 1, or 0
-                               for the default 1): the flow equilibrium is the
-                               incompressible one about the unit density                 */
+  double rho[3];            /* density per phase (> 0; 0 means the default 1), mixed
+                               linearly (Eq. 9 with rho(Phi)).  All 1: the incompressible
+                               flow about the unit density.  Unequal: the velocity-based
+                               form (the flow populations carry p / (rho cs^2); the
+                               acceleration F / rho with the pressure force
+                               -cs^2 p* grad(rho) and the viscous force
+                               nu (grad u + grad u^T) . grad(rho)); ehdlb_adjoint then
+                               returns EINVAL                                          */
 } ehdlb_params;
 
 typedef struct {
@@ -129,7 +135,7 @@ typedef struct {
 /* Validate lattice and parameters and create a context (no device work).
  * EINVAL: dim not 2/3, sizes < 1, Nz != 1 in 2D, tau <= 1/2, M <= 0, W <= 0,
  * any Upsilon_i <= 0, eps <= 0, cond < 0, alpha < 0, tol <= 0, max_iter < 1,
- * s_high outside (0, 2), a density other than 1. */
+ * s_high outside (0, 2), a density < 0. */
 ehdlb_status ehdlb_create(const ehdlb_lattice* lattice, const ehdlb_params* params,
                           ehdlb_ctx** out);
 
@@ -235,7 +241,8 @@ int64_t ehdlb_wetting_links(const ehdlb_ctx* ctx, int64_t* nodes, int32_t* dirs,
  *   state again.  ESTATE if anything that changes the state or the steps was
  *   called since the checkpointed forward (ehdlb_generation differs: set_geometry,
  *   set_phase, set_charge, set_schedule, set_solver_options, step with n > 0,
- *   load_state, another forward_checkpointed), EINVAL if the field is off. */
+ *   load_state, another forward_checkpointed), EINVAL if the field is off or the
+ *   phase densities differ. */
 size_t ehdlb_adjoint_workspace_bytes(const ehdlb_ctx* ctx, int64_t T, int32_t K);
 ehdlb_status ehdlb_forward_checkpointed(ehdlb_ctx* ctx, int64_t T, int32_t K, void* device_workspace,
                                         size_t bytes);

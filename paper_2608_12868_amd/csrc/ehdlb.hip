@@ -218,6 +218,7 @@ static Phys<T> make_phys(const ehdlb_params& p) {
   r.s_high = (T)p.s_high;
   for (int i = 0; i < 3; ++i) {
     r.nu[i] = (T)((p.tau_flow[i] - 0.5) / 3.0);
+    r.rho[i] = (T)p.rho[i];
     r.eps[i] = (T)p.eps[i];
     r.cond[i] = (T)p.cond[i];
     r.body[i] = (T)p.body_force[i];
@@ -383,8 +384,7 @@ static ehdlb_status validate(ehdlb_ctx* c, const ehdlb_lattice* L, const ehdlb_p
   }
   if (!(p->s_high > 0.0 && p->s_high < 2.0)) return fail(c, EHDLB_EINVAL, "s_high must lie in (0, 2)");
   for (int i = 0; i < 3; ++i)
-    if (p->rho[i] != 1.0)
-      return fail(c, EHDLB_EINVAL, "density ratio 1 only: rho must be 1 for every phase (or 0 for the default)");
+    if (!(p->rho[i] > 0.0)) return fail(c, EHDLB_EINVAL, "densities must be > 0 (or 0 for the default 1)");
   if (!(p->mobility > 0.0)) return fail(c, EHDLB_EINVAL, "mobility must be > 0");
   if (!(p->width > 0.0)) return fail(c, EHDLB_EINVAL, "interface width must be > 0");
   double u[3], ut;
@@ -751,21 +751,38 @@ static void launch_moments(const ehdlb_ctx* c, int families, const Dims& dm, con
                        fam0);
 }
 
-template <class LT, class T, bool EHD, bool STORE, bool HIGH>
+template <class LT, class T, bool EHD, bool STORE, bool HIGH, bool VRHO>
 static void launch_step_h(const ehdlb_ctx* c, const StepArgs<T>& a) {
   if (c->stream_pops)
-    hipLaunchKernelGGL((k_step<LT, T, EHD, STORE, true, HIGH>), dim3(nblocks(a.d.N)), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL((k_step<LT, T, EHD, STORE, true, HIGH, VRHO>), dim3(nblocks(a.d.N)), dim3(kBlock), 0,
+                       c->stream, a);
   else
-    hipLaunchKernelGGL((k_step<LT, T, EHD, STORE, false, HIGH>), dim3(nblocks(a.d.N)), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL((k_step<LT, T, EHD, STORE, false, HIGH, VRHO>), dim3(nblocks(a.d.N)), dim3(kBlock), 0,
+                       c->stream, a);
 }
 
-// the variant with the higher moments away from rate 1 only when they are
+static bool var_rho(const ehdlb_ctx* c) {
+  return !(c->prm.rho[0] == 1.0 && c->prm.rho[1] == 1.0 && c->prm.rho[2] == 1.0);
+}
+
+// the variants with the higher moments away from rate 1, or with unequal densities, only when
+// they are (the adjoint's recompute, STORE, never runs with unequal densities)
 template <class LT, class T, bool EHD, bool STORE>
 static void launch_step(const ehdlb_ctx* c, const StepArgs<T>& a) {
-  if (c->prm.s_high != 1.0)
-    launch_step_h<LT, T, EHD, STORE, true>(c, a);
+  const bool high = c->prm.s_high != 1.0;
+  if constexpr (!STORE) {
+    if (var_rho(c)) {
+      if (high)
+        launch_step_h<LT, T, EHD, STORE, true, true>(c, a);
+      else
+        launch_step_h<LT, T, EHD, STORE, false, true>(c, a);
+      return;
+    }
+  }
+  if (high)
+    launch_step_h<LT, T, EHD, STORE, true, false>(c, a);
   else
-    launch_step_h<LT, T, EHD, STORE, false>(c, a);
+    launch_step_h<LT, T, EHD, STORE, false, false>(c, a);
 }
 
 // ============================================================================ step
@@ -1822,6 +1839,7 @@ ehdlb_status ehdlb_adjoint(ehdlb_ctx* c, const double* dL_dcentroid, const doubl
   if (!dL_dcentroid || !dL_dvelocity || !dL_dvolts) return fail(c, EHDLB_EINVAL, "null argument");
   if (electrode < 0 || electrode >= EHDLB_MAX_ELECTRODES) return fail(c, EHDLB_EINVAL, "electrode index out of range");
   if (!c->ehd) return fail(c, EHDLB_EINVAL, "adjoint with respect to voltages needs the field on");
+  if (var_rho(c)) return fail(c, EHDLB_EINVAL, "the adjoint of the variable-density flow is not built");
   if (!c->adj.ready) return fail(c, EHDLB_ESTATE, "adjoint before forward_checkpointed");
   if (c->sched[electrode].v.size() > (size_t)c->adj.nvseg) return fail(c, EHDLB_EINVAL, "too many schedule segments");
   if (c->gen != c->adj.gen || c->t != c->adj.t0 + c->adj.T)

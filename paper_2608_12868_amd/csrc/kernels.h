@@ -110,6 +110,7 @@ struct Phys {
   T s_e;          // first-order rate of the charge, 1/(1/2 + alpha/cs2)
   T s_high;       // rate of the higher moments: order >= 2 (phase, charge), >= 3 (flow)
   T nu[3];        // kinematic viscosity per phase
+  T rho[3];       // density per phase (all 1 unless the variable-density flow is selected)
   T eps[3], cond[3];
   T body[3];
 };

@@ -16,7 +16,14 @@ namespace ehd {
 // j - u + F/2 = 0), so M^-1 (I - S) M d = (1 - s_high) d + (s_high - s_k) P_k d with P_k the
 // projection on the moments of the one order k relaxing at its own rate s_k (first order for
 // the phase fields and the charge, second order for the flow).
-template <class L, class T, bool EHD, bool STORE, bool NT, bool HIGH>
+//
+// VRHO: unequal phase densities (Eq. 9 with rho(Phi) = sum rho_i Phi_i) in the velocity-based
+// form: the flow populations carry p* = p / (rho cs2) (their zeroth moment) and the velocity;
+// the momentum equation divided by rho needs the acceleration F / rho with F adding the pressure
+// force -cs2 p* grad(rho) and the viscous force nu (grad u + grad u^T) . grad(rho), the strain
+// rate taken from the non-equilibrium second moments of a provisional collision with the other
+// forces (nu S_ab = -3 nu s_nu Pi_ab).  grad(rho) = sum rho_i grad(Phi_i) reuses the stencils.
+template <class L, class T, bool EHD, bool STORE, bool NT, bool HIGH, bool VRHO>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
   using ML = MomLayout<L>;
   constexpr int Q = L::Q;
@@ -140,12 +147,48 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
       j[1] += T(L::ey[q]) * gq[q];
       j[2] += T(L::ez[q]) * gq[q];
     }
+    const T nu = p.nu[0] * pc[0] + p.nu[1] * pc[1] + p.nu[2] * pc[2];
+    const T s_nu = T(1) / (T(0.5) + T(3) * nu);
+    if (VRHO) {
+      const T irho = T(1) / (p.rho[0] * pc[0] + p.rho[1] * pc[1] + p.rho[2] * pc[2]);
+      T grho[3], u1[3], a1[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        grho[c] = p.rho[0] * gr[0][c] + p.rho[1] * gr[1][c] + p.rho[2] * gr[2][c];
+        a1[c] = F[c] * irho;
+        u1[c] = j[c] + T(0.5) * a1[c];
+      }
+      const T uu1 = u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2];
+      const T ua1 = u1[0] * a1[0] + u1[1] * a1[1] + u1[2] * a1[2];
+      // second-order moments of g - g_eq + F_q/2 of the provisional collision (xx yy zz xy xz yz)
+      T P[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const T exq = T(L::ex[q]), eyq = T(L::ey[q]), ezq = T(L::ez[q]);
+        const T w = T(L::w36[q]) / T(36);
+        const T eu = exq * u1[0] + eyq * u1[1] + ezq * u1[2];
+        const T ea = exq * a1[0] + eyq * a1[1] + ezq * a1[2];
+        const T dq = gq[q] - w * (drho + T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu1) +
+                     T(0.5) * w * (T(3) * (ea - ua1) + T(9) * eu * ea);
+        P[0] += exq * exq * dq;
+        P[1] += eyq * eyq * dq;
+        P[2] += ezq * ezq * dq;
+        P[3] += exq * eyq * dq;
+        P[4] += exq * ezq * dq;
+        P[5] += eyq * ezq * dq;
+      }
+      const T cmu = -T(3) * nu * s_nu;
+      const T cp = -cs2 * drho;
+      F[0] += cp * grho[0] + cmu * (P[0] * grho[0] + P[3] * grho[1] + P[4] * grho[2]);
+      F[1] += cp * grho[1] + cmu * (P[3] * grho[0] + P[1] * grho[1] + P[5] * grho[2]);
+      F[2] += cp * grho[2] + cmu * (P[4] * grho[0] + P[5] * grho[1] + P[2] * grho[2]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[c] *= irho;  // from here on the acceleration
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) u[c] = j[c] + T(0.5) * F[c];
     const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-    const T nu = p.nu[0] * pc[0] + p.nu[1] * pc[1] + p.nu[2] * pc[2];
-    const T s_nu = T(1) / (T(0.5) + T(3) * nu);
     // second-order raw moments of g - g_eq + F_q/2
     T Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
 #pragma unroll
