@@ -89,7 +89,10 @@ typedef struct {
                                mixed linearly in the phase fields                         */
   double mobility;          /* M of Eq. 8 (> 0)                                           */
   double width;             /* W_int of Eqs. 8, 10, 18, 20 (> 0)                          */
-  double gamma12, gamma13, gamma23;   /* pair tensions, Eq. 11; each Upsilon_i must be > 0 */
+  double gamma12, gamma13, gamma23;   /* pair tensions (> 0), Eq. 11; each Upsilon_i nonzero
+                                         (negative for a spreading phase, e.g. the
+                                         lubricant cloaking the droplet when gamma13 >
+                                         gamma12 + gamma23) and Upsilon_T finite            */
   double cos12, cos13, cos23;         /* cos(theta_ij) of Eq. 20, theta_ij measured through
                                          phase i                                          */
   int32_t ehd;              /* 0: no electric field (no potential, no charge family)      */
@@ -134,7 +137,7 @@ typedef struct {
 
 /* Validate lattice and parameters and create a context (no device work).
  * EINVAL: dim not 2/3, sizes < 1, Nz != 1 in 2D, tau <= 1/2, M <= 0, W <= 0,
- * any Upsilon_i <= 0, eps <= 0, cond < 0, alpha < 0, tol <= 0, max_iter < 1,
+ * a tension <= 0, a zero Upsilon_i or an infinite Upsilon_T, eps <= 0, cond < 0, alpha < 0, tol <= 0, max_iter < 1,
  * s_high outside (0, 2), a density < 0. */
 ehdlb_status ehdlb_create(const ehdlb_lattice* lattice, const ehdlb_params* params,
                           ehdlb_ctx** out);

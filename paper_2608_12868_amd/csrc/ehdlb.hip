@@ -387,10 +387,15 @@ static ehdlb_status validate(ehdlb_ctx* c, const ehdlb_lattice* L, const ehdlb_p
     if (!(p->rho[i] > 0.0)) return fail(c, EHDLB_EINVAL, "densities must be > 0 (or 0 for the default 1)");
   if (!(p->mobility > 0.0)) return fail(c, EHDLB_EINVAL, "mobility must be > 0");
   if (!(p->width > 0.0)) return fail(c, EHDLB_EINVAL, "interface width must be > 0");
+  // pair tensions positive; Upsilon_i may be negative (a spreading phase: the lubricant cloaking
+  // the droplet when gamma13 > gamma12 + gamma23) but not zero, and Upsilon_T must be finite
+  if (!(p->gamma12 > 0.0 && p->gamma13 > 0.0 && p->gamma23 > 0.0))
+    return fail(c, EHDLB_EINVAL, "pair tensions must be > 0");
   double u[3], ut;
   upsilons(*p, u, ut);
   for (int i = 0; i < 3; ++i)
-    if (!(u[i] > 0.0)) return fail(c, EHDLB_EINVAL, "every Upsilon_i (Eq. 11) must be > 0");
+    if (u[i] == 0.0) return fail(c, EHDLB_EINVAL, "every Upsilon_i (Eq. 11) must be nonzero");
+  if (!std::isfinite(ut)) return fail(c, EHDLB_EINVAL, "Upsilon_T (Eq. 11) must be finite");
   if (p->ehd) {
     if (!(p->charge_diffusion >= 0.0)) return fail(c, EHDLB_EINVAL, "charge diffusion must be >= 0");
     if (!(p->poisson_tol > 0.0)) return fail(c, EHDLB_EINVAL, "poisson_tol must be > 0");

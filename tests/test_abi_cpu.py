@@ -52,7 +52,8 @@ def _ctx(case, **over):
 
 
 @pytest.mark.parametrize("over", [dict(tau_flow=(0.5, 1, 1)), dict(mobility=0.0), dict(width=-1.0),
-                                  dict(gamma12=1e-3, gamma13=1e-3, gamma23=3e-3), dict(eps=(80, 0, 1)),
+                                  dict(gamma12=1e-3, gamma13=2e-3, gamma23=1e-3), dict(gamma12=-1e-3),
+                                  dict(eps=(80, 0, 1)),
                                   dict(cond=(-1, 0, 0)), dict(charge_diffusion=-1.0), dict(poisson_tol=0.0),
                                   dict(poisson_max_iter=0), dict(s_high=2.0), dict(s_high=-0.5),
                                   dict(rho=(1.0, 1.0, -2.0))])
@@ -162,6 +163,7 @@ def test_zero_rates_and_densities_mean_the_defaults(L):
     _ctx(case, s_high=0.0, rho=(0.0, 0.0, 0.0))
     _ctx(case, s_high=1.7, rho=(1.0, 0.0, 1.0))
     _ctx(case, rho=(998.0, 970.0, 1.2))          # the paper's Table 1 densities are accepted
+    _ctx(case, gamma12=1e-3, gamma13=2.5e-3, gamma23=1e-3)   # cloaking: Upsilon_2 < 0
 
 
 @pytest.mark.parametrize("name", ["c1", "c1s", "c2", "c2s", "c3", "c3s", "c4", "c4s", "c5"])

@@ -144,3 +144,21 @@ def test_adjoint_higher_moment_rate_matches_oracle_autograd():
     print("adjoint (s_high 1.3) vs oracle autograd", err, flush=True)
     assert np.allclose(ob["centroid"], xc.numpy(), rtol=1e-12, atol=1e-12)
     assert err <= 1e-8
+
+
+def test_adjoint_cloaking_tensions_matches_oracle_autograd():
+    """Upsilon_2 < 0 (gamma13 > gamma12 + gamma23): the reverse of the chemical potentials."""
+    from oracle import Oracle
+    from oracle.adjoint import schedule_gradient
+    case = make_case("c4s", precision="fp64")
+    over = dict(gamma12=1e-3, gamma13=2.5e-3, gamma23=1e-3)
+    sched = case.schedule.copy()
+    T = t_total = 16
+    g_gpu, ob = _gpu_grad(case, sched, T, t_total, K=5, **over)
+    p = dict(case.params)
+    p.update(over)
+    o = Oracle(case.dim, case.n, case.periodic, p, case.flags)
+    g_ref, xc, vc = schedule_gradient(o, case.phi, sched, T, t_total, GX, GV)
+    err = np.abs(g_gpu - g_ref.numpy()).max() / np.abs(g_ref.numpy()).max()
+    print("adjoint (cloaking tensions) vs oracle autograd", err, flush=True)
+    assert err <= 1e-8

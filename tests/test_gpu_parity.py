@@ -272,3 +272,13 @@ def test_paper_regime_densities_and_viscosities():
     print("  FP32 after 2000 steps: mass drift", (ob["mass"] - m0) / m0, "velocity", ob["velocity"], flush=True)
     assert ob["flags"] == 0
     assert np.all(np.abs(ob["mass"] - m0) / m0 <= 2000 * 9 * 2.0 ** -24)
+
+
+def test_fp64_parity_cloaking_tensions():
+    """gamma13 > gamma12 + gamma23 (Upsilon_2 < 0, the lubricant cloaks the droplet)."""
+    case = make_case("c2s", precision="fp64")
+    over = dict(gamma12=1e-3, gamma13=2.5e-3, gamma23=1e-3)
+    sim = _gpu(case, **over)
+    sim.step(100)
+    o, s, aux = gu.oracle_run(case, 100, params=over)
+    _compare(sim, o, s, aux, FP64_TOL)

@@ -648,3 +648,33 @@ def test_v14_two_layer_poiseuille_with_density_contrast(rho1):
     print("two-layer profile vs quadrature", err)
     assert err < 1e-2             # diffuse-interface discretisation: 6e-3 (rho1 = 5), 4e-3 (0.2)
     assert float(aux["u"][1].abs().max()) < 1e-4 * float(np.abs(u).max())
+
+
+def test_v15_cloaking_tensions_spread_the_lubricant():
+    """gamma13 > gamma12 + gamma23 (the paper's cloaking condition: positive spreading coefficient of
+    the lubricant on the droplet in the ambient) makes Upsilon_2 < 0 in Eq. 11.  The phase fields
+    evolve by Eq. 8, which does not involve Upsilon, and the pair tensions (Upsilon_i + Upsilon_j)/2
+    stay positive, so the model runs; no Neumann triangle closes, so the lubricant spreads between
+    droplet and ambient: the droplet/ambient contact sum(Phi_1 Phi_3) keeps falling (to below half
+    of its value at step 1000 by step 4000), while with gamma13 below gamma12 + gamma23 the lens of
+    V3 keeps it.  Phase masses stay constant."""
+    from oracle import model
+    (u1, u2, u3), ut = model.upsilons(0.01, 0.025, 0.01)
+    assert u2 < 0 < u1 and u3 > 0 and math.isfinite(ut)
+    case = pc.lens(nx=112, ny=96, gamma12=0.01, gamma13=0.025, gamma23=0.01, mobility=0.05)
+    contact = {}
+    m0 = None
+
+    def cb(k, o, s, aux):
+        nonlocal m0
+        f = o.fields(s)["phi"]
+        contact[k] = float((f[0] * f[2]).sum())
+        m = f.sum(1)
+        if m0 is None:
+            m0 = m
+        assert torch.all((m - m0).abs() <= 1e-10 * m0)
+    _run(case, 4000, every=1000, cb=cb)
+    c = [contact[k] for k in sorted(contact)]
+    print("droplet/ambient contact every 1000 steps", c)
+    assert all(b < a for a, b in zip(c, c[1:]))
+    assert c[-1] < 0.5 * c[0]
