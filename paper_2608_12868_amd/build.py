@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libehdlb.so")
 SOURCES = [os.path.join(HERE, "csrc", "ehdlb.hip")]
-HEADERS = [os.path.join(HERE, "csrc", n) for n in ("kernels.h", "step.h", "lattice.h", "adjoint.h")] + [
+HEADERS = [os.path.join(HERE, "csrc", n) for n in ("kernels.h", "step.h", "lattice.h", "adjoint.h", "preset.h")] + [
     os.path.join(ROOT, "include", "ehdlb.h")]
 
 
