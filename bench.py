@@ -106,8 +106,10 @@ FD_H = (1e-3, 1e-4)   # central-difference steps: 1e-4 as the workload names it,
 def adjoint_leg(key, seed=1):
     """Cost of dL/dV for L = (x_c(T) - x*)^2 (x* = initial centroid + 5 lu), FP32 path: plain
     forward, checkpointed forward and reverse sweep (recompute included), timed with device
-    syncs, with the default forward warm start (projected onto the last four potentials then at
-    least one CG iteration) and, for the 2D leg, the other three (the projection alone; previous
+    syncs, with the forward warm start that the default uses for the gradient's forward
+    (projected onto the last four potentials, then at least one CG iteration: `warm_projected`,
+    which also times the default's plain forward, where a projected start that meets the
+    tolerance is kept) and, for the 2D leg, the other three (the projection alone; previous
     potential; extrapolated from the last two); each gradient's error against the FP64 adjoint
     (2D leg) and the directional derivatives against central differences of the FP64 forward at
     each step of FD_H."""
@@ -137,6 +139,18 @@ def adjoint_leg(key, seed=1):
         torch.cuda.synchronize()
         t_fwd = time.perf_counter() - t0
         st_f = sim.solver_stats(reset=True)
+        default_fwd = None
+        if mode == 2:
+            # the library's default (4): plain steps keep a projected start that meets the
+            # tolerance, only the gradient's forward iterates at least once (as mode 2)
+            sim.set_solver_options(warm_start=4)
+            sim.set_phase(case.phi)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(T)
+            torch.cuda.synchronize()
+            default_fwd = time.perf_counter() - t0
+            sim.set_solver_options(warm_start=mode)
         sim.set_phase(case.phi)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -157,6 +171,8 @@ def adjoint_leg(key, seed=1):
                            potential_iters_per_step={"forward": st_f["forward"]["iters"] / T,
                                                      "adjoint": st_a["iters"] / T},
                            grad=g)
+        if default_fwd is not None:
+            runs[label].update(default_forward_s=default_fwd, ratio_adjoint_to_default_forward=t_adj / default_fwd)
         ws = sim.adjoint_workspace_bytes(T, K) / 1e9
         del sim
         torch.cuda.empty_cache()

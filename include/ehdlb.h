@@ -266,13 +266,17 @@ ehdlb_status ehdlb_adjoint(ehdlb_ctx* ctx, const double dL_dcentroid[3], const d
  * their span, followed by at least one CG iteration; 3 = the same projection
  * without the minimum (fewest iterations; a solve that keeps the projected
  * start carries its error into the next steps' starts, correlated from step to
- * step, which biases gradients of the trajectory: ~7e-4 against the FP64
- * adjoint on 512x256 FP32 instead of ~8e-5 with 2).  The adjoint's solves
+ * step, which biases gradients of the trajectory: ~6e-4 against the FP64
+ * adjoint on 512x256 FP32 instead of ~1e-4 with 2); 4 (default) = 3 in
+ * ehdlb_step and 2 in the forward that a gradient differentiates
+ * (ehdlb_forward_checkpointed, and the adjoint's recompute of it), so plain
+ * forward runs take the fewest iterations and gradients keep their accuracy
+ * (the two forwards agree to the solver tolerance).  The adjoint's solves
  * always start from the projection onto the adjoint potentials of steps
  * t+1..t+6.  The earlier potentials are part of the saved state, so replays
  * from a checkpoint take the same iterates; switching modes in mid-run projects
  * once onto stale potentials (still a valid start).  Defaults lo = 0.5, hi = 2,
- * overcorrect = 2, warm_start = 2.  EINVAL outside the ranges. */
+ * overcorrect = 2, warm_start = 4.  EINVAL outside the ranges. */
 ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* ctx, double lo, double hi, double overcorrect,
                                       int32_t warm_start);
 

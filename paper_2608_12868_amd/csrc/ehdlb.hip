@@ -30,6 +30,7 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 // grid of the grid-stride reduction kernels (fixed, so the reduction order is fixed)
 constexpr int kRedBlocks = 1024;
+constexpr int kZeroBlocks = 256;  // grid of k_cg_zero (grid-stride; returns at once unless b == 0)
 // levels with at most this many cells whose working vectors, with those of every coarser
 // level, fit the tail's LDS run inside the single-workgroup V-cycle tail
 constexpr int64_t kTailMaxCells = 2048;
@@ -108,7 +109,9 @@ struct ehdlb_ctx {
   // iteration counts of the last potential solves of each kind (0: forward, 1: adjoint): they
   // decide how much work is queued before the host looks at the control block (speed only)
   struct CgHistory {
-    int last = 0, prev = 0, last_nonzero = 1;
+    int last = 0, last_nonzero = 1;
+    unsigned zeros = 0;  // bit k: the solve k solves ago took no iteration (last 8 solves)
+    unsigned over = 0;   // bit k: the solve k solves ago took more iterations than first queued
     int64_t solves = 0, iters = 0;  // statistics (ehdlb_solver_stats)
     double max_rel0 = 0.0;
   } cg_hist[2];
@@ -155,8 +158,10 @@ struct ehdlb_ctx {
   double mg_overcorrect = 2.0;
   bool stream_pops = false;       // population loads with the non-temporal hint
   // forward warm start: 0 previous potential, 1 extrapolated, 2 projected with at least one CG
-  // iteration, 3 projected
-  int warm_mode = 2;
+  // iteration, 3 projected, 4 (default) projected, with at least one CG iteration in the
+  // gradient's forward (ehdlb_forward_checkpointed and the adjoint's recompute) only
+  int warm_mode = 4;
+  bool grad_fwd = false;  // inside ehdlb_forward_checkpointed or ehdlb_adjoint
   // smoothing polynomial z += c1 y - c2 D^-1 A y: p(mu) = 1 - c1 mu + c2 mu^2 = T2(s(mu))/T2(s(0)),
   // s(mu) = (hi + lo - 2 mu)/(hi - lo)
   void poly(double& c1, double& c2) const {
@@ -553,7 +558,7 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
   hipLaunchKernelGGL(k_cg_judge, dim3(1), dim3(kBlock), 0, s, ctl, (const double*)ptrue, (const double*)pmax, rb0,
                      tol, eps_t, 0, 0, 1, min1);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_cg_zero<T>, dim3(nb0), dim3(kBlock), 0, s, (const CgCtl*)ctl, N, x);
+  hipLaunchKernelGGL(k_cg_zero<T>, dim3(std::min(nb0, kZeroBlocks)), dim3(kBlock), 0, s, (const CgCtl*)ctl, N, x);
   // The host reads the control block after an event that follows its copy, not after the whole
   // stream: `spec` (if given) queues work that depends on the solution behind the copy, gated
   // on the device by the stop flag, so it runs without a host round trip when the solve has
@@ -569,8 +574,10 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
   };
   bool stopped = false;
   int batch = std::max(hist.last, 1);
-  if (hist.last == 0 || hist.prev == 0) {
-    // solves without iterations are common here: look before queueing the hierarchy
+  if (__builtin_popcount(hist.zeros & 0xffu) >= 4) {
+    // at least half of the last 8 solves took no iteration: look before queueing the hierarchy
+    // (otherwise the iterations are queued at once, and return at once if the start already
+    // met the tolerance: cheaper than the GPU waiting for the host on most solves)
     ehdlb_status e = read_ctl();
     if (e) return e;
     stopped = c->hctl.stop != 0;
@@ -607,6 +614,8 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
   ehdlb_status st = EHDLB_OK;
   if (!stopped && (st = precondition(prz[0]))) return st;
   const int maxit = c->prm.poisson_max_iter, every = c->prm.poisson_check_every;
+  const bool spec_tail = __builtin_popcount(hist.over & 0xffu) >= 4;
+  bool overran = false;
   int queued = 0;
   for (; !stopped;) {
     for (int k = 0; k < batch && queued < maxit; ++k) {
@@ -629,10 +638,16 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
                            rb0, tol, eps_t, it, force, 0, 0);
       }
       LAUNCHCHK();
-      if ((st = precondition(prz[it & 1]))) return st;
+      // the preconditioning for the next iteration: within the batch at once; after its last
+      // iteration only once the control block shows that the solve goes on (a queued V-cycle
+      // that returns at once still costs a launch per kernel), unless recent solves often
+      // needed more than their first batch (then it runs while the host reads the block)
+      if ((k + 1 < batch || spec_tail) && queued < maxit && (st = precondition(prz[it & 1]))) return st;
     }
     if ((st = read_ctl())) return st;
     if (c->hctl.stop || queued >= maxit) break;
+    overran = true;
+    if (!spec_tail && (st = precondition(prz[queued & 1]))) return st;
     batch = 1;
   }
   const CgCtl& h = c->hctl;
@@ -645,7 +660,8 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
     if (h.iterated && !h.conv) c->sticky |= 2;
     if (!std::isfinite(h.rel)) c->sticky |= 1;
   }
-  hist.prev = hist.last;
+  hist.zeros = (hist.zeros << 1) | (c->last_iters == 0 ? 1u : 0u);
+  hist.over = (hist.over << 1) | (overran ? 1u : 0u);
   hist.last = c->last_iters;
   if (c->last_iters > 0) hist.last_nonzero = c->last_iters;
   ++hist.solves;
@@ -701,10 +717,11 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
   // steps (the default; kept in the saved state, so a replay from a checkpoint takes the same
   // iterates)
   T* pot = c->ptr<T>(c->off_pot);
-  if (c->warm_mode == 1) {
+  const int mode = c->warm_mode == 4 ? (c->grad_fwd ? 2 : 3) : c->warm_mode;
+  if (mode == 1) {
     hipLaunchKernelGGL(k_extrapolate<T>, dim3(nblocks(c->N)), dim3(kBlock), 0, c->stream, c->N, pot,
                        c->ptr<T>(c->off_pot_old));
-  } else if (c->warm_mode >= 2 && c->t >= 1) {
+  } else if (mode >= 2 && c->t >= 1) {
     const int64_t t = c->t;
     const int m = (int)std::min<int64_t>(t, kProjFwd);
     const T* older[kProjFwd - 1];
@@ -723,8 +740,7 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
   // mode 2: at least one CG iteration after the projected start (a solve that keeps the start
   // leaves an error that is carried into the next steps' starts, correlated from step to step,
   // and biases the gradients of the trajectory)
-  return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b), c->cg_hist[0], c->warm_mode == 2 ? 1 : 0,
-                    spec);
+  return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b), c->cg_hist[0], mode == 2 ? 1 : 0, spec);
 }
 
 // ============================================================================ timing
@@ -1831,7 +1847,9 @@ ehdlb_status ehdlb_forward_checkpointed(ehdlb_ctx* c, int64_t T, int32_t K, void
   a.t0 = c->t;
   c->adj = a;
   ++c->gen;
+  c->grad_fwd = true;
   ehdlb_status st = dispatch<FwdCkptFn>(c, 0);
+  c->grad_fwd = false;
   if (st) return st;
   c->adj.gen = c->gen;
   c->adj.ready = true;
@@ -1849,7 +1867,10 @@ ehdlb_status ehdlb_adjoint(ehdlb_ctx* c, const double* dL_dcentroid, const doubl
   if (c->sched[electrode].v.size() > (size_t)c->adj.nvseg) return fail(c, EHDLB_EINVAL, "too many schedule segments");
   if (c->gen != c->adj.gen || c->t != c->adj.t0 + c->adj.T)
     return fail(c, EHDLB_ESTATE, "state or schedule changed since forward_checkpointed");
-  return dispatch<AdjFn>(c, dL_dcentroid, dL_dvelocity, (int)electrode, dL_dvolts);
+  c->grad_fwd = true;  // the recompute replays the checkpointed forward's solves
+  const ehdlb_status st = dispatch<AdjFn>(c, dL_dcentroid, dL_dvelocity, (int)electrode, dL_dvolts);
+  c->grad_fwd = false;
+  return st;
 }
 
 ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* c, double lo, double hi, double overcorrect,
@@ -1857,7 +1878,7 @@ ehdlb_status ehdlb_set_solver_options(ehdlb_ctx* c, double lo, double hi, double
   if (!c) return EHDLB_EINVAL;
   if (!(lo > 0.0 && hi > lo && hi <= 2.0)) return fail(c, EHDLB_EINVAL, "need 0 < lo < hi <= 2");
   if (!(overcorrect > 0.0 && overcorrect <= 4.0)) return fail(c, EHDLB_EINVAL, "over-correction must lie in (0, 4]");
-  if (warm_start < 0 || warm_start > 3) return fail(c, EHDLB_EINVAL, "warm_start must be 0, 1, 2 or 3");
+  if (warm_start < 0 || warm_start > 4) return fail(c, EHDLB_EINVAL, "warm_start must be 0, 1, 2, 3 or 4");
   ++c->gen;
   c->mg_lo = lo;
   c->mg_hi = hi;

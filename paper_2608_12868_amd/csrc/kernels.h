@@ -1302,8 +1302,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_judge(CgCtl* __restrict__ ctl, co
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_cg_zero(const CgCtl* __restrict__ ctl, int64_t N, T* __restrict__ x) {
   if (!ctl->zero) return;
-  const int64_t i = gidx();
-  if (i < N) x[i] = T(0);
+  for (int64_t i = gidx(); i < N; i += (int64_t)gridDim.x * blockDim.x) x[i] = T(0);
 }
 
 // ---- warm start by Galerkin projection onto earlier solutions ------------------------------

@@ -192,11 +192,12 @@ class Simulation(Context):
         return {k: dict(solves=int(counts[2 * j]), iters=int(counts[2 * j + 1]), max_rel0=float(rel0[j]))
                 for j, k in enumerate(("forward", "adjoint"))}
 
-    def set_solver_options(self, lo=0.5, hi=2.0, overcorrect=2.0, warm_start=2):
+    def set_solver_options(self, lo=0.5, hi=2.0, overcorrect=2.0, warm_start=4):
         """Chebyshev smoothing interval [lo, hi] of D^-1 A, coarse-correction scale, and the
         forward warm start (0: previous step's potential; 1: extrapolated from the last two;
-        2: Galerkin projection onto the last four, then at least one CG iteration, the default;
-        3: the projection alone)."""
+        2: Galerkin projection onto the last four, then at least one CG iteration; 3: the
+        projection alone; 4, the default: 3 in step(), 2 in forward_checkpointed() and the
+        adjoint's recompute)."""
         self._chk(L.lib().ehdlb_set_solver_options(self.h, float(lo), float(hi), float(overcorrect),
                                                    int(warm_start)))
 

@@ -115,7 +115,8 @@ def test_calls_out_of_order(L):
     assert L.lib().ehdlb_bind(ctx.h, C.c_void_p(0x1000), 16, None) == L.ENOMEM             # too small
     assert L.lib().ehdlb_set_schedule(ctx.h, 9, 1, out.ctypes.data, 10) == L.EINVAL
     assert L.lib().ehdlb_set_solver_options(ctx.h, 0.5, 2.5, 2.0, 0) == L.EINVAL
-    assert L.lib().ehdlb_set_solver_options(ctx.h, 0.5, 2.0, 2.0, 4) == L.EINVAL
+    assert L.lib().ehdlb_set_solver_options(ctx.h, 0.5, 2.0, 2.0, 5) == L.EINVAL
+    assert L.lib().ehdlb_set_solver_options(ctx.h, 0.5, 2.0, 2.0, 4) == L.OK
 
 
 @pytest.mark.parametrize("name", ["c1s", "c2s", "c3s", "c2", "c3"])

@@ -162,3 +162,31 @@ def test_adjoint_cloaking_tensions_matches_oracle_autograd():
     err = np.abs(g_gpu - g_ref.numpy()).max() / np.abs(g_ref.numpy()).max()
     print("adjoint (cloaking tensions) vs oracle autograd", err, flush=True)
     assert err <= 1e-8
+
+
+def test_default_warm_start_differentiates_the_iterated_forward():
+    """With the default forward warm start (4), plain steps keep a projected start that meets the
+    tolerance, while the checkpointed forward and the adjoint's recompute iterate at least once
+    (mode 2): the FP32 gradient equals mode 2's bit for bit, and the plain forward's centroid
+    agrees with the checkpointed one to the FP32 solve's tolerance."""
+    case = make_case("c4s")
+    sched = case.schedule.copy()
+    T = t_total = 60
+    g, x = {}, {}
+    for warm in (4, 2):
+        sim = _sim(case, "fp32", poisson_tol=1e-5)
+        sim.set_solver_options(warm_start=warm)
+        sim.set_schedule(0, sched, t_total)
+        sim.forward_checkpointed(T, 10)
+        x[warm] = sim.observables()["centroid"]
+        g[warm] = sim.adjoint(GX, GV, 0, len(sched))
+        if warm == 4:
+            sim.set_phase(case.phi)
+            sim.solver_stats(reset=True)
+            sim.step(T)
+            x["plain"] = sim.observables()["centroid"]
+            it_plain = sim.solver_stats()["forward"]["iters"]
+    print("c4s fp32 T", T, "plain forward iterations", it_plain, "centroids", x, flush=True)
+    assert np.array_equal(g[4], g[2])
+    assert np.array_equal(x[4], x[2])
+    assert np.allclose(x["plain"], x[4], rtol=1e-5, atol=0)

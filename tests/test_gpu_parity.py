@@ -107,7 +107,7 @@ def test_fp32_centroid_trajectory():
 
 @pytest.mark.parametrize("name,precision,save_at,warm", [("c2s", "fp64", 20, 2), ("c3s", "fp32", 2, 2),
                                                          ("c3s", "fp32", 20, 3), ("c3s", "fp32", 20, 1),
-                                                         ("c2s", "fp64", 20, 0)])
+                                                         ("c2s", "fp64", 20, 0), ("c3s", "fp32", 20, 4)])
 def test_determinism_and_checkpoint_replay(name, precision, save_at, warm):
     """Two runs agree bit for bit, and so does a replay from a saved state: the potentials that the
     warm starts use (the last four for the projection, t = 2 leaves a partial history) are part
