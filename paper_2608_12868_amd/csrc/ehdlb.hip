@@ -530,7 +530,7 @@ static ehdlb_status vcycle(ehdlb_ctx* c, size_t lvl, T* r, T** zout, double* dot
 // depend on this.
 template <class LT, class T>
 static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hist, int min1 = 0,
-                        const std::function<void()>* spec = nullptr) {
+                        const std::function<void()>* spec = nullptr, bool projected = false) {
   constexpr int D = LT::D;
   hipStream_t s = c->stream;
   const int64_t N = c->N;
@@ -558,7 +558,9 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
   hipLaunchKernelGGL(k_cg_judge, dim3(1), dim3(kBlock), 0, s, ctl, (const double*)ptrue, (const double*)pmax, rb0,
                      tol, eps_t, 0, 0, 1, min1);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_cg_zero<T>, dim3(std::min(nb0, kZeroBlocks)), dim3(kBlock), 0, s, (const CgCtl*)ctl, N, x);
+  // (a projected start is already 0 then: the Galerkin right-hand side u_i . b vanishes)
+  if (!projected)
+    hipLaunchKernelGGL(k_cg_zero<T>, dim3(std::min(nb0, kZeroBlocks)), dim3(kBlock), 0, s, (const CgCtl*)ctl, N, x);
   // The host reads the control block after an event that follows its copy, not after the whole
   // stream: `spec` (if given) queues work that depends on the solution behind the copy, gated
   // on the device by the stop flag, so it runs without a host round trip when the solve has
@@ -740,7 +742,8 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
   // mode 2: at least one CG iteration after the projected start (a solve that keeps the start
   // leaves an error that is carried into the next steps' starts, correlated from step to step,
   // and biases the gradients of the trajectory)
-  return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b), c->cg_hist[0], mode == 2 ? 1 : 0, spec);
+  return pcg<LT, T>(c, c->ptr<T>(c->off_pot), c->ptr<T>(c->off_b), c->cg_hist[0], mode == 2 ? 1 : 0, spec,
+                    mode >= 2 && c->t >= 1);
 }
 
 // ============================================================================ timing

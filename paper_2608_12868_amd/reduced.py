@@ -207,3 +207,41 @@ def two_electrode_switch_times(u, alpha0, half_gap, s_sw, t_sw1=None):
     x1 = half_gap - s_e1
     t2 = _leg_time(x1, -(half_gap - s_sw), u, alpha0, half_gap + x1, s_sw)
     return t_sw1, t_sw1 + t2, x1
+
+
+# ------------------------------------------------------------------ long-distance transport (Fig. 5c)
+def relay_switch_times(u, alpha0, s0, pitch, s_sw, n_electrodes=3):
+    """The long-distance protocol of the Results (Fig. 5c) in the overdamped form of Eq. 5:
+    electrodes at a fixed pitch ahead of the droplet, the first at distance s0; each is switched
+    off, and the next one on, when the droplet's distance to it falls to s_sw.  u is the pull
+    velocity at zero distance.  Returns (switch times, arrival time at s_sw from the last
+    electrode), times from the start; the droplet has then travelled s0 - s_sw + (n - 1) pitch."""
+    if not (s0 > s_sw and pitch > 0 and s_sw >= 0 and n_electrodes >= 1):
+        raise ValueError("need s0 > s_sw >= 0 and pitch > 0")
+    t, times = 0.0, []
+    dist = s0
+    for k in range(n_electrodes):
+        t += _leg_time(0.0, dist - s_sw, u, alpha0, dist, s_sw)
+        times.append(t)
+        dist = s_sw + pitch
+    return times[:-1], times[-1]
+
+
+def relay_position(t, u, alpha0, s0, pitch, s_sw, switch_times):
+    """Displacement at times t under the relay protocol with the given switch times (the droplet
+    keeps moving towards the last electrode after the last switch), from the overdamped law: under
+    an electrode at distance S, exp(2 alpha0 S) falls at the rate 2 alpha0 u."""
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    out = np.empty_like(t)
+    for i, ti in enumerate(t):
+        x, t0, dist0 = 0.0, 0.0, s0   # displacement and electrode distance at the stage start
+        for k, ts in enumerate(list(switch_times) + [math.inf]):
+            tend = min(ti, ts)
+            e = math.exp(2.0 * alpha0 * dist0) - 2.0 * alpha0 * u * (tend - t0)
+            d = math.log(e) / (2.0 * alpha0) if e > 1.0 else 0.0   # at the electrode: stays there
+            x += dist0 - d
+            if ti <= ts:
+                break
+            t0, dist0 = ts, d + pitch
+        out[i] = x
+    return out

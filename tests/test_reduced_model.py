@@ -167,3 +167,31 @@ def test_two_electrode_switch_times_and_sensitivity():
     assert abs(late[1] / t2 - 1) > 0.1 and abs(early[1] / t2 - 1) > 0.1
     with pytest.raises(ValueError):
         rm.two_electrode_switch_times(u, a0, half, s_sw, t_sw1=10 * t1)
+
+
+def test_relay_switch_times_and_positions():
+    """The long-distance protocol (Results, Fig. 5c) in the overdamped Eq. 5: electrodes at a
+    fixed pitch, each switched off when the droplet is s_sw from it.  The closed-form switch
+    times agree with a direct integration of dS/dt = u exp(-2 alpha0 S_e) under the active
+    electrode, and the displacement at each switch is s0 - s_sw + k pitch."""
+    u, a0, s0, pitch, s_sw = 7.7e-4, 0.02533, 48.0, 24.0, 18.0
+    sw, arrive = rm.relay_switch_times(u, a0, s0, pitch, s_sw, 3)
+    assert len(sw) == 2 and sw[0] < sw[1] < arrive
+    x, t, dt, k, hits = 0.0, 0.0, 1.0, 0, []
+    edge = s0
+    while k < 3:
+        x += dt * u * math.exp(-2 * a0 * (edge - x))
+        t += dt
+        if edge - x <= s_sw:
+            hits.append(t)
+            edge += pitch
+            k += 1
+    for a, b in zip(hits, list(sw) + [arrive]):
+        assert a / b == pytest.approx(1.0, abs=1e-3)
+    pos = rm.relay_position(list(sw) + [arrive], u, a0, s0, pitch, s_sw, sw)
+    assert pos == pytest.approx([s0 - s_sw, s0 - s_sw + pitch, s0 - s_sw + 2 * pitch], abs=1e-9)
+    # after the last switch the droplet keeps approaching the last electrode, never past it
+    late = rm.relay_position([10 * arrive], u, a0, s0, pitch, s_sw, sw)[0]
+    assert s0 - s_sw + 2 * pitch < late <= s0 + 2 * pitch
+    with pytest.raises(ValueError):
+        rm.relay_switch_times(u, a0, s_sw, pitch, s_sw)
