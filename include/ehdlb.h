@@ -101,7 +101,8 @@ typedef struct {
   double cond[3];           /* conductivity per phase (>= 0), mixed linearly              */
   double charge_diffusion;  /* alpha of Eq. 14 (>= 0)                                     */
   double body_force[3];     /* uniform body force density                                 */
-  double electrode_volts[EHDLB_MAX_ELECTRODES];  /* constant V_k unless a schedule is set */
+  double electrode_volts[EHDLB_MAX_ELECTRODES];  /* constant V_k unless a schedule is set;
+                                                    NaN: switched off and floating (below) */
   double poisson_tol;       /* stop when max|b - A phi| <= tol * max|b| (residual in FP64),
                                or when it reaches the rounding floor of phi stored in the
                                path's precision, 8 eps max_i sum_j |A_ij phi_j|           */
@@ -171,8 +172,15 @@ ehdlb_status ehdlb_set_charge(ehdlb_ctx* ctx, const double* rho_e);
 
 /* Piecewise-constant voltage schedule of electrode k: during step t (0-based)
  * the electrode holds volts[s] with s = floor(t * n_seg / t_total), clamped to
- * n_seg - 1 for t >= t_total.  The array is copied.  EINVAL on k out of range,
- * n_seg < 1 or t_total < 1.  n_seg = 0 clears the schedule. */
+ * n_seg - 1 for t >= t_total.  The array is copied.  A NaN voltage switches
+ * the electrode off and leaves it floating for that segment: its faces then
+ * carry no flux (insulating, as the walls without electrodes), the reading of
+ * the switching protocols of the Results (Fig. 5), where an electrode that is
+ * switched off stops acting on the droplet; the adjoint's dL/dV of such a
+ * segment is 0.  A region whose only Dirichlet faces float has a singular
+ * potential problem (the solve then reports ENOCONV).  EINVAL on k out of
+ * range, n_seg < 0, t_total < 1 or an infinite voltage.  n_seg = 0 clears the
+ * schedule. */
 ehdlb_status ehdlb_set_schedule(ehdlb_ctx* ctx, int32_t electrode, int32_t n_seg,
                                 const double* volts, int64_t t_total);
 

@@ -26,9 +26,9 @@ def observables_after(oracle, phi0, volts_seg, T, t_total, electrode=0, rho0=Non
     n_seg = volts_seg.numel()
     for t in range(T):
         seg = segment_of(t, n_seg, t_total)
-        onehot = torch.zeros(base.numel(), dtype=F64)
-        onehot[electrode] = 1.0
-        volts = base * (1 - onehot) + onehot * volts_seg[seg]
+        sel = torch.zeros(base.numel(), dtype=torch.bool)
+        sel[electrode] = True
+        volts = torch.where(sel, volts_seg[seg], base)   # (NaN: a floating electrode)
         s, _ = oracle.step(s, volts)
     ob = oracle.observables(s)
     return ob["centroid"], ob["velocity"]

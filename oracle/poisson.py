@@ -9,7 +9,8 @@ finite-volume form of Eq. 13 on the axis faces of every fluid node,
     c_f = (eps_x + eps_nb)/2              fluid neighbour,
     c_f = 2 eps_x, phi_nb -> phi_D       grounded (phi_D = 0) or electrode (phi_D = V_k)
                                          solid neighbour: Dirichlet on the half-cell face,
-    no flux                              insulating solid neighbour,
+    no flux                              insulating solid neighbour, or an electrode whose
+                                         voltage is NaN (switched off and left floating),
 
 with the boundary conditions stated with Fig. 1 (pillars and substrate at zero
 potential, electrode at its potential, Neumann on the other walls).  The oracle
@@ -59,10 +60,16 @@ class PotentialSystem:
         self.dir_k = np.concatenate(dir_k)
 
     def assemble(self, eps_f, rho_f, volts):
-        """Matrix and right-hand side over the fluid unknowns (numpy float64)."""
+        """Matrix and right-hand side over the fluid unknowns (numpy float64).  An electrode
+        whose voltage is NaN is floating: its faces carry no flux (insulating)."""
         nf = self.nf
+        volts = np.asarray(volts, dtype=np.float64)
+        el = self.dir_k >= 0
+        floating = np.zeros(self.dir_k.size, dtype=bool)
+        if el.any():
+            floating[el] = np.isnan(volts[self.dir_k[el]])
         c = 0.5 * (eps_f[self.ff_i] + eps_f[self.ff_j])
-        cd = 2.0 * eps_f[self.dir_i]
+        cd = np.where(floating, 0.0, 2.0 * eps_f[self.dir_i])
         diag = np.zeros(nf)
         np.add.at(diag, self.ff_i, c)
         np.add.at(diag, self.ff_j, c)
@@ -71,7 +78,7 @@ class PotentialSystem:
         cols = np.concatenate([np.arange(nf), self.ff_j, self.ff_i])
         vals = np.concatenate([diag, -c, -c])
         A = sp.csc_matrix((vals, (rows, cols)), shape=(nf, nf))
-        phid = np.where(self.dir_k >= 0, np.asarray(volts)[np.maximum(self.dir_k, 0)], 0.0)
+        phid = np.where(el & ~floating, volts[np.maximum(self.dir_k, 0)], 0.0)
         b = rho_f.copy()
         np.add.at(b, self.dir_i, cd * phid)
         return A, b, c, cd, phid
@@ -131,6 +138,7 @@ class _Solve(torch.autograd.Function):
         ctx.x = x
         ctx.phid = phid
         ctx.cd = cd
+        ctx.active = cd != 0.0
         ctx.nvolts = volts.numel()
         return phi
 
@@ -149,7 +157,7 @@ class _Solve(torch.autograd.Function):
         np.add.at(g_eps_f, s.ff_i, 0.5 * dc)
         np.add.at(g_eps_f, s.ff_j, 0.5 * dc)
         # Dirichlet faces: A_ii += c, b_i += c phi_D -> dL/dc = lam_i (phi_D - x_i); c = 2 eps_i
-        dcd = lam[s.dir_i] * (ctx.phid - x[s.dir_i])
+        dcd = np.where(ctx.active, lam[s.dir_i] * (ctx.phid - x[s.dir_i]), 0.0)   # floating faces: none
         np.add.at(g_eps_f, s.dir_i, 2.0 * dcd)
         g_eps = np.zeros(N)
         g_eps[fidx] = g_eps_f

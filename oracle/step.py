@@ -133,8 +133,11 @@ class Oracle:
     # ------------------------------------------------------------ O6 helper
     def axis_values(self, pot, volts):
         """phi at x +- e_a for every axis a < dim, with solid neighbours replaced by their
-        mirror across the face: 2 phi_D - phi(x) (Dirichlet) or phi(x) (insulating)."""
+        mirror across the face: 2 phi_D - phi(x) (Dirichlet) or phi(x) (insulating, and an
+        electrode whose voltage is NaN: switched off and floating)."""
         geom, lat = self.geom, self.lat
+        off = torch.isnan(volts)
+        vs = torch.where(off, torch.zeros_like(volts), volts)
         out = []
         for a in range(lat.dim):
             pair = []
@@ -143,12 +146,13 @@ class Oracle:
                 fy = geom.flags[y]
                 vy = pot[y]
                 phid = torch.zeros(self.N, dtype=F64)
-                el = fy >= 3
+                k = (fy - 3).clamp(min=0)
+                el = (fy >= 3) & ~off[k]
                 if el.any():
-                    phid = torch.where(el, volts[(fy - 3).clamp(min=0)], phid)
+                    phid = torch.where(el, vs[k], phid)
                 dirich = (fy == 1) | el
                 v = torch.where(fy == 0, vy, torch.where(dirich, 2.0 * phid - pot, pot))
-                pair.append((v, fy, phid))
+                pair.append((v, fy, phid, dirich))
             out.append(pair)
         return out
 
@@ -160,11 +164,10 @@ class Oracle:
         for a in range(lat.dim):
             for k, q in enumerate(lat.axis_dirs[a]):
                 y = geom.nbr[q]
-                _, fy, phid = axes[a][k]
+                _, fy, phid, dirich = axes[a][k]
                 fluid_face = 0.5 * (sig + sig[y]) * (pot[y] - pot)
                 dir_face = 2.0 * sig * (phid - pot)
-                Q = Q + torch.where(fy == 0, fluid_face,
-                                    torch.where((fy == 1) | (fy >= 3), dir_face, torch.zeros_like(pot)))
+                Q = Q + torch.where(fy == 0, fluid_face, torch.where(dirich, dir_face, torch.zeros_like(pot)))
         return Q * self.fl
 
     # ------------------------------------------------------------ streaming

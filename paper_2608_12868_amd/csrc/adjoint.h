@@ -139,7 +139,7 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
       f.fm = a.flags[m];
       f.sig = p.cond[0] * R(RL::PHI, m) + p.cond[1] * R(RL::PHI + 1, m) + p.cond[2] * R(RL::PHI + 2, m);
       f.pn = f.fm == 0 ? R(RL::POT, m) : T(0);
-      f.pd = (f.fm == 1 || f.fm >= 3) ? (f.fm == 1 ? T(0) : a.volts.v[f.fm - 3]) : T(0);
+      f.pd = dirichlet_face(f.fm, a.volts) ? (f.fm == 1 ? T(0) : a.volts.v[f.fm - 3]) : T(0);
       return f;
     };
     T E[3] = {0, 0, 0}, ge[3] = {0, 0, 0};
@@ -157,7 +157,7 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
           if (f.fm == 0) {
             side[k] = f.pn;
             Qs += T(0.5) * (sigx + f.sig) * (f.pn - phx);
-          } else if (f.fm == 1 || f.fm >= 3) {
+          } else if (dirichlet_face(f.fm, a.volts)) {
             side[k] = T(2) * f.pd - phx;
             Qs += T(2) * sigx * (f.pd - phx);
           } else {
@@ -484,7 +484,7 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
             lsn = T(0.5) * dphi * lQs;
             lpn = hs * lQs + lside;
             lpot -= hs * lQs;
-          } else if (fm == 1 || fm >= 3) {
+          } else if (dirichlet_face(fm, a.volts)) {
             lsigx += T(2) * (f.pd - phx) * lQs;
             lpot -= T(2) * sigx * lQs + lside;
             if (fm >= 3) vloc[fm - 3] += (double)(T(2) * sigx * lQs + T(2) * lside);
@@ -686,7 +686,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_cd(Dims d, const uint8_t* __rest
             const uint8_t fm = flags[m];
             if (fm == 0) {
               leps += -T(0.5) * (lbx - lb[m]) * (phx - rec[(int64_t)RL::POT * N + m]);
-            } else if (fm == 1 || fm >= 3) {
+            } else if (dirichlet_face(fm, volts)) {
               const T pd = fm == 1 ? T(0) : volts.v[fm - 3];
               leps += T(2) * lbx * (pd - phx);
               if (fm >= 3) vloc[fm - 3] += (double)(T(2) * ex * lbx);

@@ -241,6 +241,20 @@ static double volts_at(const ehdlb_ctx* c, int k, int64_t t) {
   return s.v[(size_t)seg];
 }
 
+// electrode voltages of step t for the kernels: NaN (switched off, floating) -> 0 and the
+// electrode's bit in off
+template <class T>
+static Volts<T> volts_of(const ehdlb_ctx* c, int64_t t) {
+  Volts<T> v{};
+  for (int e = 0; e < kMaxE; ++e) {
+    const double x = volts_at(c, e, t);
+    const bool floating = std::isnan(x);
+    v.v[e] = floating ? T(0) : (T)x;
+    if (floating) v.off |= 1u << e;
+  }
+  return v;
+}
+
 // lattice tables on the host (same canonical order as the device)
 static void host_lattice(int dim, std::vector<int>& ex, std::vector<int>& ey, std::vector<int>& ez,
                          std::vector<int>& w36) {
@@ -406,6 +420,8 @@ static ehdlb_status validate(ehdlb_ctx* c, const ehdlb_lattice* L, const ehdlb_p
     if (!(p->poisson_tol > 0.0)) return fail(c, EHDLB_EINVAL, "poisson_tol must be > 0");
     if (p->poisson_max_iter < 1) return fail(c, EHDLB_EINVAL, "poisson_max_iter must be >= 1");
     if (p->poisson_check_every < 1) return fail(c, EHDLB_EINVAL, "poisson_check_every must be >= 1");
+    for (int e = 0; e < EHDLB_MAX_ELECTRODES; ++e)
+      if (std::isinf(p->electrode_volts[e])) return fail(c, EHDLB_EINVAL, "electrode voltages must be finite or NaN");
   }
   return EHDLB_OK;
 }
@@ -821,8 +837,7 @@ static ehdlb_status step_impl(ehdlb_ctx* c, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
     const int64_t t = c->t;
     const int pi = (int)(t & 1), pp = 1 - pi;
-    Volts<T> v{};
-    for (int e = 0; e < kMaxE; ++e) v.v[e] = (T)volts_at(c, e, t);
+    const Volts<T> v = volts_of<T>(c, t);
     T* phi = c->ptr<T>(c->off_phi[pi]);
     T* rho = c->ptr<T>(c->off_rho[pi]);
     const T* pin = c->ptr<T>(c->off_pop[c->cur]);
@@ -1152,8 +1167,7 @@ static ehdlb_status step_record(ehdlb_ctx* c, T* rec) {
   const int G = (int)c->ghost_node.size();
   const int64_t t = c->t;
   const int pi = (int)(t & 1), pp = 1 - pi;
-  Volts<T> v{};
-  for (int e = 0; e < kMaxE; ++e) v.v[e] = (T)volts_at(c, e, t);
+  const Volts<T> v = volts_of<T>(c, t);
   T* phi = c->ptr<T>(c->off_phi[pi]);
   T* rho = c->ptr<T>(c->off_rho[pi]);
   const T* pin = c->ptr<T>(c->off_pop[c->cur]);
@@ -1237,8 +1251,7 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
   const Phys<T> ph = make_phys<T>(c->prm);
   const uint8_t* flags = c->ptr<uint8_t>(c->off_flags);
   auto A = [&](size_t off) { return reinterpret_cast<T*>(J.ws + off); };
-  Volts<T> v{};
-  for (int e = 0; e < kMaxE; ++e) v.v[e] = (T)volts_at(c, e, t);
+  const Volts<T> v = volts_of<T>(c, t);
   const int nb = nblocks(N);
   const size_t lbx = J.lb;
   AdjArgs<T> a{};
@@ -1659,6 +1672,8 @@ ehdlb_status ehdlb_set_schedule(ehdlb_ctx* c, int32_t k, int32_t n_seg, const do
     return EHDLB_OK;
   }
   if (n_seg < 0 || !volts || t_total < 1) return fail(c, EHDLB_EINVAL, "bad schedule");
+  for (int32_t s = 0; s < n_seg; ++s)
+    if (std::isinf(volts[s])) return fail(c, EHDLB_EINVAL, "schedule voltages must be finite or NaN (floating)");
   c->sched[k].v.assign(volts, volts + n_seg);
   c->sched[k].t_total = t_total;
   return EHDLB_OK;

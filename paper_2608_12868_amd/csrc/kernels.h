@@ -118,7 +118,14 @@ struct Phys {
 template <class T>
 struct Volts {
   T v[kMaxE];
+  unsigned off;  // bit e: electrode e is switched off and floating (its faces insulate; v[e] = 0)
 };
+
+// Dirichlet face towards a solid neighbour of flag fm: grounded, or an electrode that is on
+template <class T>
+__device__ __forceinline__ bool dirichlet_face(uint8_t fm, const Volts<T>& volts) {
+  return fm == 1 || (fm >= 3 && !((volts.off >> (fm - 3)) & 1u));
+}
 
 template <class T>
 struct StepArgs {
@@ -500,11 +507,11 @@ __global__ __launch_bounds__(kBlock) void k_pois_setup(Dims d, const uint8_t* __
       const int m = neighbour<L>(d, x, y, z, q);
       const uint8_t fm = flags[m];
       const T em = p.eps[0] * phi[m] + p.eps[1] * phi[N + m] + p.eps[2] * phi[2 * N + m];
-      const bool fluid = fm == 0, dirichlet = fm == 1 || fm >= 3;
+      const bool fluid = fm == 0, dirichlet = dirichlet_face(fm, volts);
       const T c = fluid ? T(0.5) * (ex + em) : T(0);
       const T cd = T(2) * ex;
       dg += fluid ? c : (dirichlet ? cd : T(0));
-      if (fm >= 3) rhs += cd * volts.v[fm - 3];
+      if (fm >= 3 && dirichlet) rhs += cd * volts.v[fm - 3];
       if (k == 0) cp[(int64_t)ax * N + node] = c;
     }
   }

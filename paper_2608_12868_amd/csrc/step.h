@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
           const T v = a.pot[nb[q]];
           side[k] = v;
           Qs += T(0.5) * (sigx + sig_ax[2 * ax + k]) * (v - phx);
-        } else if (fm == 1 || fm >= 3) {
+        } else if (dirichlet_face(fm, a.volts)) {
           const T pd = fm == 1 ? T(0) : a.volts.v[fm - 3];
           side[k] = T(2) * pd - phx;
           Qs += T(2) * sigx * (pd - phx);

@@ -9,6 +9,8 @@ of the linearised residual, r + J dV = 0, over the segments that are not held at
 (projected Gauss-Newton), halving it until |r| decreases.  Host-side driver only: every forward
 step and every adjoint step runs in the library.
 """
+import math
+
 import numpy as np
 
 
@@ -116,3 +118,20 @@ def design_switch_time(sim, phi0, t_sw0, target, volts, n_seg, T, K, axis=0, ele
         t, x, d = t_new, x_new, d_new
         history.append(dict(iteration=k, t_sw=t, residual=x - target, slope=d))
     return t, history
+
+
+def relay_schedules(switch_times, volts, n_electrodes, t_total, seg_len):
+    """Schedules of the long-distance protocol (Results, Fig. 5c): electrode k holds `volts` from
+    switch k - 1 to switch k (the last one to the end) and floats otherwise (NaN: switched off,
+    its faces insulate).  Segments of seg_len steps over t_total; a switch takes effect at the
+    segment boundary nearest to it.  Returns (list of per-electrode arrays, switch steps used)."""
+    n_seg = int(math.ceil(t_total / seg_len))
+    edges = [int(round(t / seg_len)) for t in switch_times]
+    bounds = [0] + edges + [n_seg]
+    out = []
+    for k in range(n_electrodes):
+        v = np.full(n_seg, np.nan)
+        if k < len(bounds) - 1:
+            v[bounds[k]:bounds[k + 1]] = volts
+        out.append(v)
+    return out, [e * seg_len for e in edges]

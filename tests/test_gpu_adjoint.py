@@ -190,3 +190,31 @@ def test_default_warm_start_differentiates_the_iterated_forward():
     assert np.array_equal(g[4], g[2])
     assert np.array_equal(x[4], x[2])
     assert np.allclose(x["plain"], x[4], rtol=1e-5, atol=0)
+
+
+def test_adjoint_with_floating_segment_matches_oracle_autograd():
+    """Electrode 1 on, floating (NaN), on: the reverse sweep treats its faces as insulating in
+    the floating segment (dL/dV = 0 there) and as Dirichlet elsewhere."""
+    from inputs.presets import ELECTRODE0
+    from oracle import Oracle
+    from oracle.adjoint import schedule_gradient
+    case = make_case("c4s", precision="fp64")
+    n = case.n
+    fl = case.flags.copy().reshape(n[1], n[0])
+    fl[n[1] - 1, 2:18] = ELECTRODE0 + 1
+    fl = fl.reshape(-1)
+    sched = np.array([0.04, np.nan, 0.06])
+    T = t_total = 18
+    sim = _sim(case)
+    sim.set_geometry(fl)
+    sim.set_phase(case.phi)
+    sim.set_schedule(1, sched, t_total)
+    sim.forward_checkpointed(T, 5)
+    g = sim.adjoint(GX, GV, 1, len(sched))
+    o = Oracle(case.dim, case.n, case.periodic, case.params, fl)
+    g_ref, _, _ = schedule_gradient(o, case.phi, sched, T, t_total, GX, GV, electrode=1)
+    g_ref = g_ref.numpy()
+    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    print("adjoint with a floating segment vs oracle autograd", err, g, g_ref, flush=True)
+    assert g[1] == 0.0 and g_ref[1] == 0.0
+    assert err <= 1e-8

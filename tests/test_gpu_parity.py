@@ -282,3 +282,60 @@ def test_fp64_parity_cloaking_tensions():
     sim.step(100)
     o, s, aux = gu.oracle_run(case, 100, params=over)
     _compare(sim, o, s, aux, FP64_TOL)
+
+
+def _two_electrodes(case, second=None):
+    """c2s/c3s geometry with a second electrode on the top wall behind the droplet (flag
+    `second`, default electrode 1)."""
+    from inputs.presets import ELECTRODE0
+    n = case.n
+    f = case.flags.copy()
+    if case.dim == 2:
+        f = f.reshape(n[1], n[0])
+        f[n[1] - 1, 2:22] = ELECTRODE0 + 1 if second is None else second
+    else:
+        f = f.reshape(n[2], n[1], n[0])
+        f[n[2] - 1, :, 1:7] = ELECTRODE0 + 1 if second is None else second
+    return f.reshape(-1)
+
+
+@pytest.mark.parametrize("name,steps", [("c2s", 60), ("c3s", 6)])
+def test_fp64_parity_floating_electrode(name, steps):
+    """An electrode switched off and floating (NaN in its schedule): electrode 1 is on, floating,
+    then on again while electrode 0 holds its voltage; fields against the oracle."""
+    import torch
+    from oracle import Oracle
+    case = make_case(name, precision="fp64")
+    fl = _two_electrodes(case)
+    sched = np.array([0.04, np.nan, 0.06])
+    sim = _gpu(case)
+    sim.set_geometry(fl)
+    sim.set_phase(case.phi)
+    sim.set_schedule(1, sched, steps)
+    sim.step(steps)
+    V = case.params["electrode_volts"][0]
+    o = Oracle(case.dim, case.n, case.periodic, case.params, fl)
+    s = o.init_state(case.phi)
+    aux = None
+    for t in range(steps):
+        seg = min(t * 3 // steps, 2)
+        s, aux = o.step(s, torch.tensor([V, sched[seg], 0.0, 0.0], dtype=torch.float64))
+    print("case", name, case.n, "steps", steps, "electrode 1 schedule", sched, flush=True)
+    _compare(sim, o, s, aux, FP64_TOL)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_floating_electrode_equals_insulating_wall(precision):
+    """A floating electrode and an insulating wall in its place give the same bits."""
+    from inputs.presets import NEUMANN
+    case = make_case("c2s", precision=precision)
+    out = []
+    for fl, v1 in ((_two_electrodes(case), np.nan), (_two_electrodes(case, NEUMANN), 0.0)):
+        sim = _gpu(case, precision, poisson_tol=1e-13 if precision == "fp64" else 1e-5)
+        sim.set_geometry(fl)
+        sim.set_phase(case.phi)
+        sim.set_schedule(1, np.array([v1]), 1)
+        sim.step(40)
+        out.append(sim.field("pops"))
+    print("c2s", precision, "floating vs insulating: max |diff|", np.abs(out[0] - out[1]).max(), flush=True)
+    assert np.array_equal(out[0], out[1])

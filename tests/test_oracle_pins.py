@@ -678,3 +678,51 @@ def test_v15_cloaking_tensions_spread_the_lubricant():
     print("droplet/ambient contact every 1000 steps", c)
     assert all(b < a for a, b in zip(c, c[1:]))
     assert c[-1] < 0.5 * c[0]
+
+
+# ---------------------------------------------------------------- V16
+def test_v16_floating_electrode_is_an_insulating_wall():
+    """An electrode switched off and left floating (voltage NaN, the reading of the switching
+    protocols of the Results, Fig. 5) carries no flux: every field equals, bit for bit, that of
+    the same geometry with the electrode's nodes flagged insulating, while a second electrode
+    drives the droplet; its schedule gradient is zero on the floating segments and matches
+    central differences elsewhere."""
+    from oracle.adjoint import schedule_gradient, observables_after
+    case = make_case("c2s", precision="fp64")
+    n = case.n
+    f2 = case.flags.copy().reshape(n[1], n[0])
+    f2[n[1] - 1, 2:22] = ELECTRODE0 + 1                 # electrode 1 behind the droplet
+    fl_float = f2.reshape(-1)
+    fl_ins = f2.copy()
+    fl_ins[n[1] - 1, 2:22] = NEUMANN
+    fl_ins = fl_ins.reshape(-1)
+    V = case.params["electrode_volts"][0]
+    out = []
+    for fl, volts in ((fl_float, (V, float("nan"), 0.0, 0.0)), (fl_ins, (V, 0.0, 0.0, 0.0))):
+        o = Oracle(2, n, case.periodic, case.params, fl)
+        s = o.init_state(case.phi)
+        for _ in range(6):
+            s, aux = o.step(s, torch.tensor(volts, dtype=F64))
+        out.append((o.fields(s), aux["pot"]))
+    (fa, pa), (fb, pb) = out
+    for k in fa:
+        assert torch.equal(fa[k], fb[k]), k
+    assert torch.equal(pa, pb)
+    assert float(pa.abs().max()) > 0.0 and float(fa["rho_e"].abs().max()) > 0.0
+    # schedule of electrode 1: on, floating, on; electrode 0 held at V
+    o = Oracle(2, n, case.periodic, case.params, fl_float)
+    sched = torch.tensor([0.03, float("nan"), 0.05], dtype=F64)
+    T = 9
+    gx, gv = np.array([1.0, 0.5, 0.0]), np.array([20.0, -10.0, 0.0])
+    g, _, _ = schedule_gradient(o, case.phi, sched, T, T, gx, gv, electrode=1)
+    assert g[1].item() == 0.0 and g[0].item() != 0.0 and g[2].item() != 0.0
+    h = 1e-3    # the loss carries the ~60 lu centroid: smaller steps meet FP64 round-off
+    for k in (0, 2):
+        vals = []
+        for sg in (1, -1):
+            v = sched.clone()
+            v[k] += sg * h
+            xc, vc = observables_after(o, case.phi, v, T, T, electrode=1)
+            vals.append(float((torch.tensor(gx) * xc).sum() + (torch.tensor(gv) * vc).sum()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[k].item()) <= 1e-5 * abs(fd)
