@@ -88,15 +88,20 @@ def copy_ceiling(nbytes=1 << 30, reps=10):
     return dict(bytes_per_copy=2 * nbytes, gbs=2 * nbytes / (ms * 1e-3) / 1e9)
 
 
-# adjoint legs: workload, T, K, central-difference directions, FP64 adjoint, every warm start, description
+# adjoint legs: workload, steps before the window, T, K, central-difference directions, FP64 adjoint,
+# every warm start, description
 ADJOINT = {
-    "c4": ("c4", 4000, 100, 3, True, True,
+    "c4": ("c4", 0, 4000, 100, 3, True, True,
            "2D D2Q9 ternary EHD LB, 512x256 (pillars, droplet R=40, electrode), FP32-deviation storage, 64-segment "
            "voltage schedule, T=4000, checkpoint every 100 steps"),
-    "c5": ("c5", 200, 50, 1, False, False,
+    "c5": ("c5", 0, 200, 50, 1, False, False,
            "3D D3Q19 ternary EHD LB, 384x192x128 (pillars pitch 12, droplet R=48, electrode strip), FP32-deviation "
-           "storage, the 32-segment schedule over T=200 (of its 2000), checkpoint every 50"),
-    "c5full": ("c5", 2000, 50, 1, False, True,
+           "storage, the 32-segment schedule, steps 0-200 (of its 2000), checkpoint every 50"),
+    "c5late": ("c5", 600, 200, 50, 1, False, False,
+               "3D D3Q19 ternary EHD LB, 384x192x128 (pillars pitch 12, droplet R=48, electrode strip), "
+               "FP32-deviation storage, the 32-segment schedule, steps 600-800 (of its 2000; the first 600 run "
+               "untimed), checkpoint every 50"),
+    "c5full": ("c5", 0, 2000, 50, 1, False, True,
                "3D D3Q19 ternary EHD LB, 384x192x128 (pillars pitch 12, droplet R=48, electrode strip), "
                "FP32-deviation storage, 32-segment schedule, T=2000, checkpoint every 50"),
 }
@@ -117,7 +122,7 @@ def adjoint_leg(key, seed=1):
     import torch
     from inputs import make_case
     from paper_2608_12868_amd import Simulation
-    name, T, K, ndir, with_fp64_adjoint, all_modes, desc = ADJOINT[key]
+    name, start, T, K, ndir, with_fp64_adjoint, all_modes, desc = ADJOINT[key]
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
     case = make_case(name)
@@ -132,6 +137,7 @@ def adjoint_leg(key, seed=1):
         sim.set_phase(case.phi)
         if target is None:
             target = sim.observables()["centroid"][0] + 5.0
+        sim.step(start)
         sim.solver_stats(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -145,6 +151,7 @@ def adjoint_leg(key, seed=1):
             # tolerance, only the gradient's forward iterates at least once (as mode 2)
             sim.set_solver_options(warm_start=4)
             sim.set_phase(case.phi)
+            sim.step(start)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sim.step(T)
@@ -152,6 +159,7 @@ def adjoint_leg(key, seed=1):
             default_fwd = time.perf_counter() - t0
             sim.set_solver_options(warm_start=mode)
         sim.set_phase(case.phi)
+        sim.step(start)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sim.forward_checkpointed(T, K)
@@ -186,7 +194,10 @@ def adjoint_leg(key, seed=1):
     t64 = {}
 
     def loss(v):
+        # the schedule perturbed from the window's start (the gradient covers the window only)
         s64.set_phase(case64.phi)
+        s64.set_schedule(0, case64.schedule, case64.t_total)
+        s64.step(start)
         s64.set_schedule(0, v, case64.t_total)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -199,6 +210,7 @@ def adjoint_leg(key, seed=1):
         loss(case64.schedule)
         s64.set_phase(case64.phi)
         s64.set_schedule(0, case64.schedule, case64.t_total)
+        s64.step(start)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s64.forward_checkpointed(T, K)
@@ -236,7 +248,7 @@ def adjoint_leg(key, seed=1):
             row[f"h={h:g}"] = r_h
         print(f"adjoint leg {key}: central difference {len(fd) + 1}/{ndir} done", file=sys.stderr, flush=True)
         fd.append(row)
-    out = {"workload": desc, "dtype": "f32", "T": T, "K": K, "adjoint_workspace_gb": ws, "peak_hbm_gb": peak32,
+    out = {"workload": desc, "dtype": "f32", "start_step": start, "T": T, "K": K, "adjoint_workspace_gb": ws, "peak_hbm_gb": peak32,
            "fd_h": list(FD_H), "fd_directions": fd}
 
     def worst(key_, h):
@@ -289,10 +301,10 @@ def main():
     ap.add_argument("--no-copy-probe", action="store_true",
                     help="skip the plain 1 GiB device copy (practical bandwidth ceiling; the "
                          "calibration kernel of the rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
-    ap.add_argument("--adjoint", default="c4,c5",
+    ap.add_argument("--adjoint", default="c4,c5,c5late",
                     help="comma-separated adjoint legs: c4 (2D 512x256, T = 4000, every forward warm "
-                         "start), c5 (3D 384x192x128 over T = 200), c5full (3D at T = 2000: about "
-                         "250 GB of HBM and two minutes), or none")
+                         "start), c5 (3D 384x192x128, steps 0-200), c5late (3D, steps 600-800), c5full "
+                         "(3D at T = 2000: about 250 GB of HBM and two minutes), or none")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the step is built for a single MI355X (multi-GPU slab "

@@ -55,7 +55,7 @@ struct AdjArgs {
   T* lpot_loc;         // [N]
   T* lrho_loc;         // [N]
   T* lmom;             // [MomLayout::COUNT][N]
-  double* vpart;       // per-block partials of dL/dV_k [nblocks][kMaxE]
+  double* vpart;       // per-block partials of dL/dV_k [nblocks][kMaxE], accumulated over a segment's steps
   Phys<T> p;
   Volts<T> volts;
   T dt_on;
@@ -540,7 +540,7 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
       a.lqp[node] = T(0);
     }
   }
-  if (EHD) block_reduce<kMaxE, false>(vloc, a.vpart + (int64_t)blockIdx.x * kMaxE);
+  if (EHD) block_reduce<kMaxE, false>(vloc, a.vpart + (int64_t)blockIdx.x * kMaxE, 1, true);
 }
 
 template <class L, class T, bool EHD, bool HIGH>
@@ -740,7 +740,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_cd(Dims d, const uint8_t* __rest
       }
     }
   }
-  if (EHD) block_reduce<kMaxE, false>(vloc, vpart + (int64_t)blockIdx.x * kMaxE);
+  if (EHD) block_reduce<kMaxE, false>(vloc, vpart + (int64_t)blockIdx.x * kMaxE, 1, true);
 }
 
 // ----------------------------------------------------------------------------- terminal cotangent

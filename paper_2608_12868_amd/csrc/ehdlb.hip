@@ -54,6 +54,7 @@ int rblocks(int64_t n) { return std::min(nblocks(n), kRedBlocks); }
 struct MGLevel {
   Level L;
   size_t cp, diag, dinv, r, z, t;  // byte offsets
+  size_t acp, adiag, adinv;        // the adjoint solves' own coarse operators (levels >= 1)
 };
 
 }  // namespace
@@ -120,6 +121,10 @@ struct ehdlb_ctx {
   ehd::CgCtl* hctl_pin = nullptr;  // pinned staging of the control block (allocated at bind)
   hipEvent_t ev_ctl = nullptr;     // marks the control block's copy in the stream
   int64_t hier_t = -1;  // step whose operator the coarse hierarchy was built from (-1: none); saved
+  // the adjoint solves' hierarchy (own storage, swapped in for their solves): the step it was built
+  // from, and the step of the solve in progress
+  int64_t adj_hier_t = -1, adj_step = 0;
+  size_t off_inv_adj = 0;
   // layout (byte offsets into ws)
   size_t off_pop[2]{}, off_phi[2]{}, off_rho[2]{}, off_u[2]{}, off_q[2]{}, off_pot = 0, off_pot_old = 0;
   size_t off_pot_hist[kProjFwd]{};  // potentials of earlier steps for the projected warm start (ring by t)
@@ -363,8 +368,12 @@ static void plan_layout(ehdlb_ctx* c) {
       m.r = take(levels[l].N * ts);
       m.z = take(levels[l].N * ts);
       m.t = take(levels[l].N * ts);
+      m.acp = take((size_t)c->D * levels[l].N * ts);
+      m.adiag = take(levels[l].N * ts);
+      m.adinv = take(levels[l].N * ts);
       c->mg.push_back(m);
     }
+    c->off_inv_adj = take((size_t)levels.back().N * levels.back().N * 8);
     c->tail_first = c->mg.size() - 1;
     int64_t tail_cells = c->mg.back().L.N;
     while (c->tail_first > 0) {
@@ -384,6 +393,18 @@ static void plan_layout(ehdlb_ctx* c) {
   c->off_pcoef = take(std::max(kProjFwd, kProjAdj) * 8);
   c->state_bytes = 256 + align_up((size_t)c->F * c->Q * N * ts) + (c->state_end() - c->off_phi[0]);
   c->total = o;
+}
+
+// Exchange the coarse operators of levels >= 1 and the dense coarsest inverse with the adjoint
+// solves' own copies (called around each adjoint solve).
+static void swap_hierarchy(ehdlb_ctx* c) {
+  for (size_t l = 1; l < c->mg.size(); ++l) {
+    MGLevel& m = c->mg[l];
+    std::swap(m.cp, m.acp);
+    std::swap(m.diag, m.adiag);
+    std::swap(m.dinv, m.adinv);
+  }
+  std::swap(c->off_inv, c->off_inv_adj);
 }
 
 // ============================================================================ validation
@@ -604,9 +625,13 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
   // coarse hierarchy (Galerkin aggregation, with inverse diagonals) and the dense coarsest
   // inverse, only when iterating; the fine level's inverse diagonal comes from pois_setup.  The
   // forward solves rebuild it every kHierLag steps (it only preconditions the current fine
-  // operator); the adjoint's solves rebuild it every time, which invalidates the forward's.
+  // operator).  The adjoint's solves keep their own hierarchy (swapped in by the caller), rebuilt
+  // on the same lag counted in adjoint steps, so that it does not depend on the checkpoint
+  // interval (the recompute between them restores the forward's from the checkpoints).
   const bool fwd_solve = &hist == &c->cg_hist[0];
-  const bool rebuild = !fwd_solve || c->hier_t < 0 || c->t - c->hier_t >= kHierLag;
+  int64_t& hier_t = fwd_solve ? c->hier_t : c->adj_hier_t;
+  const int64_t t_now = fwd_solve ? c->t : c->adj_step;
+  const bool rebuild = hier_t < 0 || std::llabs(t_now - hier_t) >= kHierLag;
   if (!stopped && rebuild) {
     for (size_t l = 0; l < c->tail_first; ++l) {
       MGLevel& f = c->mg[l];
@@ -670,7 +695,7 @@ static ehdlb_status pcg(ehdlb_ctx* c, T* x, const T* b, ehdlb_ctx::CgHistory& hi
   }
   const CgCtl& h = c->hctl;
   // the build kernels ran iff the solve iterated (they return at once once it has stopped)
-  if (!stopped && rebuild) c->hier_t = fwd_solve && h.iterated ? c->t : -1;
+  if (!stopped && rebuild) hier_t = h.iterated ? t_now : -1;
   c->last_resid0 = h.rel0;
   c->last_iters = h.iterated && !h.zero ? h.iters : 0;
   c->last_resid = h.zero ? 0.0 : h.rel;
@@ -1240,9 +1265,11 @@ static ehdlb_status step_record(ehdlb_ctx* c, T* rec) {
   return EHDLB_OK;
 }
 
-// adjoint of step t: cotangents of step t+1 in slot nx, of step t written into slot cu
+// adjoint of step t: cotangents of step t+1 in slot nx, of step t written into slot cu.  Passes A
+// and CD add their dL/dV contributions to per-block partials, which are summed into segment seg's
+// entry (and cleared) when flush is set: at the last step of the sweep within the segment.
 template <class LT, class T, bool EHD>
-static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, int cu, int seg) {
+static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, int cu, int seg, bool flush) {
   using RL = RecLayout<LT>;
   auto& J = c->adj;
   hipStream_t s = c->stream;
@@ -1294,10 +1321,6 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
     else
       hipLaunchKernelGGL((k_adj_a<LT, T, EHD, false>), dim3(nb), dim3(kBlock), 0, s, a);
   }
-  if (EHD) {
-    hipLaunchKernelGGL((k_final_wide<kMaxE, false>), dim3(1), dim3(kFinalWide), 0, s, vpart, nb, vred);
-    hipLaunchKernelGGL(k_vacc_add, dim3(1), dim3(64), 0, s, vred, vacc, seg, J.nvseg);
-  }
   hipLaunchKernelGGL((k_adj_b<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, (const T*)A(J.lgr),
                      (const T*)A(J.llap), (const T*)A(J.lsig), (const T*)A(J.lpnb), (const T*)A(J.lphi_loc),
                      (const T*)A(J.lpot_loc), A(J.lphi), A(J.lpot));
@@ -1330,7 +1353,11 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
                                               A(J.lbr[(t + 1) % kProjAdj]), kBasis);
       }
     }
-    if ((st = pcg<LT, T>(c, A(lbx), (const T*)A(J.lpot), c->cg_hist[1]))) return st;
+    c->adj_step = t;
+    swap_hierarchy(c);
+    st = pcg<LT, T>(c, A(lbx), (const T*)A(J.lpot), c->cg_hist[1]);
+    swap_hierarchy(c);
+    if (st) return st;
   }
   if (high)
     hipLaunchKernelGGL((k_adj_cd<LT, T, EHD, true>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, v, rec,
@@ -1340,9 +1367,11 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
     hipLaunchKernelGGL((k_adj_cd<LT, T, EHD, false>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, v, rec,
                        (const T*)A(J.lphi), (const T*)A(J.lrho_loc), (const T*)A(lbx), (const T*)A(J.lmom),
                        (const T*)A(J.lP[nx]), A(J.lP[cu]), vpart);
-  if (EHD) {
+  if (EHD && flush) {
     hipLaunchKernelGGL((k_final_wide<kMaxE, false>), dim3(1), dim3(kFinalWide), 0, s, vpart, nb, vred);
     hipLaunchKernelGGL(k_vacc_add, dim3(1), dim3(64), 0, s, vred, vacc, seg, J.nvseg);
+    hipLaunchKernelGGL(k_zero<double>, dim3(nblocks((int64_t)nb * kMaxE)), dim3(kBlock), 0, s, (int64_t)nb * kMaxE,
+                       vpart);
   }
   LAUNCHCHK();
   return EHDLB_OK;
@@ -1372,6 +1401,7 @@ struct AdjFn {
     const int64_t N = c->N;
     const Dims dm{c->lat.n[0], c->lat.n[1], c->lat.n[2], N};
     ehdlb_status st;
+    c->adj_hier_t = -1;  // the adjoint solves' hierarchy is built afresh in every sweep
     // terminal cotangent from the FP64 observables of the final state
     ehdlb_obs ob;
     if ((st = observables_impl<LT, T, EHD>(c, &ob))) return st;
@@ -1389,6 +1419,8 @@ struct AdjFn {
                        gx[0], gx[1], gx[2], gv[0], gv[1], gv[2], A(J.lP[cu]), A(J.lphip[cu]), A(J.lup[cu]),
                        A(J.lrhop[cu]), A(J.lqp[cu]));
     HIPCHK(hipMemsetAsync(J.ws + J.vacc, 0, (size_t)kMaxE * J.nvseg * 8, s));
+    hipLaunchKernelGGL(k_zero<double>, dim3(nblocks((int64_t)nblocks(N) * kMaxE)), dim3(kBlock), 0, s,
+                       (int64_t)nblocks(N) * kMaxE, reinterpret_cast<double*>(J.ws + J.vpart));
     hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(N)), dim3(kBlock), 0, s, N, A(J.lb));
     LAUNCHCHK();
     const auto& sch = c->sched[electrode];
@@ -1400,16 +1432,17 @@ struct AdjFn {
       for (int64_t t = ta; t < tb; ++t)
         if ((st = step_record<LT, T, EHD>(c, reinterpret_cast<T*>(J.ws + J.rec + (size_t)(t - ta) * J.rec_stride))))
           return st;
+      auto seg_of = [&](int64_t tt) {
+        if (sch.v.empty()) return 0;
+        return (int)std::min<int64_t>((tt * (int64_t)nseg) / sch.t_total, nseg - 1);
+      };
       for (int64_t t = tb - 1; t >= ta; --t) {
-        int seg = 0;
-        if (!sch.v.empty()) {
-          const int64_t sg = (t * (int64_t)nseg) / sch.t_total;
-          seg = (int)std::min<int64_t>(sg, nseg - 1);
-        }
+        const int seg = seg_of(t);
+        const bool flush = t == J.t0 || seg_of(t - 1) != seg;
         const int nx = cu;
         cu = 1 - cu;
         if ((st = adjoint_step<LT, T, EHD>(c, t, reinterpret_cast<T*>(J.ws + J.rec + (size_t)(t - ta) * J.rec_stride),
-                                            nx, cu, seg)))
+                                            nx, cu, seg, flush)))
           return st;
       }
     }

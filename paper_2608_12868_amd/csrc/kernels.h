@@ -254,8 +254,10 @@ __global__ __launch_bounds__(kBlock) void k_init(Dims d, const uint8_t* __restri
 }
 
 // ----------------------------------------------------------------------------- block reductions
+// out[k * ostride] = the block's sum (or max) of v[k]; accumulate: added to what out holds
 template <int K, bool MAX>
-__device__ __forceinline__ void block_reduce(double (&v)[K], double* __restrict__ out, int64_t ostride = 1) {
+__device__ __forceinline__ void block_reduce(double (&v)[K], double* __restrict__ out, int64_t ostride = 1,
+                                             bool accumulate = false) {
   __shared__ double sm[kBlock / 64][K];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -273,7 +275,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[K], double* __restrict_
   if (threadIdx.x < K) {
     double x = sm[0][threadIdx.x];
     for (int w = 1; w < kBlock / 64; ++w) x = MAX ? fmax(x, sm[w][threadIdx.x]) : x + sm[w][threadIdx.x];
-    out[threadIdx.x * ostride] = x;
+    out[threadIdx.x * ostride] = accumulate ? out[threadIdx.x * ostride] + x : x;
   }
 }
 
