@@ -112,7 +112,7 @@ def adjoint_leg(key, seed=1):
     """Cost of dL/dV for L = (x_c(T) - x*)^2 (x* = initial centroid + 5 lu), FP32 path: plain
     forward, checkpointed forward and reverse sweep (recompute included), timed with device
     syncs, with the forward warm start that the default uses for the gradient's forward
-    (projected onto the last four potentials, then at least one CG iteration: `warm_projected`,
+    (projected onto the last five potentials, then at least one CG iteration: `warm_projected`,
     which also times the default's plain forward, where a projected start that meets the
     tolerance is kept) and, for the 2D leg, the other three (the projection alone; previous
     potential; extrapolated from the last two); each gradient's error against the FP64 adjoint
@@ -292,7 +292,7 @@ def cpu_baseline(budget_s=12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--spin-up", type=int, default=200,

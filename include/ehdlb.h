@@ -269,7 +269,7 @@ ehdlb_status ehdlb_adjoint(ehdlb_ctx* ctx, const double dL_dcentroid[3], const d
  * the coarse-grid correction.  warm_start (forward solves): 0 = each step's
  * solve starts from the previous step's potential; 1 = from the linear
  * extrapolation 2 phi(t-1) - phi(t-2); 2 = from the Galerkin projection of the
- * step's system onto the potentials of the last four steps (formed in the
+ * step's system onto the potentials of the last five steps (formed in the
  * basis phi(t-1) and its backward differences), the A-norm-optimal start in
  * their span, followed by at least one CG iteration; 3 = the same projection
  * without the minimum (fewest iterations; a solve that keeps the projected

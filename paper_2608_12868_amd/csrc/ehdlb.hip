@@ -35,9 +35,9 @@ constexpr int kZeroBlocks = 256;  // grid of k_cg_zero (grid-stride; returns at 
 // level, fit the tail's LDS run inside the single-workgroup V-cycle tail
 constexpr int64_t kTailMaxCells = 2048;
 constexpr int kSolverParts = 7;
-// earlier solutions spanning the projected warm starts: forward (potentials of steps t-1..t-4)
+// earlier solutions spanning the projected warm starts: forward (potentials of steps t-1..t-5)
 // and adjoint (adjoint potentials of steps t+1..t+6, which alternate in sign)
-constexpr int kProjFwd = 4, kProjAdj = 6;
+constexpr int kProjFwd = 5, kProjAdj = 6;
 // steps between rebuilds of the forward solves' coarse hierarchy (a preconditioner: the coarse
 // operators of a few steps back still precondition the current fine operator well)
 constexpr int64_t kHierLag = 8;
@@ -756,7 +756,7 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
   ehdlb_status st = pois_setup<LT, T>(c, phi, rho, volts);
   if (st) return st;
   // warm start (the potential of the previous step is the plain one): extrapolated linearly from
-  // the potentials of the two previous steps, or projected onto the potentials of the last four
+  // the potentials of the two previous steps, or projected onto the potentials of the last five
   // steps (the default; kept in the saved state, so a replay from a checkpoint takes the same
   // iterates)
   T* pot = c->ptr<T>(c->off_pot);
@@ -769,7 +769,7 @@ static ehdlb_status potential_solve(ehdlb_ctx* c, const T* phi, const T* rho, co
     const int m = (int)std::min<int64_t>(t, kProjFwd);
     const T* older[kProjFwd - 1];
     for (int j = 1; j < kProjFwd; ++j) older[j - 1] = j < m ? c->ptr<T>(c->off_pot_hist[(t - 1 - j) % kProjFwd]) : pot;
-    // basis: phi(t-1) and its backward differences up to the third, u_r = sum_k (-1)^k C(r, k) h_k
+    // basis: phi(t-1) and its backward differences up to the fourth, u_r = sum_k (-1)^k C(r, k) h_k
     double basis[kProjFwd][kProjFwd];
     for (int r = 0; r < kProjFwd; ++r)
       for (int k = 0; k < kProjFwd; ++k) {

@@ -195,7 +195,7 @@ class Simulation(Context):
     def set_solver_options(self, lo=0.5, hi=2.0, overcorrect=2.0, warm_start=4):
         """Chebyshev smoothing interval [lo, hi] of D^-1 A, coarse-correction scale, and the
         forward warm start (0: previous step's potential; 1: extrapolated from the last two;
-        2: Galerkin projection onto the last four, then at least one CG iteration; 3: the
+        2: Galerkin projection onto the last five, then at least one CG iteration; 3: the
         projection alone; 4, the default: 3 in step(), 2 in forward_checkpointed() and the
         adjoint's recompute)."""
         self._chk(L.lib().ehdlb_set_solver_options(self.h, float(lo), float(hi), float(overcorrect),
