@@ -121,9 +121,10 @@ def test_config3_fields_vs_oracle(precision, tol, names):
     assert worst <= tol
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
-def test_config3_centroid_vs_oracle(precision, tol):
-    """The droplet centroid at 256x128x96 every 10 steps over the stored oracle trajectory."""
+@pytest.mark.parametrize("precision,tol,disp_tol", [("fp64", 1e-10, 1e-7), ("fp32", 1e-4, 1e-3)])
+def test_config3_centroid_vs_oracle(precision, tol, disp_tol):
+    """The droplet centroid at 256x128x96 every 10 steps over the stored oracle trajectory,
+    relative to the position and to the droplet's displacement (3e-4 lu over 100 steps)."""
     with open(GOLD3) as f:
         g = json.load(f)
     traj = g.get("trajectory")
@@ -146,6 +147,7 @@ def test_config3_centroid_vs_oracle(precision, tol):
     print(f"  max relative centroid error {worst:.3e}; absolute {worst_abs:.3e} lu "
           f"(displacement {disp:.4f} lu)", flush=True)
     assert worst <= tol
+    assert worst_abs <= disp_tol * disp
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
