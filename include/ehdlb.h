@@ -252,8 +252,11 @@ int64_t ehdlb_wetting_links(const ehdlb_ctx* ctx, int64_t* nodes, int32_t* dirs,
  *   state again.  ESTATE if anything that changes the state or the steps was
  *   called since the checkpointed forward (ehdlb_generation differs: set_geometry,
  *   set_phase, set_charge, set_schedule, set_solver_options, step with n > 0,
- *   load_state, another forward_checkpointed), EINVAL if the field is off or the
- *   phase densities differ. */
+ *   load_state, another forward_checkpointed), EINVAL if the field is off.  With
+ *   unequal phase densities the record holds the raw second moments of the flow
+ *   populations, from which the reverse of the velocity-based form (the
+ *   acceleration F/rho with the pressure and viscous density-gradient forces of
+ *   the provisional collision) is rebuilt. */
 size_t ehdlb_adjoint_workspace_bytes(const ehdlb_ctx* ctx, int64_t T, int32_t K);
 ehdlb_status ehdlb_forward_checkpointed(ehdlb_ctx* ctx, int64_t T, int32_t K, void* device_workspace,
                                         size_t bytes);

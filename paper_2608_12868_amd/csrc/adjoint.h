@@ -64,8 +64,14 @@ struct AdjArgs {
 // ----------------------------------------------------------------------------- pass A
 // HIGH: the higher moments relax at p.s_high (see k_step): every equilibrium and source term
 // of the collision is scaled accordingly, and the population cotangents of step t receive
-// (1 - s_high) times the streamed cotangents directly (pass CD)
-template <class L, class T, bool EHD, bool HIGH>
+// (1 - s_high) times the streamed cotangents directly (pass CD).
+// VRHO: unequal phase densities (see k_step): the force becomes the acceleration
+// F' = (F + cp grad rho + cmu P grad rho) / rho with the provisional collision's second moments
+// P = S - (drho/3 delta + u1 u1) + (u1 a1 + a1 u1)/2 (S the raw second moments of g, which the
+// record holds in this case; a1 = F / rho, u1 = j + a1/2), cp = -cs2 drho, cmu = -3 nu s_nu;
+// its reverse maps the cotangent of F' to that of F and adds the cotangents of S, drho, j, the
+// phase fields at the node and their gradients.
+template <class L, class T, bool EHD, bool HIGH, bool VRHO>
 __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
   using ML = MomLayout<L>;
   using RL = RecLayout<L>;
@@ -180,15 +186,70 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
       j[c] = R(RL::MOM + ML::J + c, node);
       up[c] = R(RL::UP + c, node);
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) u[c] = j[c] + T(0.5) * F[c];
-    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
     const T nu = p.nu[0] * pc[0] + p.nu[1] * pc[1] + p.nu[2] * pc[2];
     const T s_nu = T(1) / (T(0.5) + T(3) * nu);
     T Pi[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) Pi[k] = R(RL::MOM + ML::PI + k, node);
+    // unequal densities: symmetric tensors as (xx yy zz xy xz yz); vs = the raw second moments
+    // (record), vp = the provisional collision's, vG = F + cp grad rho + cmu vp grad rho
+    T Fpre[3] = {F[0], F[1], F[2]}, vs[6] = {0, 0, 0, 0, 0, 0}, vp[6] = {0, 0, 0, 0, 0, 0};
+    T vG[3] = {0, 0, 0}, grho[3] = {0, 0, 0}, a1[3] = {0, 0, 0}, u1[3] = {0, 0, 0};
+    T irho = T(1), cp_ = T(0), cmu = T(0);
+    if (VRHO) {
+      if (D == 2) {
+        vs[0] = Pi[0];
+        vs[1] = Pi[1];
+        vs[3] = Pi[2];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) vs[k] = Pi[k < P ? k : 0];
+      }
+      irho = T(1) / (p.rho[0] * pc[0] + p.rho[1] * pc[1] + p.rho[2] * pc[2]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        grho[c] = p.rho[0] * gr[0][c] + p.rho[1] * gr[1][c] + p.rho[2] * gr[2][c];
+        a1[c] = Fpre[c] * irho;
+        u1[c] = j[c] + T(0.5) * a1[c];
+      }
+      const T d3 = drho / T(3);
+      vp[0] = vs[0] - d3 - u1[0] * u1[0] + u1[0] * a1[0];
+      vp[1] = vs[1] - d3 - u1[1] * u1[1] + u1[1] * a1[1];
+      vp[3] = vs[3] - u1[0] * u1[1] + T(0.5) * (u1[0] * a1[1] + u1[1] * a1[0]);
+      if (D == 3) {
+        vp[2] = vs[2] - d3 - u1[2] * u1[2] + u1[2] * a1[2];
+        vp[4] = vs[4] - u1[0] * u1[2] + T(0.5) * (u1[0] * a1[2] + u1[2] * a1[0]);
+        vp[5] = vs[5] - u1[1] * u1[2] + T(0.5) * (u1[1] * a1[2] + u1[2] * a1[1]);
+      }
+      cmu = -T(3) * nu * s_nu;
+      cp_ = -cs2 * drho;
+      vG[0] = Fpre[0] + cp_ * grho[0] + cmu * (vp[0] * grho[0] + vp[3] * grho[1] + vp[4] * grho[2]);
+      vG[1] = Fpre[1] + cp_ * grho[1] + cmu * (vp[3] * grho[0] + vp[1] * grho[1] + vp[5] * grho[2]);
+      vG[2] = Fpre[2] + cp_ * grho[2] + cmu * (vp[4] * grho[0] + vp[5] * grho[1] + vp[2] * grho[2]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[c] = vG[c] * irho;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = j[c] + T(0.5) * F[c];
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    if (VRHO) {
+      // the non-equilibrium second moments of the collision, with the final u and F
+      const T d3 = drho / T(3);
+      const T pn[6] = {vs[0] - d3 - u[0] * u[0] + u[0] * F[0], vs[1] - d3 - u[1] * u[1] + u[1] * F[1],
+                       vs[2] - d3 - u[2] * u[2] + u[2] * F[2],
+                       vs[3] - u[0] * u[1] + T(0.5) * (u[0] * F[1] + u[1] * F[0]),
+                       vs[4] - u[0] * u[2] + T(0.5) * (u[0] * F[2] + u[2] * F[0]),
+                       vs[5] - u[1] * u[2] + T(0.5) * (u[1] * F[2] + u[2] * F[1])};
+      if (D == 2) {
+        Pi[0] = pn[0];
+        Pi[1] = pn[1];
+        Pi[P - 1] = pn[3];
+      } else {
+#pragma unroll
+        for (int k = 0; k < P; ++k) Pi[k] = pn[k];
+      }
+    }
 
     // ---------------------------------------------------------- cotangents of the outputs
     // streamed populations: the value pushed from node along q landed on node + e_q (or on
@@ -432,6 +493,69 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
       // u = j + F/2  (lu now complete)
 #pragma unroll
       for (int c = 0; c < 3; ++c) lF[c] += T(0.5) * lu[c];
+      if (VRHO) {
+        // reverse of F' = vG / rho (lF: cotangent of F'; afterwards that of the force F)
+        T lG[3], lvp[6], la1[3], lu1[3];
+        T lirho = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          lG[c] = irho * lF[c];
+          lirho += lF[c] * vG[c];
+        }
+        const T lcp = lG[0] * grho[0] + lG[1] * grho[1] + lG[2] * grho[2];
+        const T pg[3] = {vp[0] * grho[0] + vp[3] * grho[1] + vp[4] * grho[2],
+                         vp[3] * grho[0] + vp[1] * grho[1] + vp[5] * grho[2],
+                         vp[4] * grho[0] + vp[5] * grho[1] + vp[2] * grho[2]};
+        const T lcmu = lG[0] * pg[0] + lG[1] * pg[1] + lG[2] * pg[2];
+        const T gl[3] = {vp[0] * lG[0] + vp[3] * lG[1] + vp[4] * lG[2],
+                         vp[3] * lG[0] + vp[1] * lG[1] + vp[5] * lG[2],
+                         vp[4] * lG[0] + vp[5] * lG[1] + vp[2] * lG[2]};
+        T lgrho[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lgrho[c] = cp_ * lG[c] + cmu * gl[c];
+        lvp[0] = cmu * lG[0] * grho[0];
+        lvp[1] = cmu * lG[1] * grho[1];
+        lvp[2] = cmu * lG[2] * grho[2];
+        lvp[3] = cmu * (lG[0] * grho[1] + lG[1] * grho[0]);
+        lvp[4] = cmu * (lG[0] * grho[2] + lG[2] * grho[0]);
+        lvp[5] = cmu * (lG[1] * grho[2] + lG[2] * grho[1]);
+        // vp = vs - (drho/3 delta + u1 u1) + (u1 a1 + a1 u1)/2
+        ldrho += -cs2 * lcp - (lvp[0] + lvp[1] + lvp[2]) / T(3);
+        lu1[0] = lvp[0] * (-T(2) * u1[0] + a1[0]) + lvp[3] * (-u1[1] + T(0.5) * a1[1]) +
+                 lvp[4] * (-u1[2] + T(0.5) * a1[2]);
+        lu1[1] = lvp[1] * (-T(2) * u1[1] + a1[1]) + lvp[3] * (-u1[0] + T(0.5) * a1[0]) +
+                 lvp[5] * (-u1[2] + T(0.5) * a1[2]);
+        lu1[2] = lvp[2] * (-T(2) * u1[2] + a1[2]) + lvp[4] * (-u1[0] + T(0.5) * a1[0]) +
+                 lvp[5] * (-u1[1] + T(0.5) * a1[1]);
+        la1[0] = lvp[0] * u1[0] + T(0.5) * (lvp[3] * u1[1] + lvp[4] * u1[2]);
+        la1[1] = lvp[1] * u1[1] + T(0.5) * (lvp[3] * u1[0] + lvp[5] * u1[2]);
+        la1[2] = lvp[2] * u1[2] + T(0.5) * (lvp[4] * u1[0] + lvp[5] * u1[1]);
+        // u1 = j + a1/2, a1 = F / rho
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          lu[c] += lu1[c];  // the cotangent of j below
+          la1[c] += T(0.5) * lu1[c];
+          lirho += Fpre[c] * la1[c];
+          lF[c] = lG[c] + irho * la1[c];
+        }
+        // the raw second moments: their cotangent maps to the populations as that of Pi does
+        if (D == 2) {
+          lm[(int64_t)(ML::PI + 0) * N + node] += lvp[0];
+          lm[(int64_t)(ML::PI + 1) * N + node] += lvp[1];
+          lm[(int64_t)(ML::PI + 2) * N + node] += lvp[3];
+        } else {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) lm[(int64_t)(ML::PI + k) * N + node] += lvp[k];
+        }
+        // 1/rho and nu of the phase fields at the node, grad rho of their gradients
+        const T lnu_v = lcmu * (-T(1.5) * s_nu * s_nu);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          lphi[i] += -p.rho[i] * irho * irho * lirho + p.nu[i] * lnu_v;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) lgr[i][c] += p.rho[i] * lgrho[c];
+        }
+      }
       lm[(int64_t)ML::DRHO * N + node] = ldrho;
 #pragma unroll
       for (int c = 0; c < D; ++c) lm[(int64_t)(ML::J + c) * N + node] = lu[c];
@@ -543,16 +667,16 @@ __device__ __forceinline__ void adj_a_body(const AdjArgs<T>& a) {
   if (EHD) block_reduce<kMaxE, false>(vloc, a.vpart + (int64_t)blockIdx.x * kMaxE, 1, true);
 }
 
-template <class L, class T, bool EHD, bool HIGH>
+template <class L, class T, bool EHD, bool HIGH, bool VRHO>
 __global__ __launch_bounds__(kBlock) void k_adj_a(AdjArgs<T> a) {
-  adj_a_body<L, T, EHD, HIGH>(a);
+  adj_a_body<L, T, EHD, HIGH, VRHO>(a);
 }
 // FP32: capped at 256 registers so that two waves fit per SIMD (one 8-byte spill in 3D);
 // uncapped, the kernel needs just over 256 and runs one wave per SIMD.  The FP64 variants
 // would spill heavily under the same cap.
-template <class L, bool EHD, bool HIGH>
+template <class L, bool EHD, bool HIGH, bool VRHO>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_a32(AdjArgs<float> a) {
-  adj_a_body<L, float, EHD, HIGH>(a);
+  adj_a_body<L, float, EHD, HIGH, VRHO>(a);
 }
 
 // ----------------------------------------------------------------------------- pass B

@@ -831,18 +831,16 @@ static bool var_rho(const ehdlb_ctx* c) {
 }
 
 // the variants with the higher moments away from rate 1, or with unequal densities, only when
-// they are (the adjoint's recompute, STORE, never runs with unequal densities)
+// they are
 template <class LT, class T, bool EHD, bool STORE>
 static void launch_step(const ehdlb_ctx* c, const StepArgs<T>& a) {
   const bool high = c->prm.s_high != 1.0;
-  if constexpr (!STORE) {
-    if (var_rho(c)) {
-      if (high)
-        launch_step_h<LT, T, EHD, STORE, true, true>(c, a);
-      else
-        launch_step_h<LT, T, EHD, STORE, false, true>(c, a);
-      return;
-    }
+  if (var_rho(c)) {
+    if (high)
+      launch_step_h<LT, T, EHD, STORE, true, true>(c, a);
+    else
+      launch_step_h<LT, T, EHD, STORE, false, true>(c, a);
+    return;
   }
   if (high)
     launch_step_h<LT, T, EHD, STORE, true, false>(c, a);
@@ -1310,16 +1308,29 @@ static ehdlb_status adjoint_step(ehdlb_ctx* c, int64_t t, const T* rec, int nx, 
   double* vred = reinterpret_cast<double*>(J.ws + J.vred);
   double* vacc = reinterpret_cast<double*>(J.ws + J.vacc);
   const bool high = c->prm.s_high != 1.0;
+  const bool vr = var_rho(c);
   if constexpr (std::is_same<T, float>::value) {
-    if (high)
-      hipLaunchKernelGGL((k_adj_a32<LT, EHD, true>), dim3(nb), dim3(kBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_adj_a32<LT, EHD, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    if (vr) {
+      if (high)
+        hipLaunchKernelGGL((k_adj_a32<LT, EHD, true, true>), dim3(nb), dim3(kBlock), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_adj_a32<LT, EHD, false, true>), dim3(nb), dim3(kBlock), 0, s, a);
+    } else if (high) {
+      hipLaunchKernelGGL((k_adj_a32<LT, EHD, true, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    } else {
+      hipLaunchKernelGGL((k_adj_a32<LT, EHD, false, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    }
   } else {
-    if (high)
-      hipLaunchKernelGGL((k_adj_a<LT, T, EHD, true>), dim3(nb), dim3(kBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_adj_a<LT, T, EHD, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    if (vr) {
+      if (high)
+        hipLaunchKernelGGL((k_adj_a<LT, T, EHD, true, true>), dim3(nb), dim3(kBlock), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_adj_a<LT, T, EHD, false, true>), dim3(nb), dim3(kBlock), 0, s, a);
+    } else if (high) {
+      hipLaunchKernelGGL((k_adj_a<LT, T, EHD, true, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    } else {
+      hipLaunchKernelGGL((k_adj_a<LT, T, EHD, false, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    }
   }
   hipLaunchKernelGGL((k_adj_b<LT, T, EHD>), dim3(nb), dim3(kBlock), 0, s, dm, flags, ph, (const T*)A(J.lgr),
                      (const T*)A(J.llap), (const T*)A(J.lsig), (const T*)A(J.lpnb), (const T*)A(J.lphi_loc),
@@ -1913,7 +1924,6 @@ ehdlb_status ehdlb_adjoint(ehdlb_ctx* c, const double* dL_dcentroid, const doubl
   if (!dL_dcentroid || !dL_dvelocity || !dL_dvolts) return fail(c, EHDLB_EINVAL, "null argument");
   if (electrode < 0 || electrode >= EHDLB_MAX_ELECTRODES) return fail(c, EHDLB_EINVAL, "electrode index out of range");
   if (!c->ehd) return fail(c, EHDLB_EINVAL, "adjoint with respect to voltages needs the field on");
-  if (var_rho(c)) return fail(c, EHDLB_EINVAL, "the adjoint of the variable-density flow is not built");
   if (!c->adj.ready) return fail(c, EHDLB_ESTATE, "adjoint before forward_checkpointed");
   if (c->sched[electrode].v.size() > (size_t)c->adj.nvseg) return fail(c, EHDLB_EINVAL, "too many schedule segments");
   if (c->gen != c->adj.gen || c->t != c->adj.t0 + c->adj.T)

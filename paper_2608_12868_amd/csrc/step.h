@@ -215,15 +215,28 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
       r[(int64_t)ML::DRHO * N + node] = drho;
 #pragma unroll
       for (int c = 0; c < D; ++c) r[(int64_t)(ML::J + c) * N + node] = j[c];
-      r[(int64_t)(ML::PI + 0) * N + node] = Pxx;
-      r[(int64_t)(ML::PI + 1) * N + node] = Pyy;
+      // the second moments of g - g_eq + F_q/2; with unequal densities the raw second moments of g
+      // instead (the adjoint rebuilds the provisional collision's from them): add back the
+      // equilibrium's drho/3 delta + u u and take off half the forcing's u F + F u
+      T sxx = Pxx, syy = Pyy, szz = Pzz, sxy = Pxy, sxz = Pxz, syz = Pyz;
+      if (VRHO) {
+        const T d3 = drho / T(3);
+        sxx += d3 + u[0] * u[0] - u[0] * F[0];
+        syy += d3 + u[1] * u[1] - u[1] * F[1];
+        szz += d3 + u[2] * u[2] - u[2] * F[2];
+        sxy += u[0] * u[1] - T(0.5) * (u[0] * F[1] + u[1] * F[0]);
+        sxz += u[0] * u[2] - T(0.5) * (u[0] * F[2] + u[2] * F[0]);
+        syz += u[1] * u[2] - T(0.5) * (u[1] * F[2] + u[2] * F[1]);
+      }
+      r[(int64_t)(ML::PI + 0) * N + node] = sxx;
+      r[(int64_t)(ML::PI + 1) * N + node] = syy;
       if (D == 2) {
-        r[(int64_t)(ML::PI + 2) * N + node] = Pxy;
+        r[(int64_t)(ML::PI + 2) * N + node] = sxy;
       } else {
-        r[(int64_t)(ML::PI + 2) * N + node] = Pzz;
-        r[(int64_t)(ML::PI + 3) * N + node] = Pxy;
-        r[(int64_t)(ML::PI + 4) * N + node] = Pxz;
-        r[(int64_t)(ML::PI + 5) * N + node] = Pyz;
+        r[(int64_t)(ML::PI + 2) * N + node] = szz;
+        r[(int64_t)(ML::PI + 3) * N + node] = sxy;
+        r[(int64_t)(ML::PI + 4) * N + node] = sxz;
+        r[(int64_t)(ML::PI + 5) * N + node] = syz;
       }
     }
 #pragma unroll
