@@ -248,3 +248,30 @@ def test_adjoint_variable_density_matches_oracle_autograd(name, rho, T, K):
     print("adjoint (unequal densities) vs oracle autograd", err, g, g_ref, flush=True)
     assert np.allclose(ob["centroid"], xc.numpy(), rtol=1e-12, atol=1e-12)
     assert err <= 1e-8
+
+
+def test_adjoint_paper_regime_fluids_matches_oracle_autograd():
+    """The paper's Table 1 fluids (densities 998 : 970 : 1.2, dynamic viscosities 1 : 0.5 :
+    0.0179, so a density ratio of 830 between droplet and ambient): the variable-density
+    adjoint against the oracle's autograd on the 96x48 schedule case."""
+    from oracle import Oracle
+    from oracle.adjoint import schedule_gradient
+    case = make_case("c4s", precision="fp64")
+    rho = (1.0, 970.0 / 998.0, 1.2 / 998.0)
+    nu = (0.01, 0.01 * 0.5 / rho[1], 0.01 * 0.0179 / rho[2])
+    over = dict(rho=rho, tau_flow=tuple(0.5 + 3.0 * v for v in nu))
+    sched = case.schedule.copy()
+    T = t_total = 24
+    print("case c4s, Table 1 fluids", rho, "T", T, flush=True)
+    sim = _sim(case, **over)
+    sim.set_schedule(0, sched, t_total)
+    sim.forward_checkpointed(T, 7)
+    g = sim.adjoint(GX, GV, 0, len(sched))
+    p = dict(case.params)
+    p.update(over)
+    o = Oracle(case.dim, case.n, case.periodic, p, case.flags)
+    g_ref, _, _ = schedule_gradient(o, case.phi, sched, T, t_total, GX, GV)
+    g_ref = g_ref.numpy()
+    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    print("adjoint (Table 1 fluids) vs oracle autograd", err, flush=True)
+    assert err <= 1e-8
