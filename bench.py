@@ -7,7 +7,7 @@ second, all nodes counted; fluid-only MLUPS beside it) of whole steps (moments
 and wetting ghosts, potential solve to tolerance, fused collide-stream of all
 population families), with inputs resident in HBM; the roofline of the dominant
 kernel (the fused collide-stream) from its algorithmic bytes and its HIP-event
-time; a plain device-copy ceiling; the FP64 CPU oracle timed on a bounded
+time; bandwidth references (device copies and the bare population pattern); the FP64 CPU oracle timed on a bounded
 sample of the same physics; and the adjoint leg: the cost of the gradient of
 the droplet centroid with respect to a piecewise-constant electrode schedule
 relative to the forward run, with its error stated against the FP64 adjoint
@@ -71,21 +71,59 @@ def measured_traffic(workload):
     return d.get("hbm_bytes_per_launch")
 
 
-def copy_ceiling(nbytes=1 << 30, reps=10):
-    """Practical HBM ceiling: a plain device-to-device copy of nbytes (read + write counted),
-    timed with HIP events on torch's stream."""
+def _timed(fn, reps):
+    """Mean milliseconds of fn() over reps launches (HIP events on torch's current stream, which
+    is also the stream fn queues on), after one untimed launch."""
     import torch
-    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
+    fn()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        dst.copy_(src)
+        fn()
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    return dict(bytes_per_copy=2 * nbytes, gbs=2 * nbytes / (ms * 1e-3) / 1e9)
+    return e0.elapsed_time(e1) / reps
+
+
+def copy_ceiling(dims, q, nfam, nbytes=1 << 30, reps=10):
+    """Practical HBM ceilings, read + write counted: a 1 GiB device-to-device copy through torch
+    (hipMemcpy; the calibration kernel of the rocprofv3 FETCH_SIZE/WRITE_SIZE counters), the
+    library's copy kernels at 16 and 4 bytes per lane, and the fused step's population access
+    pattern without its arithmetic on the workload's lattice (nfam families of q populations per
+    node, stored by population, each pushed to the node its velocity points to), with plain and
+    with non-temporal loads."""
+    import ctypes as C
+    import torch
+    from paper_2608_12868_amd import _lib
+    L = _lib.lib()
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    out = {"bytes_per_copy": 2 * nbytes}
+    out["memcpy_gbs"] = 2 * nbytes / (_timed(lambda: dst.copy_(src), reps) * 1e-3) / 1e9
+
+    def probe(kind, a, b, nb, d=None):
+        dd = (C.c_int32 * 3)(*d) if d else None
+        st = L.ehdlb_bandwidth_probe(kind, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), nb, dd, q, nfam,
+                                     stream)
+        if st != 0:
+            raise RuntimeError(f"ehdlb_bandwidth_probe({kind}) returned {st}")
+
+    for kind, key in ((0, "copy_16B_per_lane_gbs"), (1, "copy_4B_per_lane_gbs")):
+        out[key] = 2 * nbytes / (_timed(lambda: probe(kind, src, dst, nbytes), reps) * 1e-3) / 1e9
+    del src, dst
+    n_nodes = dims[0] * dims[1] * dims[2]
+    pb = nfam * q * n_nodes * 4
+    a = torch.ones(pb // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    pat = {"lattice": list(dims), "q": q, "families": nfam, "bytes_per_launch": 2 * pb}
+    for kind, key in ((2, "plain_loads"), (3, "nontemporal_loads")):
+        ms = _timed(lambda: probe(kind, a, b, pb, dims), reps)
+        pat[key] = {"us_per_launch": ms * 1e3, "gbs": 2 * pb / (ms * 1e-3) / 1e9}
+    out["population_pattern"] = pat
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 # adjoint legs: workload, steps before the window, T, K, central-difference directions, FP64 adjoint,
@@ -299,8 +337,9 @@ def main():
                     help="steps run before the warm-up (not timed): the state the timed steps start from")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true",
-                    help="skip the plain 1 GiB device copy (practical bandwidth ceiling; the "
-                         "calibration kernel of the rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
+                    help="skip the bandwidth references (1 GiB device copies, one of them the "
+                         "calibration kernel of the rocprofv3 FETCH_SIZE/WRITE_SIZE counters, and the "
+                         "fused step's bare population pattern)")
     ap.add_argument("--adjoint", default="c4,c5,c5late",
                     help="comma-separated adjoint legs: c4 (2D 512x256, T = 4000, every forward warm "
                          "start), c5 (3D 384x192x128, steps 0-200), c5late (3D, steps 600-800), c5full "
@@ -374,8 +413,16 @@ def main():
         "potential_residual_last_step": obs["poisson_residual"],
     }
     if not args.no_copy_probe:
-        out["copy_ceiling"] = copy_ceiling()
-        out["copy_ceiling"]["fused_step_frac_of_copy"] = achieved / out["copy_ceiling"]["gbs"]
+        from paper_2608_12868_amd import _lib
+        dims = list(case.n)
+        q = 9 if case.dim == 2 else 19
+        nfam = int(_lib.lib().ehdlb_num_populations(sim.h)) // (q * N)
+        cc = copy_ceiling(dims, q, nfam)
+        pat = max(cc["population_pattern"][k]["gbs"] for k in ("plain_loads", "nontemporal_loads"))
+        cc["fused_step_frac_of"] = {"memcpy": achieved / cc["memcpy_gbs"],
+                                    "copy_16B_per_lane": achieved / cc["copy_16B_per_lane_gbs"],
+                                    "population_pattern": achieved / pat}
+        out["copy_ceiling"] = cc
     del sim
     torch.cuda.empty_cache()
     if args.adjoint != "none":

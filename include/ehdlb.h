@@ -343,6 +343,24 @@ ehdlb_status ehdlb_preset(int32_t preset_id, ehdlb_lattice* lattice, ehdlb_param
  * example an autograd node) records it and checks it before ehdlb_adjoint. */
 uint64_t ehdlb_generation(const ehdlb_ctx* ctx);
 
+/* Bandwidth references (measurement only; no context, no method arithmetic): kernels
+ * that are timed beside the fused collide-stream step to give its memory traffic two
+ * ceilings.  All queue one launch on hip_stream (NULL: the null stream) and return.
+ *   kind 0: copy `bytes` from src to dst, 16 bytes per lane (one float4 per thread);
+ *           bytes and both addresses multiples of 16.
+ *   kind 1: the same copy with 4 bytes per lane (one float per thread).
+ *   kind 2: the population access pattern of the fused step without its arithmetic:
+ *           nf (1..5) families of q single-precision populations per node of a periodic
+ *           dims[0] x dims[1] x dims[2] lattice, stored by population ([nf][q][nodes],
+ *           x fastest); each population is loaded once and stored at the node its
+ *           lattice velocity points to (q = 9: D2Q9 with dims[2] = 1; q = 19: D3Q19).
+ *           src and dst hold at least nf q nodes floats (`bytes` each) and do not overlap.
+ *   kind 3: kind 2 with the population loads marked non-temporal.
+ * EINVAL for an unknown kind, NULL buffers, sizes or alignments outside the above; EHIP
+ * if the launch fails.  dst's contents are unspecified afterwards. */
+ehdlb_status ehdlb_bandwidth_probe(int32_t kind, const void* src, void* dst, size_t bytes, const int32_t* dims,
+                                   int32_t q, int32_t nf, void* hip_stream);
+
 const char* ehdlb_last_error(const ehdlb_ctx* ctx);
 void ehdlb_destroy(ehdlb_ctx* ctx);
 

@@ -84,6 +84,8 @@ SIGNATURES = {
     "ehdlb_generation": (C.c_uint64, [C.c_void_p]),
     "ehdlb_preset": (C.c_int, [C.c_int32, C.POINTER(Lattice), C.POINTER(Params), C.c_void_p, C.c_void_p,
                                C.c_uint64]),
+    "ehdlb_bandwidth_probe": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32,
+                                       C.c_int32, C.c_void_p]),
     "ehdlb_last_error": (C.c_char_p, [C.c_void_p]),
     "ehdlb_destroy": (None, [C.c_void_p]),
 }

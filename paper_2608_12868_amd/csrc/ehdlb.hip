@@ -1988,6 +1988,96 @@ ehdlb_status ehdlb_solver_stats(ehdlb_ctx* c, int32_t reset, int64_t* counts, do
 
 uint64_t ehdlb_generation(const ehdlb_ctx* c) { return c ? c->gen : 0; }
 
+}  // extern "C"
+
+// ============================================================================ bandwidth references
+// Kernels with no arithmetic of the method, timed beside the fused step to give its memory
+// traffic two ceilings: a copy at a given access width, and the fused step's own population
+// access pattern (each population of a node loaded once, stored at the node its velocity points
+// to).  They touch only the caller's buffers.
+__global__ __launch_bounds__(256) void k_probe_copy16(const float4* __restrict__ a, float4* __restrict__ b,
+                                                      size_t n) {
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ __launch_bounds__(256) void k_probe_copy4(const float* __restrict__ a, float* __restrict__ b,
+                                                     size_t n) {
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+template <class L, int NF, bool NT>
+__global__ __launch_bounds__(256) void k_probe_push(const float* __restrict__ a, float* __restrict__ b, int nx,
+                                                    int ny, int nz) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+  float v[NF * L::Q];
+#pragma unroll
+  for (int k = 0; k < NF * L::Q; ++k) {
+    const float* p = a + (int64_t)k * N + i;
+    v[k] = NT ? __builtin_nontemporal_load(p) : *p;
+  }
+#pragma unroll
+  for (int k = 0; k < NF * L::Q; ++k) {
+    const int q = k % L::Q;
+    int xd = x + L::ex[q], yd = y + L::ey[q], zd = z + L::ez[q];
+    xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
+    yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
+    zd = zd < 0 ? zd + nz : (zd >= nz ? zd - nz : zd);
+    b[(int64_t)k * N + ((int64_t)zd * ny + yd) * nx + xd] = v[k];
+  }
+}
+
+template <class L, bool NT>
+static bool launch_probe_push(int nf, const float* a, float* b, const int32_t* n, hipStream_t s) {
+  const int64_t N = (int64_t)n[0] * n[1] * n[2];
+  const dim3 grid((unsigned)((N + 255) / 256)), block(256);
+  switch (nf) {
+    case 1: hipLaunchKernelGGL((k_probe_push<L, 1, NT>), grid, block, 0, s, a, b, n[0], n[1], n[2]); return true;
+    case 2: hipLaunchKernelGGL((k_probe_push<L, 2, NT>), grid, block, 0, s, a, b, n[0], n[1], n[2]); return true;
+    case 3: hipLaunchKernelGGL((k_probe_push<L, 3, NT>), grid, block, 0, s, a, b, n[0], n[1], n[2]); return true;
+    case 4: hipLaunchKernelGGL((k_probe_push<L, 4, NT>), grid, block, 0, s, a, b, n[0], n[1], n[2]); return true;
+    case 5: hipLaunchKernelGGL((k_probe_push<L, 5, NT>), grid, block, 0, s, a, b, n[0], n[1], n[2]); return true;
+    default: return false;
+  }
+}
+
+extern "C" {
+
+ehdlb_status ehdlb_bandwidth_probe(int32_t kind, const void* src, void* dst, size_t bytes, const int32_t* dims,
+                                   int32_t q, int32_t nf, void* stream) {
+  if (!src || !dst || kind < 0 || kind > 3) return EHDLB_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (kind == 0) {
+    if (bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16) return EHDLB_EINVAL;
+    const size_t n = bytes / 16;
+    if (n == 0) return EHDLB_OK;
+    hipLaunchKernelGGL(k_probe_copy16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const float4*)src,
+                       (float4*)dst, n);
+  } else if (kind == 1) {
+    if (bytes % 4 || ((uintptr_t)src | (uintptr_t)dst) % 4) return EHDLB_EINVAL;
+    const size_t n = bytes / 4;
+    if (n == 0) return EHDLB_OK;
+    hipLaunchKernelGGL(k_probe_copy4, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const float*)src,
+                       (float*)dst, n);
+  } else {
+    if (!dims || dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || nf < 1 || nf > 5) return EHDLB_EINVAL;
+    if (!((q == 9 && dims[2] == 1) || q == 19)) return EHDLB_EINVAL;
+    if (((uintptr_t)src | (uintptr_t)dst) % 4) return EHDLB_EINVAL;
+    const int64_t N = (int64_t)dims[0] * dims[1] * dims[2];
+    if (N > ((int64_t)1 << 31) || bytes < (size_t)nf * q * N * sizeof(float)) return EHDLB_EINVAL;
+    const bool ok = kind == 2 ? (q == 9 ? launch_probe_push<D2Q9, false>(nf, (const float*)src, (float*)dst, dims, s)
+                                        : launch_probe_push<D3Q19, false>(nf, (const float*)src, (float*)dst, dims, s))
+                              : (q == 9 ? launch_probe_push<D2Q9, true>(nf, (const float*)src, (float*)dst, dims, s)
+                                        : launch_probe_push<D3Q19, true>(nf, (const float*)src, (float*)dst, dims, s));
+    if (!ok) return EHDLB_EINVAL;
+  }
+  return hipGetLastError() == hipSuccess ? EHDLB_OK : EHDLB_EHIP;
+}
+
 const char* ehdlb_last_error(const ehdlb_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 void ehdlb_destroy(ehdlb_ctx* c) {

@@ -202,3 +202,21 @@ def test_preset_matches_the_input_generator(L, name):
 def test_preset_rejects_unknown_ids(L):
     lat, p = L.Lattice(), L.Params()
     assert L.lib().ehdlb_preset(99, C.byref(lat), C.byref(p), None, None, 0) == L.EINVAL
+
+
+def test_bandwidth_probe_rejects_bad_arguments(L):
+    """Every rejection happens before anything is queued, so no device is needed."""
+    lib = L.lib()
+    fake = C.c_void_p(4096)
+    dims = (C.c_int32 * 3)(8, 6, 5)
+    assert lib.ehdlb_bandwidth_probe(4, fake, fake, 64, None, 0, 0, None) == L.EINVAL     # unknown kind
+    assert lib.ehdlb_bandwidth_probe(0, None, fake, 64, None, 0, 0, None) == L.EINVAL     # NULL source
+    assert lib.ehdlb_bandwidth_probe(0, fake, fake, 40, None, 0, 0, None) == L.EINVAL     # not 16-byte sized
+    assert lib.ehdlb_bandwidth_probe(0, C.c_void_p(4100), fake, 64, None, 0, 0, None) == L.EINVAL  # misaligned
+    assert lib.ehdlb_bandwidth_probe(1, fake, fake, 6, None, 0, 0, None) == L.EINVAL      # not 4-byte sized
+    need = 2 * 19 * 8 * 6 * 5 * 4
+    assert lib.ehdlb_bandwidth_probe(2, fake, fake, need, None, 19, 2, None) == L.EINVAL  # no dims
+    assert lib.ehdlb_bandwidth_probe(2, fake, fake, need - 4, dims, 19, 2, None) == L.EINVAL  # too small
+    assert lib.ehdlb_bandwidth_probe(2, fake, fake, need, dims, 9, 2, None) == L.EINVAL   # D2Q9 with nz > 1
+    assert lib.ehdlb_bandwidth_probe(3, fake, fake, need, dims, 15, 2, None) == L.EINVAL  # unknown velocity set
+    assert lib.ehdlb_bandwidth_probe(2, fake, fake, need * 4, dims, 19, 6, None) == L.EINVAL  # too many families
