@@ -143,7 +143,9 @@ ADJOINT = {
                "3D D3Q19 ternary EHD LB, 384x192x128 (pillars pitch 12, droplet R=48, electrode strip), "
                "FP32-deviation storage, 32-segment schedule, T=2000, checkpoint every 50"),
 }
-FD_H = (1e-3, 1e-4)   # central-difference steps: 1e-4 as the workload names it, 1e-3 above its round-off floor
+# central-difference steps: 1e-4 as the workload names it; the quotient of the FP64 forward shows no
+# h^2 term up to 8e-3 and its round-off grows as 1/h, so the largest step is the most accurate
+FD_H = (8e-3, 1e-3, 1e-4)
 
 
 def adjoint_leg(key, seed=1):
