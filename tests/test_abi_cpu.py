@@ -67,7 +67,8 @@ def test_create_rejects_invalid_parameters(L, over):
 def test_create_rejects_bad_lattice(L):
     from paper_2608_12868_amd.sim import make_structs
     case = make_case("c1s")
-    for dim, n in ((4, case.n), (2, (16, 16, 2)), (3, (0, 4, 4))):
+    # bad dimension, 2D with Nz > 1, an empty axis, 2^31 nodes (the library takes fewer)
+    for dim, n in ((4, case.n), (2, (16, 16, 2)), (3, (0, 4, 4)), (3, (2048, 1024, 1024))):
         lat, p = make_structs(dim, n, case.periodic, "fp64", case.params)
         h = C.c_void_p()
         assert L.lib().ehdlb_create(C.byref(lat), C.byref(p), C.byref(h)) == L.EINVAL
