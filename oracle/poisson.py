@@ -96,6 +96,9 @@ class PotentialSystem:
 
 
 CG_RTOL = 1e-15
+# Progress lines from the 3D conjugate-gradient solve every so many iterations (0: none), for the
+# long oracle runs that write stored references of the large lattices; no effect on the result.
+PROGRESS_EVERY = 0
 
 
 class _Factor:
@@ -116,7 +119,15 @@ class _Factor:
         nb = np.linalg.norm(b)
         if nb == 0.0:
             return np.zeros_like(b)
-        x, info = spla.cg(self.A, b, rtol=CG_RTOL, atol=0.0, maxiter=50 * b.size, M=self.Minv)
+        count = [0]
+
+        def progress(_x):
+            count[0] += 1
+            if count[0] % PROGRESS_EVERY == 0:
+                print(f"  oracle CG iteration {count[0]}", flush=True)
+
+        x, info = spla.cg(self.A, b, rtol=CG_RTOL, atol=0.0, maxiter=50 * b.size, M=self.Minv,
+                          callback=progress if PROGRESS_EVERY > 0 else None)
         if info != 0:
             raise RuntimeError(f"oracle CG did not converge (info={info})")
         return x

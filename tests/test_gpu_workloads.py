@@ -33,6 +33,7 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLD = os.path.join(HERE, "golden", "config2_oracle.json")
 GOLD3 = os.path.join(HERE, "golden", "config3_oracle.json")
+GOLD5 = os.path.join(HERE, "golden", "config5_oracle.json")
 
 
 def _gold():
@@ -124,6 +125,39 @@ def test_config3_fields_vs_oracle(precision, tol, names):
             err = float(np.abs(a - np.asarray(ref["sample"])).max() / max(ref["max_abs"], 1e-300))
             print(f"  {name}: {err:.3e}", flush=True)
             worst = max(worst, err)
+    assert worst <= tol
+
+
+# The same bars at 384x192x128, the lattice of the 3D adjoint workload (its forward at full size).
+@pytest.mark.parametrize("precision,tol,names", [
+    ("fp64", 1e-10, ("phi1", "phi2", "phi3", "ux", "uy", "uz", "p", "rho_e", "pot", "q")),
+    ("fp32", 1e-4, ("phi1", "phi2", "phi3", "ux", "uy", "uz"))])
+def test_config5_fields_vs_oracle(precision, tol, names):
+    """Every field after each stored step (1 and 2) on 4096 sampled fluid nodes against the stored FP64
+    oracle output (tests/golden/config5_oracle.json, written by make_config5_oracle.py from the
+    oracle alone), and the droplet mass and centroid at both steps."""
+    with open(GOLD5) as f:
+        g = json.load(f)
+    case = make_case("c5", precision=precision)
+    sim = _sim(case, precision, poisson_tol=1e-14 if precision == "fp64" else 1e-5)
+    idx = np.asarray(g["sample_nodes"])
+    obs = {t["step"]: t for t in g["trajectory"]}
+    worst = 0.0
+    for step in range(1, g["steps_done"] + 1):
+        print("c5", precision, case.n, step, "steps vs stored oracle fields", flush=True)
+        sim.step(1)
+        rec = g["fields_at"][str(step)]
+        for name in names:
+            a = sim.field(name)[idx]
+            err = float(np.abs(a - np.asarray(rec[name]["sample"])).max() / max(rec[name]["max_abs"], 1e-300))
+            print(f"  {name}: {err:.3e}", flush=True)
+            worst = max(worst, err)
+        ob = sim.observables()
+        m_err = float(np.abs(np.asarray(ob["mass"]) - obs[step]["mass"]).max() / max(obs[step]["mass"]))
+        c_err = float(np.abs(np.asarray(ob["centroid"]) - obs[step]["centroid"]).max()
+                      / np.abs(obs[step]["centroid"]).max())
+        print(f"  mass {m_err:.3e}, centroid {c_err:.3e}", flush=True)
+        worst = max(worst, m_err, c_err)
     assert worst <= tol
 
 
