@@ -14,6 +14,10 @@ make_config3_oracle.py from the oracle alone); per-component mass over 100 steps
 FP32-deviation path against the FP64 path over the configured 5000 steps, a length the CPU
 oracle cannot run at this size.
 
+384x192x128 3D EHD, the 3D adjoint workload's lattice: every field after 1 and 2 steps on 4096
+sampled fluid nodes and the observables against tests/golden/config5_oracle.json (written by
+make_config5_oracle.py from the oracle alone).
+
 The 2D adjoint workload (512x256, 64-segment schedule, T = 4000, K = 100): the FP32 gradient
 against the FP64 adjoint, and the FP64 adjoint against central differences of the FP64 forward
 over a sequence of step sizes.
