@@ -275,3 +275,33 @@ def test_adjoint_paper_regime_fluids_matches_oracle_autograd():
     err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
     print("adjoint (Table 1 fluids) vs oracle autograd", err, flush=True)
     assert err <= 1e-8
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("fp32", 1e-3)])
+def test_adjoint_full_size_2d_matches_stored_oracle_gradient(precision, tol):
+    """The 512x256 adjoint workload (its 64-segment schedule spread over T = 16 steps, K = 5 with
+    a ragged last segment) against the oracle's autograd gradient stored by
+    tests/golden/make_config4_adjoint_oracle.py: the launch configuration of the benchmark's 2D
+    adjoint at its full lattice.  Segments that no step uses get exactly zero.  FP64: 8e-12.
+    FP32: 2.6e-4; 16 steps from rest leave a gradient of ~2e-7, carried mostly by the droplet
+    velocity, a small net of opposing interface currents whose FP32 rounding it inherits."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config4_adjoint_oracle.json")
+    with open(path) as f:
+        gold = json.load(f)
+    case = make_case("c4", precision=precision)
+    sched = np.asarray(gold["schedule"])
+    sim = _sim(case, precision, **({"poisson_tol": 1e-5} if precision == "fp32" else {}))
+    sim.set_schedule(0, sched, gold["t_total"])
+    print("c4", precision, case.n, "T", gold["T"], "K 5, segments", len(sched), flush=True)
+    sim.forward_checkpointed(gold["T"], 5)
+    ob = sim.observables()
+    g = sim.adjoint(np.asarray(gold["dL_dcentroid"]), np.asarray(gold["dL_dvelocity"]), 0, len(sched))
+    ref = np.asarray(gold["gradient"])
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    print(f"  gradient vs oracle autograd: {err:.3e}; centroid "
+          f"{np.abs(ob['centroid'] - np.asarray(gold['centroid'])).max():.3e} lu", flush=True)
+    assert np.all(g[ref == 0.0] == 0.0)
+    assert np.allclose(ob["centroid"], gold["centroid"], rtol=1e-12 if precision == "fp64" else 1e-6, atol=1e-12)
+    assert err <= tol
