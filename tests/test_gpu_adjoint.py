@@ -283,8 +283,7 @@ def test_adjoint_full_size_2d_matches_stored_oracle_gradient(precision, tol):
     a ragged last segment) against the oracle's autograd gradient stored by
     tests/golden/make_config4_adjoint_oracle.py: the launch configuration of the benchmark's 2D
     adjoint at its full lattice.  Segments that no step uses get exactly zero.  FP64: 8e-12.
-    FP32: 2.6e-4; 16 steps from rest leave a gradient of ~2e-7, carried mostly by the droplet
-    velocity, a small net of opposing interface currents whose FP32 rounding it inherits."""
+    FP32: 2.6e-4 of a gradient whose largest entry is 1.8e-7 after 16 steps from rest."""
     import json
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config4_adjoint_oracle.json")
