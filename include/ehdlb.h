@@ -119,15 +119,17 @@ typedef struct {
                                form (the flow populations carry p / (rho cs^2); the
                                acceleration F / rho with the pressure force
                                -cs^2 p* grad(rho) and the viscous force
-                               nu (grad u + grad u^T) . grad(rho)); ehdlb_adjoint then
-                               returns EINVAL                                          */
+                               nu (grad u + grad u^T) . grad(rho)), which ehdlb_adjoint
+                               reverses as well                                        */
 } ehdlb_params;
 
 typedef struct {
   int64_t step;             /* completed steps                                          */
   double mass[3];           /* sum of Phi_i over fluid nodes                            */
-  double centroid[3];       /* Phi_1-weighted mean node coordinate                      */
+  double centroid[3];       /* Phi_1-weighted mean node coordinate (NaN, undefined,     */
+                            /* when mass[0] is 0: no droplet)                           */
   double velocity[3];       /* Phi_1-weighted mean velocity of the last completed step  */
+                            /* (0 when that step's Phi_1 sums to 0)                     */
   double total_charge;      /* sum of rho_e over fluid nodes                            */
   double sum_phi_drift;     /* max |Phi_1 + Phi_2 + Phi_3 - 1| over fluid nodes         */
   double poisson_residual;  /* last relative FP64 residual of the potential solve       */

@@ -203,6 +203,66 @@ def test_fp64_zero_potential():
     _compare(sim, o, s, aux, FP64_TOL)
 
 
+@pytest.mark.parametrize("n", [(64, 36, 1), (24, 20, 16)])
+def test_fp64_parity_without_droplet(n):
+    """The degenerate two-phase state of the ternary model: no droplet (Phi_1 = 0 everywhere), a
+    lubricant film under the ambient, the field on (in 3D uniform along y).  Fields against the oracle, and the
+    observables against the oracle's: the droplet mass, and a centroid that is undefined (NaN)
+    exactly when that mass is zero."""
+    import pin_cases as pc
+    from oracle import Oracle
+    dim, n, periodic, params, flags, _ = _droplet_case(n, (1, 0, 0) if n[2] == 1 else (1, 1, 0), radius=1.0)
+    x, y, z = pc.grid(n)
+    h = z if dim == 3 else y
+    p2 = 0.5 * (1 + np.tanh(2 * (4.5 - h) / 4.0))
+    phi = np.stack([np.zeros_like(p2), p2, 1 - p2])
+    phi[:, flags != 0] = 0
+    print("no droplet", n, flush=True)
+    sim, o, s, aux = _run_pair(dim, n, periodic, params, flags, phi, steps=30)
+    # in 3D the state is uniform along y, so u_y is rounding noise on both sides: the velocity
+    # components are compared against the largest of them
+    ref = gu.oracle_fields(o, s, aux)
+    uscale = max(np.abs(ref[k]).max() for k in ("ux", "uy", "uz") if k in ref)
+    errs = {}
+    for k, v in ref.items():
+        den = uscale if k in ("ux", "uy", "uz") else max(np.abs(v).max(), 1e-300)
+        errs[k] = float(np.abs(sim.field(k) - v).max() / den)
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert max(errs.values()) <= FP64_TOL, errs
+    ob = sim.observables(strict=False)
+    ref = o.observables(s)
+    m1 = float(ref["mass"][0])
+    print("droplet mass", ob["mass"][0], m1, "centroid", ob["centroid"], flush=True)
+    assert ob["status"] == 0
+    assert abs(ob["mass"][0] - m1) <= 1e-12
+    if m1 == 0.0:
+        assert ob["mass"][0] == 0.0 and np.all(np.isnan(ob["centroid"]))
+    else:
+        assert np.allclose(ob["centroid"], ref["centroid"].numpy(), rtol=1e-10, atol=1e-10)
+    assert np.allclose(ob["mass"][1:], ref["mass"].numpy()[1:], rtol=1e-12)
+
+
+def test_zero_steps_change_nothing():
+    """step(0) leaves the state, the step counter and the forward generation unchanged."""
+    case = make_case("c2s", precision="fp64")
+    sim = _gpu(case, "fp64")
+    sim.step(3)
+
+    def state():
+        buf = sim.save_state()
+        off = (-buf.data_ptr()) % 256          # save_state writes at the first 256-byte boundary
+        return buf[off:off + sim.state_bytes].clone()
+
+    ob0 = sim.observables()
+    g0, st0 = sim.generation, state()
+    sim.step(0)
+    assert sim.generation == g0
+    assert bool((state() == st0).all())
+    ob1 = sim.observables()
+    assert ob1["step"] == ob0["step"] == 3
+    assert np.array_equal(ob1["centroid"], ob0["centroid"])
+
+
 @pytest.mark.parametrize("name,steps,s_high", [("c2s", 120, 1.3), ("c3s", 10, 0.8)])
 def test_fp64_parity_higher_moment_rate(name, steps, s_high):
     """The higher raw moments away from rate 1 (s_high: orders >= 2 of the phase fields and the
