@@ -6,8 +6,10 @@ The residual r(V) = x_c(T; V)[axis] - x* of the droplet centroid after T steps i
 function of the piecewise-constant schedule V of one electrode; its gradient J = dr/dV comes
 from one checkpointed forward and one adjoint sweep.  Each iteration takes the minimum-norm step
 of the linearised residual, r + J dV = 0, over the segments that are not held at a voltage bound
-(projected Gauss-Newton), halving it until |r| decreases.  Host-side driver only: every forward
-step and every adjoint step runs in the library.
+(projected Gauss-Newton), halving it until |r| decreases.  Also: switch times designed with the
+adjoint, the relay protocol's schedules (Fig. 5c) and the two-electrode periodic protocol
+(Fig. 5b) switched on the droplet's position.  Host-side drivers only: every forward step and
+every adjoint step runs in the library.
 """
 import math
 
@@ -135,3 +137,38 @@ def relay_schedules(switch_times, volts, n_electrodes, t_total, seg_len):
             v[bounds[k]:bounds[k + 1]] = volts
         out.append(v)
     return out, [e * seg_len for e in edges]
+
+
+def periodic_protocol(sim, x0, d, volts, n_switches, electrodes=(0, 1), chunk=250, max_steps=2_000_000, axis=0):
+    """The two-electrode periodic motion of the Results (Fig. 5b), switched on the droplet's
+    position: electrodes[0] holds `volts` (electrodes[1] floats) until the centroid passes
+    x0 + d, then electrodes[1] holds it (electrodes[0] floats) until the centroid passes x0 - d,
+    and so on for n_switches switches.  The centroid is read every `chunk` steps; a switch takes
+    effect from the next step.  Returns dict(switch_steps, switch_positions, trajectory) with
+    positions relative to x0 and the trajectory as (step, position) pairs.  Raises if the state
+    turns non-finite or max_steps pass first."""
+    e_a, e_b = electrodes
+    on = 0
+
+    def apply():
+        sim.set_schedule(e_a, np.array([volts if on == 0 else np.nan]), 1)
+        sim.set_schedule(e_b, np.array([volts if on == 1 else np.nan]), 1)
+
+    apply()
+    steps, pos, traj = [], [], []
+    start = int(sim.observables()["step"])
+    while len(steps) < n_switches:
+        sim.step(chunk)
+        ob = sim.observables(strict=False)
+        if ob["status"] != 0:
+            raise RuntimeError(f"status {ob['status']} at step {ob['step']}")
+        x = float(ob["centroid"][axis]) - x0
+        traj.append((int(ob["step"]), x))
+        if (on == 0 and x >= d) or (on == 1 and x <= -d):
+            steps.append(int(ob["step"]))
+            pos.append(x)
+            on = 1 - on
+            apply()
+        if ob["step"] - start >= max_steps:
+            raise RuntimeError(f"{len(steps)} of {n_switches} switches after {max_steps} steps")
+    return dict(switch_steps=steps, switch_positions=pos, trajectory=traj)

@@ -62,3 +62,43 @@ def test_stops_at_relative_tolerance():
     sim = LinearSim(a, 0.0)
     v, hist = design_schedule(sim, None, np.full(4, 0.02), 100, 10, 5, a @ np.full(4, 0.02), iters=5)
     assert len(hist) == 1 and sim.forward_runs == 1   # already on target: no adjoint sweep
+
+
+class PullSim:
+    """Stand-in for the periodic protocol: the centroid moves at speed v towards whichever of
+    electrodes 0 (ahead, +x) and 1 (behind) holds a finite voltage; a floating one (NaN) pulls
+    nothing."""
+
+    def __init__(self, v):
+        self.v, self.x, self.t = float(v), 0.0, 0
+        self.volts = {0: np.nan, 1: np.nan}
+
+    def set_schedule(self, electrode, volts, t_total):
+        assert len(volts) == 1 and t_total == 1
+        self.volts[electrode] = float(volts[0])
+
+    def step(self, n):
+        sign = (0.0 if np.isnan(self.volts[0]) else 1.0) - (0.0 if np.isnan(self.volts[1]) else 1.0)
+        self.x += sign * self.v * n
+        self.t += n
+
+    def observables(self, strict=True):
+        return {"step": self.t, "centroid": np.array([self.x, 0.0, 0.0]), "status": 0}
+
+
+def test_periodic_protocol_switches_on_position():
+    from paper_2608_12868_amd.schedule import periodic_protocol
+    sim = PullSim(2.0 ** -7)                  # 1 lu per chunk of 128 steps, exactly
+    out = periodic_protocol(sim, 0.0, 4.0, 0.7, n_switches=4, chunk=128)
+    # a first leg of 4 lu, then legs of 8 lu between the turning points
+    assert out["switch_steps"] == [512, 1536, 2560, 3584]
+    assert out["switch_positions"] == [4.0, -4.0, 4.0, -4.0]
+    # one electrode holds the voltage at a time, the other floats
+    assert sim.volts[0] == 0.7 and np.isnan(sim.volts[1])
+
+
+def test_periodic_protocol_gives_up_after_max_steps():
+    import pytest
+    from paper_2608_12868_amd.schedule import periodic_protocol
+    with pytest.raises(RuntimeError):
+        periodic_protocol(PullSim(0.0), 0.0, 1.0, 0.7, n_switches=2, chunk=100, max_steps=1000)
