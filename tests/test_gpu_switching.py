@@ -178,3 +178,51 @@ def test_two_electrode_periodic_motion_follows_the_reduced_model():
     assert abs(t1 - legs[0]) <= 1e-6 * legs[0] and abs(x1 - d) <= 1e-9
     assert np.all(np.abs(legs[1:] / model_leg - 1) <= 0.40)
     assert legs[1:].max() <= 1.25 * legs[1:].min()
+
+
+def test_return_leg_sensitivity_to_the_first_switch():
+    """The sensitivity the paper points out for the periodic protocol (Results, Fig. 5b): moving
+    the first switch changes the return leg.  On m2s (FP32), electrode 0 pulls for t_sw1 = 0.9,
+    1.0 and 1.1 times the 23,000 steps the droplet needs to move R0/2; then it floats and
+    electrode 1 pulls until the centroid is R0/2 behind its start.  The return leg changes with
+    the same sign as in the overdamped Eq. 5 calibrated on the 1.0 run's first leg, by 0.5-1.5
+    times the model's change (measured: -5.1 % and +5.1 % against -7.2 % and +7.7 %; switching
+    this far from the electrodes, where their force varies little over R0/2, keeps both small)."""
+    import math
+    from paper_2608_12868_amd import Simulation, reduced as rm
+    gu.require_gpu()
+    case = make_case("m2s")
+    r0 = case.meta["radius"]
+    x0 = float((case.phi[0] * case.coords()[0]).sum() / case.phi[0].sum())
+    half = case.meta["electrode"][0] - x0
+    volts = case.params["electrode_volts"][0]
+    d, t_base = 0.5 * r0, 23000
+    alpha0 = math.pi / (2.0 * case.meta["channel"])
+    u = (math.exp(2 * alpha0 * half) - math.exp(2 * alpha0 * (half - d))) / (2 * alpha0 * t_base)
+    sim_leg, model_leg = {}, {}
+    for f in (1.0, 0.9, 1.1):
+        t_sw1 = int(round(f * t_base))
+        sim = Simulation.from_case(case, precision="fp32", poisson_tol=1e-5)
+        sim.set_schedule(1, np.array([np.nan]), 1)
+        print("m2s first switch at", t_sw1, flush=True)
+        sim.step(t_sw1)
+        sim.set_schedule(0, np.array([np.nan]), 1)
+        sim.set_schedule(1, np.array([volts]), 1)
+        t = t_sw1
+        while True:
+            sim.step(250)
+            t += 250
+            ob = sim.observables()
+            if ob["centroid"][0] - x0 <= -d:
+                break
+            assert t < t_sw1 + 300000
+        sim_leg[f] = t - t_sw1
+        m1, m2, _ = rm.two_electrode_switch_times(u, alpha0, half, half - d, t_sw1=t_sw1)
+        model_leg[f] = m2 - m1
+        print(f"  return leg {sim_leg[f]} steps (model {model_leg[f]:.0f})", flush=True)
+        del sim
+    for f in (0.9, 1.1):
+        ds = sim_leg[f] / sim_leg[1.0] - 1
+        dm = model_leg[f] / model_leg[1.0] - 1
+        print(f"  t_sw1 x{f}: return leg {ds:+.3f} (model {dm:+.3f})", flush=True)
+        assert ds * dm > 0 and 0.5 <= ds / dm <= 1.5
