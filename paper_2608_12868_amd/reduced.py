@@ -209,6 +209,40 @@ def two_electrode_switch_times(u, alpha0, half_gap, s_sw, t_sw1=None):
     return t_sw1, t_sw1 + t2, x1
 
 
+def two_electrode_position(t, u, alpha0, half_gap, t_sw1):
+    """Position at time t of the two-electrode protocol in the overdamped Eq. 5: pulled by
+    electrode 1 (distance half_gap ahead at the start) until t_sw1, then by electrode 2 (as far
+    behind the start).  Positions from the start, towards electrode 1; no turn-back past the
+    electrodes (t_sw1 before the arrival at electrode 1, t before the arrival at electrode 2)."""
+    a2 = 2.0 * alpha0
+    e1 = math.exp(a2 * half_gap) - a2 * u * min(t, t_sw1)
+    if not e1 > 1.0:
+        raise ValueError("the droplet reaches electrode 1")
+    x = half_gap - math.log(e1) / a2
+    if t <= t_sw1:
+        return x
+    e2 = math.exp(a2 * (half_gap + x)) - a2 * u * (t - t_sw1)
+    if not e2 > 1.0:
+        raise ValueError("the droplet reaches electrode 2")
+    return math.log(e2) / a2 - half_gap
+
+
+def two_electrode_switch_for_target(u, alpha0, half_gap, T, x_target=0.0, tol=1e-9):
+    """The switch time t_sw1 of the two-electrode protocol that puts the droplet at x_target at
+    time T (overdamped Eq. 5; x(T) grows with t_sw1, so bisection on [0, T])."""
+    f = lambda ts: two_electrode_position(T, u, alpha0, half_gap, ts) - x_target
+    lo, hi = 0.0, float(T)
+    if not (f(lo) <= 0.0 <= f(hi)):
+        raise ValueError("target not reachable with one switch before T")
+    while hi - lo > tol * T:
+        mid = 0.5 * (lo + hi)
+        if f(mid) < 0.0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
 # ------------------------------------------------------------------ long-distance transport (Fig. 5c)
 def relay_switch_times(u, alpha0, s0, pitch, s_sw, n_electrodes=3):
     """The long-distance protocol of the Results (Fig. 5c) in the overdamped form of Eq. 5:

@@ -195,3 +195,24 @@ def test_relay_switch_times_and_positions():
     assert s0 - s_sw + 2 * pitch < late <= s0 + 2 * pitch
     with pytest.raises(ValueError):
         rm.relay_switch_times(u, a0, s_sw, pitch, s_sw)
+
+
+def test_two_electrode_position_and_switch_for_target():
+    """The protocol's position in time (overdamped Eq. 5, one switch) against a direct
+    integration of dx/dt = +-u exp(-2 alpha0 S_e), and the switch time that returns the
+    droplet to its start at T."""
+    u, a0, half = 1.37e-3, math.pi / 92.0, 32.0
+    t_sw, T = 19000.0, 45000.0
+    x, t, dt = 0.0, 0.0, 0.5
+    while t < T - 1e-9:
+        s = (half - x) if t < t_sw else (half + x)
+        x += (1.0 if t < t_sw else -1.0) * dt * u * math.exp(-2 * a0 * s)
+        t += dt
+        if abs(t - t_sw) < 1e-9:
+            assert rm.two_electrode_position(t_sw, u, a0, half, t_sw) == pytest.approx(x, abs=2e-4)
+    assert rm.two_electrode_position(T, u, a0, half, t_sw) == pytest.approx(x, abs=2e-4)
+    ts = rm.two_electrode_switch_for_target(u, a0, half, T)
+    assert abs(rm.two_electrode_position(T, u, a0, half, ts)) <= 1e-6
+    assert rm.two_electrode_position(T, u, a0, half, 0.99 * ts) < 0.0 < rm.two_electrode_position(T, u, a0, half, 1.01 * ts)
+    with pytest.raises(ValueError):
+        rm.two_electrode_switch_for_target(u, a0, half, T, x_target=40.0)
