@@ -1,12 +1,14 @@
-"""Two-electrode switching designed with the adjoint, the periodic protocol and long-distance
-transport (the protocols of the Results, Fig. 5b-c).
+"""Electrode-switching protocols of the Results (Fig. 5b-c) in the full model.
 
 Workload m2s (192x48 2D, droplet R0 = 8 on a flat lubricant film between two top-wall
-electrodes at 0.7 lu, FP64 path): electrode 1 pulls until the switch time, electrode 2 after it.
-The derivative of the droplet centroid at step T with respect to the switch time, formed from the
-adjoint with respect to both electrodes' schedules (paper_2608_12868_amd/schedule.py), is checked
-against central differences of the forward, and Newton steps on it find the switch time that
-puts the droplet at a target position."""
+electrodes at 0.7 lu): the derivative of the droplet centroid at step T with respect to a
+switch time, formed from the adjoint with respect to both electrodes' schedules
+(paper_2608_12868_amd/schedule.py), against central differences of the forward (FP64), and
+Newton steps on it that find the switch time putting the droplet at a target position; the
+switch time returning the droplet to its start designed that way and with the calibrated
+overdamped Eq. 5 (FP32); the periodic motion switched on the droplet's position and the return
+leg's sensitivity to the first switch time (FP32).  Workload m2 with three electrodes: the
+long-distance relay designed with the reduced model (FP32)."""
 import numpy as np
 import pytest
 
