@@ -147,6 +147,8 @@ def periodic_protocol(sim, x0, d, volts, n_switches, electrodes=(0, 1), chunk=25
     effect from the next step.  Returns dict(switch_steps, switch_positions, trajectory) with
     positions relative to x0 and the trajectory as (step, position) pairs.  Raises if the state
     turns non-finite or max_steps pass first."""
+    if not (d > 0 and n_switches >= 1 and chunk >= 1 and electrodes[0] != electrodes[1]):
+        raise ValueError("need d > 0, n_switches >= 1, chunk >= 1 and two distinct electrodes")
     e_a, e_b = electrodes
     on = 0
 

@@ -102,3 +102,14 @@ def test_periodic_protocol_gives_up_after_max_steps():
     from paper_2608_12868_amd.schedule import periodic_protocol
     with pytest.raises(RuntimeError):
         periodic_protocol(PullSim(0.0), 0.0, 1.0, 0.7, n_switches=2, chunk=100, max_steps=1000)
+
+
+def test_periodic_protocol_rejects_bad_arguments():
+    import pytest
+    from paper_2608_12868_amd.schedule import periodic_protocol
+    for kw in (dict(d=0.0), dict(n_switches=0), dict(chunk=0), dict(electrodes=(1, 1))):
+        args = dict(d=1.0, n_switches=2, chunk=100, electrodes=(0, 1))
+        args.update(kw)
+        with pytest.raises(ValueError):
+            periodic_protocol(PullSim(1.0), 0.0, args["d"], 0.7, n_switches=args["n_switches"], chunk=args["chunk"],
+                              electrodes=args["electrodes"])
